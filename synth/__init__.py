@@ -1,0 +1,42 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke
+check.  Holds no arithmetic of the scattering method: only contrast
+functions sampled at caller-supplied coordinates and measurement layouts."""
+import numpy as np
+
+
+def gaussian_bumps(xy, nbumps, seed, amp=(0.1, 0.3), width=0.15, centre=0.6, rescale_max=None):
+    """q(x) = sum_j a_j exp(-|x - c_j|^2 / w^2) at points xy [n, 2], with
+    c_j ~ U[-centre, centre]^2 and a_j ~ U[amp]; optionally rescaled so that
+    the maximum over the given points equals rescale_max."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-centre, centre, size=(nbumps, 2))
+    a = rng.uniform(amp[0], amp[1], size=nbumps)
+    xy = np.asarray(xy, dtype=np.float64)
+    q = np.zeros(xy.shape[0])
+    for j in range(nbumps):
+        d2 = (xy[:, 0] - c[j, 0]) ** 2 + (xy[:, 1] - c[j, 1]) ** 2
+        q += a[j] * np.exp(-d2 / width ** 2)
+    if rescale_max is not None:
+        q *= rescale_max / np.max(q)
+    return q
+
+
+def radial_gaussian(xy, amp, sigma):
+    """q(r) = amp exp(-r^2 / sigma^2): a smooth radial contrast whose tail is
+    negligible outside r = 5 sigma."""
+    xy = np.asarray(xy, dtype=np.float64)
+    return amp * np.exp(-(xy[:, 0] ** 2 + xy[:, 1] ** 2) / sigma ** 2)
+
+
+def sine_coefficients(S, seed, scale=0.3, decay=800.0):
+    """c_mn = scale * g_mn * exp(-(m^2 + n^2) / decay), g ~ N(0, 1), m, n = 1..S,
+    returned as an [S, S] array (row = x mode m, column = y mode n)."""
+    rng = np.random.default_rng(seed)
+    m = np.arange(1, S + 1)
+    g = rng.standard_normal((S, S))
+    return scale * g * np.exp(-(m[:, None] ** 2 + m[None, :] ** 2) / decay)
+
+
+def equispaced_angles(n):
+    """2 pi m / n, m = 0..n-1."""
+    return 2.0 * np.pi * np.arange(n) / n

@@ -1,0 +1,103 @@
+"""Pins for the forward oracle (Sections 1-2): zero contrast, a radial
+reference by separation of variables, p-refinement, reciprocity of the
+far-field pattern and conservation of flux."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.bie import _GW, _GX, _lagrange_rows
+from oracle.cheb import bary_weights
+from oracle.forward import Problem, directions, forward
+from oracle.grid import Grid
+from oracle.radial import scattered_on_circle
+
+
+def test_zero_contrast_scatters_nothing():
+    g = Grid(4)
+    uf, _ = forward(4, 10.0, np.zeros(g.npde), 4, 16, 2.0)
+    assert np.max(np.abs(uf)) < 1e-8
+
+
+@pytest.mark.parametrize("L,tol", [(4, 2e-6), (8, 1e-9)])
+def test_radial_gaussian_matches_separation_of_variables(L, tol):
+    k, amp, sig = 10.0, 0.4, 0.2
+    th = 2 * np.pi * np.arange(16) / 16
+    ref = scattered_on_circle(k, lambda r: amp * np.exp(-r * r / sig ** 2), 1.0, 0.7, 2.0, th)
+    g = Grid(L)
+    q = synth.radial_gaussian(g.pde_coords(), amp, sig)
+    prob = Problem(L, k).factor(q)
+    prob.solve(np.array([0.7]))
+    prob.set_measurement(th, 2.0)
+    uf = prob.far_field()[0]
+    assert np.max(np.abs(uf - ref)) < tol * np.max(np.abs(ref))
+
+
+def test_p_refinement_converges():
+    k, amp, sig = 6.0, 0.3, 0.25
+    th = 2 * np.pi * np.arange(8) / 8
+    ref = scattered_on_circle(k, lambda r: amp * np.exp(-r * r / sig ** 2), 1.0, 0.0, 2.0, th)
+    errs = []
+    for p in (8, 12, 16):
+        prob = Problem(4, k, p=p)
+        q = synth.radial_gaussian(prob.grid.pde_coords(), amp, sig)
+        prob.factor(q)
+        prob.solve(np.array([0.0]))
+        prob.set_measurement(th, 2.0)
+        errs.append(np.max(np.abs(prob.far_field()[0] - ref)))
+    assert errs[0] > 10 * errs[1] > 100 * errs[2]
+
+
+def _pattern(prob, X, obs_angles):
+    """Far-field pattern (up to a common factor) from the boundary data:
+    int [d_n e^{-ik xhat.y} s - e^{-ik xhat.y} t] ds by panel Gauss rules."""
+    g = prob.grid
+    nodes = g.t[1:-1]
+    lag = _lagrange_rows(nodes, bary_weights(nodes), _GX)
+    s, t = prob.boundary_data(X)
+    out = np.zeros((len(obs_angles), X.shape[1]), dtype=np.complex128)
+    for j, (A, B, n) in enumerate(g.panels()):
+        y = A[None, :] + (B - A)[None, :] * ((1 + _GX) / 2)[:, None]
+        w = _GW * 0.5 * np.hypot(*(B - A))
+        sl = slice(j * nodes.size, (j + 1) * nodes.size)
+        sq, tq = lag @ s[sl], lag @ t[sl]
+        for a, th in enumerate(obs_angles):
+            xh = np.array([np.cos(th), np.sin(th)])
+            e = np.exp(-1j * prob.k * (y @ xh))
+            de = -1j * prob.k * (xh @ n) * e
+            out[a] += (w * de) @ sq - (w * e) @ tq
+    return out.T  # [direction, observation]
+
+
+def test_far_field_pattern_reciprocity():
+    L, k, n = 4, 8.0, 8
+    g = Grid(L)
+    q = synth.gaussian_bumps(g.pde_coords(), 5, 11)
+    prob = Problem(L, k).factor(q)
+    ang = directions(n)
+    X = prob.solve(ang)
+    A = _pattern(prob, X, ang)
+    # u_inf(xhat; d) = u_inf(-d; -xhat): angle pairs shifted by pi
+    B = np.array([[A[(p + n // 2) % n, (m + n // 2) % n] for p in range(n)] for m in range(n)])
+    # discretisation-level at L = 4 (it converges to 3e-10 at L = 8); a wrong
+    # pairing of angles gives O(1)
+    assert np.max(np.abs(A - B)) < 1e-5 * np.max(np.abs(A))
+    assert np.max(np.abs(A - A.T)) > 0.1 * np.max(np.abs(A))
+
+
+def test_flux_conservation_real_contrast():
+    L, k = 4, 10.0
+    g = Grid(L)
+    q = synth.gaussian_bumps(g.pde_coords(), 5, 1)
+    prob = Problem(L, k).factor(q)
+    ang = directions(3)
+    X = prob.solve(ang)
+    nodes = g.t[1:-1]
+    wq = _GW @ _lagrange_rows(nodes, bary_weights(nodes), _GX) * g.h / 2
+    w = np.tile(wq, 4 * L)
+    for m, th in enumerate(ang):
+        d = np.array([np.cos(th), np.sin(th)])
+        ub = X[prob.bu, m]
+        uinc = np.exp(1j * k * g.bxy @ d)
+        dn = X[g.nu:, m] + 1j * k * (g.bnormal @ d) * uinc
+        flux = np.sum(w * np.conj(ub) * dn)
+        assert abs(flux.imag) < 1e-6 * np.sum(w * np.abs(ub) * np.abs(dn))
