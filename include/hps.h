@@ -1,0 +1,198 @@
+/*
+ * hps.h - C ABI of libhps: variable-coefficient Helmholtz scattering solves by a
+ * hierarchical impedance-to-impedance (HPS/ItI) direct solver on an AMD MI355X.
+ *
+ * The calls follow the statement of the problem in the paper (Borges,
+ * Gillman, Greengard, "High resolution inverse scattering in two dimensions
+ * using recursive linearization"):
+ *   hps_factor      factorisation of the interior problem for a contrast q at
+ *                   wavenumber k (Section 2: O(N^{3/2}) factor of the system
+ *                   matrix for a given q; eq. origpde);
+ *   hps_solve       forward solves for plane waves exp(i k x.d) (Section 1,
+ *                   eqs. fscatprob, srad; Section 2: O(N log N) per right-hand
+ *                   side given the factorisation);
+ *   hps_far_field   the measured data u_far(theta) = u_s(R cos theta,
+ *                   R sin theta) (Section 1; operator F of eq. farfielddef);
+ *   hps_jvp         the Frechet derivative J dq (Theorem 1, eqs. Jdef, vdef);
+ *   hps_vjp         its adjoint Re(J^* r), summed over the directions
+ *                   (Theorem 2 and eq. adjfrechetdef, as the exact discrete
+ *                   conjugate transpose);
+ *   hps_sine_eval / hps_sine_adjoint
+ *                   the band-limited sine model E_k and its adjoint
+ *                   (Section 3.2, eq. sineseries; square index set).
+ *
+ * Discretisation (the paper defers it to the HPS solver it cites; the
+ * reading used here): Omega = [x0, x1] x [y0, y1] is split into nleaf x nleaf
+ * square leaves with p x p Chebyshev-Lobatto points (corner points dropped).
+ * The PDE is collocated at the (p-2)^2 interior points of every leaf; leaves
+ * are glued by continuity of u and of its normal derivative, through
+ * impedance-to-impedance maps merged on a binary tree (alternating x / y
+ * merges); the outer boundary is coupled to the radiating exterior through
+ * the Calderon relation S t = (K - I/2) s of the single- and double-layer
+ * operators (Remark in Section 2), never inverting S.
+ *
+ * Conventions
+ *  - "PDE nodes": the npde = nleaf^2 (p-2)^2 leaf-interior collocation points,
+ *    ordered by leaf in Morton order (bit 2b of the leaf index = bit b of the
+ *    column, bit 2b+1 = bit b of the row), then row-major inside the leaf
+ *    (y slow, x fast).  hps_node_coords returns their coordinates.
+ *  - Complex arrays are interleaved (re, im) double pairs (complex128).
+ *  - Pointers named *_host are host memory; every other array argument is
+ *    device memory on the GPU current when the context was created.
+ *  - All work is enqueued on opts.stream (NULL = the default stream) in call
+ *    order; calls return after enqueueing unless stated otherwise.  Inputs
+ *    are only read during the call's kernels; the caller keeps ownership of
+ *    every buffer it passes and must keep it alive until the stream reaches
+ *    the call's end.  The context owns all factors, fields and workspaces.
+ *  - Every call returns an hps_status; on failure hps_last_error() holds a
+ *    message.  A failed call leaves the context usable; the results of a
+ *    failed call are unspecified.
+ */
+#ifndef HPS_H_
+#define HPS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPS_OK = 0,
+  HPS_EINVAL = -1,     /* invalid argument (sizes, NULL pointers, k <= 0, ...) */
+  HPS_ENOMEM = -2,     /* device allocation failed */
+  HPS_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
+  HPS_ESTATE = -4,     /* call order violated (solve before factor, ...) */
+  HPS_ESINGULAR = -5,  /* a zero pivot was met in a factorisation */
+  HPS_ENOCONV = -6     /* reserved: iterative refinement did not converge */
+} hps_status;
+
+typedef enum { HPS_FP64 = 0 } hps_precision;
+
+typedef struct hps_opts {
+  double x0, x1, y0, y1; /* square domain Omega; x1 - x0 must equal y1 - y0 */
+  int nleaf;             /* leaves per side, a power of two (1 .. 256) */
+  int p;                 /* Chebyshev-Lobatto points per leaf side (4 .. 20) */
+  double eta_scale;      /* impedance parameter eta = eta_scale * k (<= 0: 1) */
+  int keep_derivs;       /* non-zero: keep the operators hps_jvp / hps_vjp need */
+  int precision;         /* hps_precision; only HPS_FP64 */
+  int host_threads;      /* threads for the per-k boundary quadrature (<= 0: auto) */
+  void* stream;          /* hipStream_t for all work (NULL = default stream) */
+} hps_opts;
+
+typedef struct hps_ctx hps_ctx;
+
+/* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
+ * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream. */
+void hps_default_opts(hps_opts* o);
+
+/* Creates a context for the geometry in *opts (host-side set-up only; device
+ * memory is allocated by the first hps_factor).  *out receives the handle. */
+hps_status hps_create(const hps_opts* opts, hps_ctx** out);
+
+/* Releases the context and all device memory it owns (synchronises its
+ * stream first).  NULL is ignored. */
+void hps_destroy(hps_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none). */
+const char* hps_last_error(const hps_ctx* ctx);
+
+/* Number of PDE nodes npde = nleaf^2 (p-2)^2. */
+int64_t hps_num_nodes(const hps_ctx* ctx);
+
+/* Number of outer-boundary nodes 4 nleaf (p-2). */
+int64_t hps_num_boundary_nodes(const hps_ctx* ctx);
+
+/* Coordinates of the PDE nodes: xy_host[2 i], xy_host[2 i + 1] for node i
+ * (host array of 2 npde doubles). */
+hps_status hps_node_coords(const hps_ctx* ctx, double* xy_host);
+
+/* Per-wavenumber exterior set-up (the q-independent boundary system): the
+ * single/double-layer matrices on the outer boundary by product quadrature
+ * on the host, the leaf base operators, and their upload.  Synchronous.
+ * hps_factor calls it when k changes; calling it first keeps that host work
+ * out of the factorisation. k > 0. */
+hps_status hps_set_wavenumber(hps_ctx* ctx, double k);
+
+/* Factorises the discrete interior + exterior problem for the real contrast
+ * q_nodes (device, npde doubles, PDE-node order) at wavenumber k > 0: leaf
+ * impedance maps, the merge tree, and the inverse of the top (boundary)
+ * system.  Synchronises the stream once to read the pivot flags; returns
+ * HPS_ESINGULAR if a zero pivot occurred.  Invalidates earlier solves. */
+hps_status hps_factor(hps_ctx* ctx, const double* q_nodes, double k);
+
+/* Total-field solves for ndir plane waves exp(i k x.d_m),
+ * d_m = (cos a_m, sin a_m), a_m = dir_angle_host[m]; keeps the fields u_0 at
+ * the PDE nodes and the boundary data on the device for far-field, jvp and
+ * vjp calls.  Requires hps_factor.  1 <= ndir <= 65535. */
+hps_status hps_solve(hps_ctx* ctx, int ndir, const double* dir_angle_host);
+
+/* Scattered field at x_p = R (cos theta_p, sin theta_p), p < ntheta, for every
+ * solved direction: ufar (device, complex128 [ndir][ntheta]).  The
+ * measurement set (theta, R) is remembered for hps_jvp / hps_vjp; its
+ * quadrature matrices are rebuilt on the host when it changes.  The points
+ * must lie outside Omega.  Requires hps_solve. */
+hps_status hps_far_field(hps_ctx* ctx, int ntheta, const double* theta_host, double R,
+                         double* ufar);
+
+/* Total field u_0 at the PDE nodes for every solved direction:
+ * u (device, complex128 [ndir][npde]).  Requires hps_solve. */
+hps_status hps_total_field(hps_ctx* ctx, double* u);
+
+/* Frechet derivative (Theorem 1): dufar = J dq for a real perturbation dq
+ * (device, npde doubles) of the factored contrast, at the solved directions
+ * and the last measurement set: dufar (device, complex128 [ndir][ntheta]).
+ * Requires hps_far_field and keep_derivs. */
+hps_status hps_jvp(hps_ctx* ctx, const double* dq, double* dufar);
+
+/* Adjoint (Theorem 2, discrete): grad = Re(J^H r) for r (device, complex128
+ * [ndir][ntheta]); grad (device, npde doubles).  Same requirements as
+ * hps_jvp. */
+hps_status hps_vjp(hps_ctx* ctx, const double* r, double* grad);
+
+/* Sine model on Omega = [x0, x1] x [y0, y1]:
+ * q(x, y) = sum_{m,n=1..S} C[(m-1) S + (n-1)] sin(m pi (x - x0)/(x1 - x0))
+ *                                             sin(n pi (y - y0)/(y1 - y0))
+ * at the PDE nodes.  coef (device, S*S doubles), q_nodes (device, npde). */
+hps_status hps_sine_eval(hps_ctx* ctx, int S, const double* coef, double* q_nodes);
+
+/* Transpose of hps_sine_eval: coef = E^T g for g (device, npde doubles). */
+hps_status hps_sine_adjoint(hps_ctx* ctx, int S, const double* g, double* coef);
+
+typedef struct hps_stats {
+  double t_wavenumber_ms; /* last hps_set_wavenumber (host quadrature + upload) */
+  double t_factor_ms;     /* last hps_factor, device time between events */
+  double t_solve_ms;      /* last hps_solve */
+  double t_far_field_ms;  /* last hps_far_field (device part) */
+  double t_jvp_ms;        /* last hps_jvp */
+  double t_vjp_ms;        /* last hps_vjp */
+  int64_t device_bytes;   /* device memory held by the context */
+  int ndir;               /* directions of the last solve */
+  int singular;           /* 1 if the last factorisation met a zero pivot */
+} hps_stats;
+
+/* Timings of the last calls (synchronises the stream) and memory use. */
+hps_status hps_get_stats(hps_ctx* ctx, hps_stats* out);
+
+/* ---- dense building blocks, exposed for testing the kernels ---- */
+
+/* Batched complex GEMM C_b = alpha op(A_b) op(B_b) + beta C_b, b < batch,
+ * column-major; op: 0 = none, 1 = transpose, 2 = conjugate transpose.
+ * alpha/beta are (re, im) pairs on the host; strides are in elements
+ * (0 broadcasts).  Enqueued on `stream`. */
+hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const double* alpha,
+                     const double* A, int64_t lda, int64_t strideA, const double* B, int64_t ldb,
+                     int64_t strideB, const double* beta, double* C, int64_t ldc, int64_t strideC,
+                     int batch);
+
+/* Batched inverse of n x n complex matrices (column-major, leading dimension
+ * n, contiguous batch) by Gauss-Jordan elimination with partial pivoting:
+ * inv = A^{-1}; A is destroyed.  Synchronous; HPS_ESINGULAR on a zero
+ * pivot.  Allocates its own workspace. */
+hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPS_H_ */

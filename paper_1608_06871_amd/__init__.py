@@ -1,0 +1,256 @@
+"""Python binding of libhps, the MI355X HPS/ItI Helmholtz scattering library.
+
+Argument marshalling only: every computation runs in the HIP kernels behind
+the C ABI of include/hps.h.  Device arrays are torch tensors on the GPU
+(float64 / complex128, contiguous); the library enqueues on the stream given
+at construction (default: torch's current stream).  If libhps.so is missing
+the first call raises: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhps.so")
+_LIB = None
+
+HPS_OK, HPS_EINVAL, HPS_ENOMEM, HPS_EDEVICE, HPS_ESTATE, HPS_ESINGULAR, HPS_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "HPS_OK", -1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESTATE",
+          -5: "HPS_ESINGULAR", -6: "HPS_ENOCONV"}
+
+
+class HpsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("nleaf", ctypes.c_int), ("p", ctypes.c_int),
+                ("eta_scale", ctypes.c_double), ("keep_derivs", ctypes.c_int),
+                ("precision", ctypes.c_int), ("host_threads", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t_wavenumber_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_far_field_ms", ctypes.c_double),
+                ("t_jvp_ms", ctypes.c_double), ("t_vjp_ms", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int)]
+
+
+# (name, restype, argtypes) of every exported entry point
+_P, _D, _I, _L = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
+SIGNATURES = [
+    ("hps_default_opts", None, [ctypes.POINTER(Opts)]),
+    ("hps_create", _I, [ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
+    ("hps_destroy", None, [_P]),
+    ("hps_last_error", ctypes.c_char_p, [_P]),
+    ("hps_num_nodes", _L, [_P]),
+    ("hps_num_boundary_nodes", _L, [_P]),
+    ("hps_node_coords", _I, [_P, _P]),
+    ("hps_set_wavenumber", _I, [_P, _D]),
+    ("hps_factor", _I, [_P, _P, _D]),
+    ("hps_solve", _I, [_P, _I, _P]),
+    ("hps_far_field", _I, [_P, _I, _P, _D, _P]),
+    ("hps_total_field", _I, [_P, _P]),
+    ("hps_jvp", _I, [_P, _P, _P]),
+    ("hps_vjp", _I, [_P, _P, _P]),
+    ("hps_sine_eval", _I, [_P, _I, _P, _P]),
+    ("hps_sine_adjoint", _I, [_P, _I, _P, _P]),
+    ("hps_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
+    ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
+    ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
+]
+
+
+def lib():
+    """Loads libhps.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1608_06871_amd.build` (no CPU fallback exists)")
+        so = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(so, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = so
+    return _LIB
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype, numel=None, name="array"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One HPS context: geometry fixed at construction; factor/solve/... as in
+    the C ABI (include/hps.h)."""
+
+    def __init__(self, nleaf=4, p=16, box=(-1.0, 1.0, -1.0, 1.0), eta_scale=1.0,
+                 keep_derivs=True, host_threads=0, stream=None):
+        torch = _torch()
+        L = lib()
+        o = Opts()
+        L.hps_default_opts(ctypes.byref(o))
+        o.x0, o.x1, o.y0, o.y1 = map(float, box)
+        o.nleaf, o.p = int(nleaf), int(p)
+        o.eta_scale = float(eta_scale)
+        o.keep_derivs = 1 if keep_derivs else 0
+        o.host_threads = int(host_threads)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        h = ctypes.c_void_p()
+        rc = L.hps_create(ctypes.byref(o), ctypes.byref(h))
+        if rc != HPS_OK:
+            raise HpsError(rc, "hps_create failed (invalid options?)")
+        self._h = h
+        self.nleaf, self.p, self.box = o.nleaf, o.p, (o.x0, o.x1, o.y0, o.y1)
+        self.npde = int(L.hps_num_nodes(h))
+        self.nb = int(L.hps_num_boundary_nodes(h))
+        self.ndir = 0
+        self.ntheta = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.hps_destroy(h)
+            self._h = None
+
+    def _check(self, rc, what):
+        if rc != HPS_OK:
+            msg = lib().hps_last_error(self._h)
+            raise HpsError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def node_coords(self):
+        """[npde, 2] numpy array of PDE-node coordinates (interface order)."""
+        xy = np.zeros((self.npde, 2), dtype=np.float64)
+        self._check(lib().hps_node_coords(self._h, xy.ctypes.data_as(ctypes.c_void_p)), "node_coords")
+        return xy
+
+    def set_wavenumber(self, k):
+        self._check(lib().hps_set_wavenumber(self._h, float(k)), "set_wavenumber")
+
+    def factor(self, q, k):
+        torch = _torch()
+        self._q = q
+        self._check(lib().hps_factor(self._h, _dev(q, torch.float64, self.npde, "q"), float(k)), "factor")
+        self.k = float(k)
+
+    def solve(self, angles):
+        a = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
+        self._check(lib().hps_solve(self._h, int(a.size), a.ctypes.data_as(ctypes.c_void_p)), "solve")
+        self.ndir = int(a.size)
+
+    def far_field(self, thetas, R, out=None):
+        torch = _torch()
+        th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).ravel())
+        if out is None:
+            out = torch.empty((self.ndir, th.size), dtype=torch.complex128, device="cuda")
+        ptr = _dev(out, torch.complex128, self.ndir * th.size, "out")
+        self._check(lib().hps_far_field(self._h, int(th.size), th.ctypes.data_as(ctypes.c_void_p),
+                                        float(R), ptr), "far_field")
+        self.ntheta = int(th.size)
+        return out
+
+    def total_field(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.ndir, self.npde), dtype=torch.complex128, device="cuda")
+        self._check(lib().hps_total_field(self._h, _dev(out, torch.complex128, self.ndir * self.npde, "out")),
+                    "total_field")
+        return out
+
+    def jvp(self, dq, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.ndir, self.ntheta), dtype=torch.complex128, device="cuda")
+        self._check(lib().hps_jvp(self._h, _dev(dq, torch.float64, self.npde, "dq"),
+                                  _dev(out, torch.complex128, self.ndir * self.ntheta, "out")), "jvp")
+        return out
+
+    def vjp(self, r, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.npde, dtype=torch.float64, device="cuda")
+        self._check(lib().hps_vjp(self._h, _dev(r, torch.complex128, self.ndir * self.ntheta, "r"),
+                                  _dev(out, torch.float64, self.npde, "grad")), "vjp")
+        return out
+
+    def sine_eval(self, coef, out=None):
+        torch = _torch()
+        S = int(round(np.sqrt(coef.numel())))
+        if out is None:
+            out = torch.empty(self.npde, dtype=torch.float64, device="cuda")
+        self._check(lib().hps_sine_eval(self._h, S, _dev(coef, torch.float64, S * S, "coef"),
+                                        _dev(out, torch.float64, self.npde, "q")), "sine_eval")
+        return out
+
+    def sine_adjoint(self, g, S, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(S * S, dtype=torch.float64, device="cuda")
+        self._check(lib().hps_sine_adjoint(self._h, int(S), _dev(g, torch.float64, self.npde, "g"),
+                                           _dev(out, torch.float64, S * S, "coef")), "sine_adjoint")
+        return out
+
+    def stats(self):
+        s = Stats()
+        self._check(lib().hps_get_stats(self._h, ctypes.byref(s)), "stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+def zgemm(A, B, C=None, opA=0, opB=0, alpha=1.0, beta=0.0, stream=None):
+    """Batched complex GEMM on [batch, rows, cols] column-major views: each
+    torch tensor X of shape [batch, cols, rows] (row-major storage of the
+    column-major matrix).  Used by the kernel tests."""
+    torch = _torch()
+    for t in (A, B):
+        _dev(t, torch.complex128)
+    batch, ka, ra = A.shape
+    _, kb, rb = B.shape
+    M = ra if opA == 0 else ka
+    K = ka if opA == 0 else ra
+    N = kb if opB == 0 else rb
+    if C is None:
+        C = torch.zeros((batch, N, M), dtype=torch.complex128, device=A.device)
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    rc = lib().hps_zgemm(st, opA, opB, M, N, K, al, _dev(A, torch.complex128), ra, ka * ra,
+                         _dev(B, torch.complex128), rb, kb * rb, be, _dev(C, torch.complex128), M, N * M, batch)
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_zgemm")
+    return C
+
+
+def zinv(A, stream=None):
+    """Batched inverse of [batch, n, n] complex128 GPU matrices (column-major
+    storage, i.e. each [n, n] slice holds the transpose); A is destroyed."""
+    torch = _torch()
+    batch, n, _ = A.shape
+    inv = torch.empty_like(A)
+    st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    rc = lib().hps_zinv(st, n, batch, _dev(A, torch.complex128), _dev(inv, torch.complex128))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_zinv")
+    return inv

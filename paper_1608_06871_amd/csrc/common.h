@@ -1,0 +1,37 @@
+// Internal declarations shared by the HIP translation units of libhps.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+typedef long long ll;
+
+namespace hps {
+
+enum Op { OP_N = 0, OP_T = 1, OP_C = 2 };
+
+// Batched complex FP64 GEMM: C_b = alpha op(A_b) op(B_b) + beta C_b for
+// b < batch, column-major operands with leading dimensions ld* and batch
+// strides s* (a stride of 0 broadcasts one operand to the whole batch).
+// beta == 0 never reads C.
+hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
+                 const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB,
+                 double2 beta, double2* C, ll ldc, ll sC, int batch);
+
+// Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
+size_t zinv_workspace(int n, int batch);
+
+// Batched in-place-elimination inverse with partial pivoting (Gauss-Jordan,
+// blocked: panel eliminations followed by rank-b GEMM updates).  `work`
+// (order n, lda, stride sA) is destroyed; the inverse is written to `out`.
+// info[b] (device, one int per matrix) is set non-zero when a zero pivot was
+// met.  `ws` must hold zinv_workspace(n, batch) bytes.
+hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo,
+                ll sO, int batch, void* ws, int* info);
+
+}  // namespace hps
+
+#define HPS_HIP_TRY(expr)                            \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return _e;                 \
+  } while (0)

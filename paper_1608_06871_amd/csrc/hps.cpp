@@ -1,0 +1,870 @@
+// libhps: the C ABI of include/hps.h on top of the HIP kernels.
+//
+// Factorisation (per contrast q, wavenumber k):
+//   leaf stage   every leaf's collocation matrix (PDE rows + incoming
+//                impedance rows) is inverted in one batched call; from the
+//                inverse come Y (interior field from incoming impedance),
+//                R (leaf impedance-to-impedance map) and H (outgoing
+//                impedance from an interior body load);
+//   merge tree   per level, all merges are batched: with child maps
+//                Ra = [A11 A13; A31 A33], Rb = [B22 B23; B32 B33] on
+//                (exterior, shared) nodes and the matching f3a = -g3b,
+//                f3b = -g3a,
+//                  W  = I - B33 A33,
+//                  X  = W^-1 [B33 A31, -B32]         (f3a from [f1; f2])
+//                  Yb = -[A31, 0] - A33 X             (f3b from [f1; f2])
+//                  R  = blkdiag(A11, B22) + [A13 X; B23 Yb],
+//                D = [X; Yb] is kept for the down-sweep and
+//                U = [A13 V; -B23 (A33 V + [I, 0])], V = W^-1 [B33, -I],
+//                for the upward propagation of body-load data (derivatives);
+//   top          the outer-boundary system Z = A1 + A2 R_root with
+//                A1 = S/2 - (K - I/2)/(2 i eta), A2 = S/2 + (K - I/2)/(2 i eta)
+//                from the Calderon relation, inverted.
+// Solve: f_root = Z^-1 [S, -(K - I/2)] [d_nu u_inc; u_inc], then the
+// down-sweep f3 = D f through the levels and u = Y f at the leaves.
+#include "../../include/hps.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+#include "geometry.h"
+#include "hps_kernels.h"
+
+using namespace hps;
+
+namespace {
+
+struct HpsError {
+  hps_status code;
+  std::string msg;
+};
+
+#define CK(expr)                                                                          \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      throw HpsError{HPS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)};     \
+  } while (0)
+
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (n == 0) n = 256;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      p = nullptr;
+      throw HpsError{HPS_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
+    }
+    bytes = n;
+  }
+  double2* z() const { return (double2*)p; }
+  double* d() const { return (double*)p; }
+  int* i() const { return (int*)p; }
+};
+
+const double2 ONE = {1.0, 0.0};
+const double2 ZERO = {0.0, 0.0};
+const double2 MONE = {-1.0, 0.0};
+
+inline size_t zb(size_t n) { return n * sizeof(double2); }
+
+}  // namespace
+
+struct hps_ctx {
+  hps_opts o{};
+  hipStream_t st = nullptr;
+  int device = 0;
+  Geometry g;
+  std::string err;
+  int nthreads = 1;
+  int n = 0, nb = 0;
+
+  // per wavenumber
+  bool have_k = false;
+  double k = 0.0, eta = 0.0;
+  DBuf dA0, dMout, dBop, dA1, dA2, dbnode;
+  std::vector<DBuf> didx;  // 4 index arrays per level
+
+  // factorisation
+  bool factored = false;
+  int singular = 0;
+  DBuf dY, dH, dRroot, dZinv;
+  std::vector<DBuf> dD, dU;
+  DBuf sA, sInv, sZws, sR0, sR1, sBlk, sW, sWinv, sQ, sVin, sV, sTmp, sInfo;
+
+  // solve
+  bool solved = false;
+  int ndir = 0;
+  std::vector<double> h_dirs;
+  DBuf d_dirs, dG, dRhs, dF0, dF1, dF3, du0, dST, dg;
+
+  // measurement set
+  bool have_meas = false;
+  std::vector<double> theta;
+  double R = 0.0;
+  DBuf dPhi;
+
+  // derivative scratch
+  DBuf sB, sST2, sW2;
+
+  // sine model
+  int sine_S = 0;
+  DBuf dSx, dSy, dNodeGrid, sS1, sS2, sS3;
+
+  hipEvent_t ev[10] = {};  // start/end pairs: factor, solve, far field, jvp, vjp
+  double t_wave = 0.0;
+  bool ev_used[5] = {};
+};
+
+namespace {
+
+double elapsed_ms(hps_ctx* c, int a) {
+  if (!c->ev_used[a]) return 0.0;
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, c->ev[2 * a], c->ev[2 * a + 1]) != hipSuccess) return 0.0;
+  return ms;
+}
+
+void mark(hps_ctx* c, int a, int end) {
+  CK(hipEventRecord(c->ev[2 * a + end], c->st));
+  if (end) c->ev_used[a] = true;
+}
+
+template <class F>
+hps_status guard(hps_ctx* c, F&& f) {
+  try {
+    if (c) CK(hipSetDevice(c->device));
+    f();
+    if (c) c->err.clear();
+    return HPS_OK;
+  } catch (const HpsError& e) {
+    if (c) c->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return HPS_ENOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return HPS_EINVAL;
+  }
+}
+
+void require(bool cond, hps_status code, const char* msg) {
+  if (!cond) throw HpsError{code, msg};
+}
+
+void upload(DBuf& b, const void* src, size_t bytes, hipStream_t st) {
+  b.ensure(bytes);
+  CK(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, st));
+  CK(hipStreamSynchronize(st));
+}
+
+void set_wavenumber(hps_ctx* c, double k) {
+  require(std::isfinite(k) && k > 0.0, HPS_EINVAL, "wavenumber must be positive and finite");
+  const auto t0 = std::chrono::steady_clock::now();
+  const Geometry& g = c->g;
+  const double eta = (c->o.eta_scale > 0.0 ? c->o.eta_scale : 1.0) * k;
+  const int n = c->n, ne = g.ne, nb = c->nb;
+
+  std::vector<cplx> A0, Mout;
+  leaf_operators(g, k, eta, A0, Mout);
+  std::vector<cplx> A0c((size_t)n * n), Mc((size_t)ne * n);
+  for (int r = 0; r < n; ++r)
+    for (int j = 0; j < n; ++j) A0c[r + (size_t)j * n] = A0[(size_t)r * n + j];
+  for (int e = 0; e < ne; ++e)
+    for (int j = 0; j < n; ++j) Mc[e + (size_t)j * ne] = Mout[(size_t)e * n + j];
+
+  std::vector<double> tx(nb), ty(nb);
+  std::vector<double> bn(4 * (size_t)nb);
+  for (int i = 0; i < nb; ++i) {
+    const BoundaryNode& b = g.root[i];
+    tx[i] = b.x;
+    ty[i] = b.y;
+    bn[4 * i] = b.x;
+    bn[4 * i + 1] = b.y;
+    bn[4 * i + 2] = b.nx;
+    bn[4 * i + 3] = b.ny;
+  }
+  std::vector<cplx> S, K;
+  layer_moments(g, k, tx, ty, S, K, c->nthreads);
+  const cplx cinv = cplx(0.0, -1.0 / (2.0 * eta));  // 1 / (2 i eta)
+  std::vector<cplx> Bop((size_t)nb * 2 * nb), A1((size_t)nb * nb), A2((size_t)nb * nb);
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < nb; ++j) {
+      const cplx s = S[(size_t)i * nb + j];
+      const cplx kmi = K[(size_t)i * nb + j] - (i == j ? 0.5 : 0.0);
+      Bop[i + (size_t)j * nb] = s;
+      Bop[i + (size_t)(nb + j) * nb] = -kmi;
+      A1[i + (size_t)j * nb] = 0.5 * s - cinv * kmi;
+      A2[i + (size_t)j * nb] = 0.5 * s + cinv * kmi;
+    }
+  upload(c->dA0, A0c.data(), A0c.size() * sizeof(cplx), c->st);
+  upload(c->dMout, Mc.data(), Mc.size() * sizeof(cplx), c->st);
+  upload(c->dBop, Bop.data(), Bop.size() * sizeof(cplx), c->st);
+  upload(c->dA1, A1.data(), A1.size() * sizeof(cplx), c->st);
+  upload(c->dA2, A2.data(), A2.size() * sizeof(cplx), c->st);
+  upload(c->dbnode, bn.data(), bn.size() * sizeof(double), c->st);
+  c->k = k;
+  c->eta = eta;
+  c->have_k = true;
+  c->factored = false;
+  c->solved = false;
+  c->have_meas = false;
+  c->t_wave = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void plan_factor_buffers(hps_ctx* c) {
+  const Geometry& g = c->g;
+  const size_t nl = g.nleaf, n = c->n, ne = g.ne, mi = g.mi, nb = c->nb;
+  size_t zws = zinv_workspace((int)n, (int)nl);
+  size_t rmax = nl * ne * ne, blk = 0, w = 0, q = 0, v = 0;
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& P = g.lev[l];
+    const size_t cnt = P.count, m = P.m, s = P.s, np = P.np;
+    zws = std::max(zws, zinv_workspace((int)s, (int)cnt));
+    rmax = std::max(rmax, cnt * np * np);
+    blk = std::max(blk, cnt * (2 * m * s + s * m + 2 * s * s));
+    w = std::max(w, cnt * s * s);
+    q = std::max(q, cnt * 2 * s * m);
+    v = std::max(v, cnt * 2 * s * s);
+  }
+  zws = std::max(zws, zinv_workspace((int)nb, 1));
+  c->sA.ensure(zb(std::max(nl * n * n, nb * nb)));
+  c->sInv.ensure(zb(nl * n * n));
+  c->sZws.ensure(zws);
+  c->sR0.ensure(zb(rmax));
+  c->sR1.ensure(zb(rmax));
+  c->sBlk.ensure(zb(blk));
+  c->sW.ensure(zb(w));
+  c->sWinv.ensure(zb(w));
+  c->sQ.ensure(zb(q));
+  c->sVin.ensure(zb(v));
+  c->sV.ensure(zb(v));
+  c->sTmp.ensure(zb(v));
+  c->sInfo.ensure(sizeof(int) * std::max<size_t>(nl, 1));
+  c->dY.ensure(zb(nl * mi * ne));
+  if (c->o.keep_derivs) c->dH.ensure(zb(nl * ne * mi));
+  c->dRroot.ensure(zb(nb * nb));
+  c->dZinv.ensure(zb(nb * nb));
+  c->dD.resize(g.nlev + 1);
+  c->dU.resize(g.nlev + 1);
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& P = g.lev[l];
+    c->dD[l].ensure(zb((size_t)P.count * 2 * P.s * 2 * P.m));
+    if (c->o.keep_derivs) c->dU[l].ensure(zb((size_t)P.count * 2 * P.m * 2 * P.s));
+  }
+}
+
+void factor(hps_ctx* c, const double* q, double k) {
+  require(q != nullptr, HPS_EINVAL, "q_nodes is NULL");
+  if (!c->have_k || k != c->k) set_wavenumber(c, k);
+  plan_factor_buffers(c);
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int n = c->n, ne = g.ne, mi = g.mi, nl = g.nleaf, nb = c->nb;
+  const ll nn = (ll)n * n;
+  c->factored = false;
+  c->solved = false;
+  mark(c, 0, 0);
+  CK(hipMemsetAsync(c->sInfo.p, 0, sizeof(int) * nl, st));
+
+  // leaf stage
+  CK(leaf_assemble(st, c->dA0.z(), q, k * k, n, mi, c->sA.z(), nl));
+  CK(zinv(st, n, c->sA.z(), n, nn, c->sInv.z(), n, nn, nl, c->sZws.p, c->sInfo.i()));
+  const double2* inv_edge = c->sInv.z() + (ll)mi * n;  // columns for the edge unknowns
+  CK(gather2d(st, mi, ne, inv_edge, n, nn, nullptr, nullptr, c->dY.z(), mi, (ll)mi * ne, 1.0, nl));
+  double2* Rc = c->sR0.z();
+  CK(zgemm(st, OP_N, OP_N, ne, ne, n, ONE, c->dMout.z(), ne, 0, inv_edge, n, nn, ZERO, Rc, ne,
+           (ll)ne * ne, nl));
+  if (c->o.keep_derivs)
+    CK(zgemm(st, OP_N, OP_N, ne, mi, n, ONE, c->dMout.z(), ne, 0, c->sInv.z(), n, nn, ZERO,
+             c->dH.z(), ne, (ll)ne * mi, nl));
+
+  // merge tree
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& P = g.lev[l];
+    const int cnt = P.count, m = P.m, s = P.s, nc = P.nc, np = P.np;
+    const int* i1a = c->didx[4 * l].i();
+    const int* i3a = c->didx[4 * l + 1].i();
+    const int* i2b = c->didx[4 * l + 2].i();
+    const int* i3b = c->didx[4 * l + 3].i();
+    const ll sc = 2LL * nc * nc;
+    const double2* Ra = Rc;
+    const double2* Rb = Rc + (ll)nc * nc;
+    double2* A13 = c->sBlk.z();
+    double2* A31 = A13 + (ll)cnt * m * s;
+    double2* A33 = A31 + (ll)cnt * s * m;
+    double2* B23 = A33 + (ll)cnt * s * s;
+    double2* B33 = B23 + (ll)cnt * m * s;
+    const ll ms = (ll)m * s, ss = (ll)s * s;
+    CK(gather2d(st, m, s, Ra, nc, sc, i1a, i3a, A13, m, ms, 1.0, cnt));
+    CK(gather2d(st, s, m, Ra, nc, sc, i3a, i1a, A31, s, ms, 1.0, cnt));
+    CK(gather2d(st, s, s, Ra, nc, sc, i3a, i3a, A33, s, ss, 1.0, cnt));
+    CK(gather2d(st, m, s, Rb, nc, sc, i2b, i3b, B23, m, ms, 1.0, cnt));
+    CK(gather2d(st, s, s, Rb, nc, sc, i3b, i3b, B33, s, ss, 1.0, cnt));
+    // W = I - B33 A33, inverted
+    double2* W = c->sW.z();
+    double2* Wi = c->sWinv.z();
+    CK(set2d(st, s, s, W, s, ss, ONE, ZERO, cnt));
+    CK(zgemm(st, OP_N, OP_N, s, s, s, MONE, B33, s, ss, A33, s, ss, ONE, W, s, ss, cnt));
+    CK(zinv(st, s, W, s, ss, Wi, s, ss, cnt, c->sZws.p, c->sInfo.i()));
+    // Q = [B33 A31, -B32]
+    double2* Q = c->sQ.z();
+    const ll sq = 2 * ms;
+    CK(zgemm(st, OP_N, OP_N, s, m, s, ONE, B33, s, ss, A31, s, ms, ZERO, Q, s, sq, cnt));
+    CK(gather2d(st, s, m, Rb, nc, sc, i3b, i2b, Q + ms, s, sq, -1.0, cnt));
+    // D = [X; Yb]
+    double2* D = c->dD[l].z();
+    const ll sd = 4 * ms;
+    CK(zgemm(st, OP_N, OP_N, s, 2 * m, s, ONE, Wi, s, ss, Q, s, sq, ZERO, D, 2 * s, sd, cnt));
+    CK(gather2d(st, s, m, Ra, nc, sc, i3a, i1a, D + s, 2 * s, sd, -1.0, cnt));
+    CK(set2d(st, s, m, D + s + (ll)m * 2 * s, 2 * s, sd, ZERO, ZERO, cnt));
+    CK(zgemm(st, OP_N, OP_N, s, 2 * m, s, MONE, A33, s, ss, D, 2 * s, sd, ONE, D + s, 2 * s, sd,
+             cnt));
+    // parent map
+    double2* Rn = (Rc == c->sR0.z()) ? c->sR1.z() : c->sR0.z();
+    const ll sp = (ll)np * np;
+    CK(set2d(st, np, np, Rn, np, sp, ZERO, ZERO, cnt));
+    CK(gather2d(st, m, m, Ra, nc, sc, i1a, i1a, Rn, np, sp, 1.0, cnt));
+    CK(gather2d(st, m, m, Rb, nc, sc, i2b, i2b, Rn + m + (ll)m * np, np, sp, 1.0, cnt));
+    CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, A13, m, ms, D, 2 * s, sd, ONE, Rn, np, sp, cnt));
+    CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, B23, m, ms, D + s, 2 * s, sd, ONE, Rn + m, np, sp,
+             cnt));
+    if (c->o.keep_derivs) {
+      double2* Vin = c->sVin.z();
+      double2* V = c->sV.z();
+      double2* Tm = c->sTmp.z();
+      const ll sv = 2 * ss;
+      CK(gather2d(st, s, s, B33, s, ss, nullptr, nullptr, Vin, s, sv, 1.0, cnt));
+      CK(set2d(st, s, s, Vin + ss, s, sv, MONE, ZERO, cnt));
+      CK(zgemm(st, OP_N, OP_N, s, 2 * s, s, ONE, Wi, s, ss, Vin, s, sv, ZERO, V, s, sv, cnt));
+      double2* U = c->dU[l].z();
+      CK(zgemm(st, OP_N, OP_N, m, 2 * s, s, ONE, A13, m, ms, V, s, sv, ZERO, U, 2 * m, sd, cnt));
+      CK(set2d(st, s, 2 * s, Tm, s, sv, ONE, ZERO, cnt));
+      CK(zgemm(st, OP_N, OP_N, s, 2 * s, s, ONE, A33, s, ss, V, s, sv, ONE, Tm, s, sv, cnt));
+      CK(zgemm(st, OP_N, OP_N, m, 2 * s, s, MONE, B23, m, ms, Tm, s, sv, ZERO, U + m, 2 * m, sd,
+               cnt));
+    }
+    Rc = Rn;
+  }
+
+  // top: Z = A1 + A2 R_root, inverted
+  CK(hipMemcpyAsync(c->dRroot.p, Rc, zb((size_t)nb * nb), hipMemcpyDeviceToDevice, st));
+  double2* Z = c->sA.z();
+  CK(hipMemcpyAsync(Z, c->dA1.p, zb((size_t)nb * nb), hipMemcpyDeviceToDevice, st));
+  CK(zgemm(st, OP_N, OP_N, nb, nb, nb, ONE, c->dA2.z(), nb, 0, c->dRroot.z(), nb, 0, ONE, Z, nb, 0,
+           1));
+  CK(zinv(st, nb, Z, nb, 0, c->dZinv.z(), nb, 0, 1, c->sZws.p, c->sInfo.i()));
+  mark(c, 0, 1);
+  std::vector<int> info(nl);
+  CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * nl, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  c->singular = 0;
+  for (int v : info) c->singular |= (v != 0);
+  if (c->singular) throw HpsError{HPS_ESINGULAR, "zero pivot in the factorisation"};
+  c->factored = true;
+}
+
+void plan_sweep_buffers(hps_ctx* c, int M) {
+  const Geometry& g = c->g;
+  size_t fmax = (size_t)g.nleaf * g.ne, f3 = 0;
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& P = g.lev[l];
+    fmax = std::max(fmax, (size_t)P.count * P.np);
+    f3 = std::max(f3, (size_t)P.count * 2 * P.s);
+  }
+  fmax = std::max(fmax, (size_t)c->nb);
+  c->dF0.ensure(zb(fmax * M));
+  c->dF1.ensure(zb(fmax * M));
+  c->dF3.ensure(zb(std::max<size_t>(f3, 1) * M));
+  c->dG.ensure(zb((size_t)2 * c->nb * M));
+  c->dRhs.ensure(zb((size_t)c->nb * M));
+  c->dg.ensure(zb((size_t)c->nb * M));
+  c->dST.ensure(zb((size_t)2 * c->nb * M));
+  c->du0.ensure(zb((size_t)g.nleaf * g.mi * M));
+}
+
+// Scatter parent data [f1; f2] and shared-edge data [f3a; f3b] into the two
+// children's boundary orderings (one level of the down-sweep; also the
+// adjoint of the up-sweep's gathers).
+void scatter_children(hps_ctx* c, int l, const double2* Fp, const double2* F3, double2* Fch, int M) {
+  const LevelPattern& P = c->g.lev[l];
+  const int cnt = P.count, m = P.m, s = P.s, nc = P.nc, np = P.np;
+  const ll sp = (ll)np * M, s3 = 2LL * s * M, sc = 2LL * nc * M;
+  hipStream_t st = c->st;
+  CK(scatter_rows(st, m, M, Fp, np, sp, c->didx[4 * l].i(), Fch, nc, sc, cnt));
+  CK(scatter_rows(st, s, M, F3, 2 * s, s3, c->didx[4 * l + 1].i(), Fch, nc, sc, cnt));
+  CK(scatter_rows(st, m, M, Fp + m, np, sp, c->didx[4 * l + 2].i(), Fch + (ll)nc * M, nc, sc, cnt));
+  CK(scatter_rows(st, s, M, F3 + s, 2 * s, s3, c->didx[4 * l + 3].i(), Fch + (ll)nc * M, nc, sc, cnt));
+}
+
+void solve(hps_ctx* c, int M, const double* ang) {
+  require(c->factored, HPS_ESTATE, "hps_solve before hps_factor");
+  require(M >= 1 && M <= 65535 && ang != nullptr, HPS_EINVAL, "bad direction list");
+  for (int i = 0; i < M; ++i) require(std::isfinite(ang[i]), HPS_EINVAL, "non-finite angle");
+  plan_sweep_buffers(c, M);
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int nb = c->nb;
+  c->h_dirs.resize(2 * (size_t)M);
+  for (int i = 0; i < M; ++i) {
+    c->h_dirs[2 * i] = std::cos(ang[i]);
+    c->h_dirs[2 * i + 1] = std::sin(ang[i]);
+  }
+  upload(c->d_dirs, c->h_dirs.data(), c->h_dirs.size() * sizeof(double), st);
+  c->solved = false;
+  mark(c, 1, 0);
+  CK(incident(st, (const double4*)c->dbnode.p, nb, c->d_dirs.z(), M, c->k, c->dG.z()));
+  CK(zgemm(st, OP_N, OP_N, nb, M, 2 * nb, ONE, c->dBop.z(), nb, 0, c->dG.z(), 2 * nb, 0, ZERO,
+           c->dRhs.z(), nb, 0, 1));
+  double2* Fc = c->dF0.z();
+  double2* Fo = c->dF1.z();
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, 0, c->dRhs.z(), nb, 0, ZERO, Fc, nb, 0,
+           1));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, 0, Fc, nb, 0, ZERO, c->dg.z(), nb, 0,
+           1));
+  CK(boundary_st(st, Fc, c->dg.z(), c->dG.z(), nb, M, c->eta, c->dST.z()));
+  for (int l = g.nlev; l >= 1; --l) {
+    const LevelPattern& P = g.lev[l];
+    const int cnt = P.count, m = P.m, s = P.s, np = P.np;
+    CK(zgemm(st, OP_N, OP_N, 2 * s, M, 2 * m, ONE, c->dD[l].z(), 2 * s, 4LL * m * s, Fc, np,
+             (ll)np * M, ZERO, c->dF3.z(), 2 * s, 2LL * s * M, cnt));
+    scatter_children(c, l, Fc, c->dF3.z(), Fo, M);
+    std::swap(Fc, Fo);
+  }
+  CK(zgemm(st, OP_N, OP_N, g.mi, M, g.ne, ONE, c->dY.z(), g.mi, (ll)g.mi * g.ne, Fc, g.ne,
+           (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf));
+  mark(c, 1, 1);
+  c->ndir = M;
+  c->solved = true;
+}
+
+void set_measurement(hps_ctx* c, int nt, const double* th, double R) {
+  bool same = c->have_meas && nt == (int)c->theta.size() && R == c->R;
+  if (same)
+    for (int i = 0; i < nt; ++i) same = same && th[i] == c->theta[i];
+  if (same) return;
+  const Geometry& g = c->g;
+  const double half = 0.5 * g.h * g.L;
+  const double xc = g.x0 + half, yc = g.y0 + half;
+  std::vector<double> tx(nt), ty(nt);
+  for (int i = 0; i < nt; ++i) {
+    require(std::isfinite(th[i]), HPS_EINVAL, "non-finite angle");
+    tx[i] = R * std::cos(th[i]);
+    ty[i] = R * std::sin(th[i]);
+    require(std::max(std::fabs(tx[i] - xc), std::fabs(ty[i] - yc)) > half * (1.0 + 1e-12),
+            HPS_EINVAL, "measurement point inside Omega");
+  }
+  std::vector<cplx> PS, PD;
+  layer_moments(g, c->k, tx, ty, PS, PD, c->nthreads);
+  const int nb = c->nb;
+  std::vector<cplx> Phi((size_t)nt * 2 * nb);
+  for (int p = 0; p < nt; ++p)
+    for (int j = 0; j < nb; ++j) {
+      Phi[p + (size_t)j * nt] = PD[(size_t)p * nb + j];
+      Phi[p + (size_t)(nb + j) * nt] = -PS[(size_t)p * nb + j];
+    }
+  upload(c->dPhi, Phi.data(), Phi.size() * sizeof(cplx), c->st);
+  c->theta.assign(th, th + nt);
+  c->R = R;
+  c->have_meas = true;
+}
+
+void far_field(hps_ctx* c, int nt, const double* th, double R, double* out) {
+  require(c->solved, HPS_ESTATE, "hps_far_field before hps_solve");
+  require(nt >= 1 && th != nullptr && out != nullptr && std::isfinite(R) && R > 0.0, HPS_EINVAL,
+          "bad measurement arguments");
+  set_measurement(c, nt, th, R);
+  const int nb = c->nb, M = c->ndir;
+  mark(c, 2, 0);
+  CK(zgemm(c->st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, 0, c->dST.z(), 2 * nb, 0, ZERO,
+           (double2*)out, nt, 0, 1));
+  mark(c, 2, 1);
+}
+
+void jvp(hps_ctx* c, const double* dq, double* out) {
+  require(c->solved && c->have_meas, HPS_ESTATE, "hps_jvp needs hps_solve and hps_far_field");
+  require(c->o.keep_derivs != 0, HPS_ESTATE, "context created without keep_derivs");
+  require(dq != nullptr && out != nullptr, HPS_EINVAL, "NULL argument");
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size();
+  c->sB.ensure(zb((size_t)g.nleaf * g.mi * M));
+  c->sST2.ensure(zb((size_t)2 * nb * M));
+  c->sW2.ensure(zb((size_t)nb * M));
+  mark(c, 3, 0);
+  CK(body_load(st, dq, c->du0.z(), c->k * c->k, g.mi, M, g.nleaf, c->sB.z()));
+  double2* Hc = c->dF0.z();
+  double2* Ho = c->dF1.z();
+  CK(zgemm(st, OP_N, OP_N, g.ne, M, g.mi, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, c->sB.z(), g.mi,
+           (ll)g.mi * M, ZERO, Hc, g.ne, (ll)g.ne * M, g.nleaf));
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& P = g.lev[l];
+    const int cnt = P.count, m = P.m, s = P.s, nc = P.nc, np = P.np;
+    const ll sc = 2LL * nc * M, sp = (ll)np * M, s3 = 2LL * s * M;
+    const double2* Ha = Hc;
+    const double2* Hb = Hc + (ll)nc * M;
+    double2* H3 = c->dF3.z();
+    CK(gather2d(st, m, M, Ha, nc, sc, c->didx[4 * l].i(), nullptr, Ho, np, sp, 1.0, cnt));
+    CK(gather2d(st, m, M, Hb, nc, sc, c->didx[4 * l + 2].i(), nullptr, Ho + m, np, sp, 1.0, cnt));
+    CK(gather2d(st, s, M, Ha, nc, sc, c->didx[4 * l + 1].i(), nullptr, H3, 2 * s, s3, 1.0, cnt));
+    CK(gather2d(st, s, M, Hb, nc, sc, c->didx[4 * l + 3].i(), nullptr, H3 + s, 2 * s, s3, 1.0, cnt));
+    CK(zgemm(st, OP_N, OP_N, np, M, 2 * s, ONE, c->dU[l].z(), np, 4LL * m * s, H3, 2 * s, s3, ONE,
+             Ho, np, sp, cnt));
+    std::swap(Hc, Ho);
+  }
+  // root: Z f = -A2 h,  g = R f + h
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA2.z(), nb, 0, Hc, nb, 0, ZERO, c->sW2.z(), nb, 0, 1));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dZinv.z(), nb, 0, c->sW2.z(), nb, 0, ZERO, Ho, nb, 0,
+           1));
+  CK(hipMemcpyAsync(c->dg.p, Hc, zb((size_t)nb * M), hipMemcpyDeviceToDevice, st));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, 0, Ho, nb, 0, ONE, c->dg.z(), nb, 0, 1));
+  CK(boundary_st(st, Ho, c->dg.z(), nullptr, nb, M, c->eta, c->sST2.z()));
+  CK(zgemm(st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, 0, c->sST2.z(), 2 * nb, 0, ZERO,
+           (double2*)out, nt, 0, 1));
+  mark(c, 3, 1);
+}
+
+void vjp(hps_ctx* c, const double* r, double* grad) {
+  require(c->solved && c->have_meas, HPS_ESTATE, "hps_vjp needs hps_solve and hps_far_field");
+  require(c->o.keep_derivs != 0, HPS_ESTATE, "context created without keep_derivs");
+  require(r != nullptr && grad != nullptr, HPS_EINVAL, "NULL argument");
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size();
+  c->sB.ensure(zb((size_t)g.nleaf * g.mi * M));
+  c->sST2.ensure(zb((size_t)2 * nb * M));
+  c->sW2.ensure(zb((size_t)nb * M));
+  mark(c, 4, 0);
+  // [sbar; tbar] = Phi^H r
+  CK(zgemm(st, OP_C, OP_N, 2 * nb, M, nt, ONE, c->dPhi.z(), nt, 0, (const double2*)r, nt, 0, ZERO,
+           c->sST2.z(), 2 * nb, 0, 1));
+  double2* Hc = c->dF0.z();
+  double2* Ho = c->dF1.z();
+  double2* fb = Ho;
+  double2* gb = Hc;
+  CK(boundary_st_adj(st, c->sST2.z(), nb, M, c->eta, fb, gb));
+  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, 0, gb, nb, 0, ONE, fb, nb, 0, 1));
+  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, 0, fb, nb, 0, ZERO, c->sW2.z(), nb, 0, 1));
+  CK(zgemm(st, OP_C, OP_N, nb, M, nb, MONE, c->dA2.z(), nb, 0, c->sW2.z(), nb, 0, ONE, gb, nb, 0, 1));
+  for (int l = g.nlev; l >= 1; --l) {
+    const LevelPattern& P = g.lev[l];
+    const int cnt = P.count, m = P.m, s = P.s, np = P.np;
+    CK(zgemm(st, OP_C, OP_N, 2 * s, M, np, ONE, c->dU[l].z(), np, 4LL * m * s, Hc, np, (ll)np * M,
+             ZERO, c->dF3.z(), 2 * s, 2LL * s * M, cnt));
+    scatter_children(c, l, Hc, c->dF3.z(), Ho, M);
+    std::swap(Hc, Ho);
+  }
+  CK(zgemm(st, OP_C, OP_N, g.mi, M, g.ne, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, Hc, g.ne,
+           (ll)g.ne * M, ZERO, c->sB.z(), g.mi, (ll)g.mi * M, g.nleaf));
+  CK(grad_reduce(st, c->du0.z(), c->sB.z(), c->k * c->k, g.mi, M, g.nleaf, grad));
+  mark(c, 4, 1);
+}
+
+void sine_setup(hps_ctx* c, int S) {
+  if (S == c->sine_S) return;
+  const Geometry& g = c->g;
+  const int m1 = g.p - 2, nX = g.L * m1;
+  const double PI = 3.14159265358979323846;
+  const double Lx = g.h * g.L;
+  std::vector<cplx> Sx((size_t)nX * S), Sy((size_t)nX * S);
+  for (int i = 0; i < nX; ++i) {
+    const int leaf = i / m1, a = i % m1 + 1;
+    const double u = (leaf + 0.5 * (1.0 + g.t[a])) / g.L;  // (x - x0) / Lx
+    for (int m = 1; m <= S; ++m) {
+      const double v = std::sin(m * PI * u);
+      Sx[i + (size_t)(m - 1) * nX] = v;
+      Sy[i + (size_t)(m - 1) * nX] = v;
+    }
+  }
+  (void)Lx;
+  std::vector<int> node(g.nleaf * (size_t)g.mi);
+  size_t o = 0;
+  for (int z = 0; z < g.nleaf; ++z) {
+    int i = 0, j = 0;
+    for (int b = 0; (z >> (2 * b)) != 0; ++b) {
+      i |= ((z >> (2 * b)) & 1) << b;
+      j |= ((z >> (2 * b + 1)) & 1) << b;
+    }
+    for (int b = 1; b <= m1; ++b)
+      for (int a = 1; a <= m1; ++a) node[o++] = (i * m1 + a - 1) + (j * m1 + b - 1) * nX;
+  }
+  upload(c->dSx, Sx.data(), Sx.size() * sizeof(cplx), c->st);
+  upload(c->dSy, Sy.data(), Sy.size() * sizeof(cplx), c->st);
+  upload(c->dNodeGrid, node.data(), node.size() * sizeof(int), c->st);
+  c->sS1.ensure(zb((size_t)nX * nX));
+  c->sS2.ensure(zb((size_t)nX * S));
+  c->sS3.ensure(zb((size_t)S * S + nX * (size_t)nX));
+  c->sine_S = S;
+}
+
+void sine_eval(hps_ctx* c, int S, const double* coef, double* q) {
+  require(S >= 1 && S <= 4096 && coef && q, HPS_EINVAL, "bad sine-model arguments");
+  sine_setup(c, S);
+  const Geometry& g = c->g;
+  const int nX = g.L * (g.p - 2);
+  hipStream_t st = c->st;
+  double2* Cc = c->sS3.z();
+  CK(real_to_complex(st, coef, (ll)S * S, Cc));
+  // T1 = Sy Cc (nX x S);  Q = Sx T1^T (nX x nX)
+  CK(zgemm(st, OP_N, OP_N, nX, S, S, ONE, c->dSy.z(), nX, 0, Cc, S, 0, ZERO, c->sS2.z(), nX, 0, 1));
+  CK(zgemm(st, OP_N, OP_T, nX, nX, S, ONE, c->dSx.z(), nX, 0, c->sS2.z(), nX, 0, ZERO, c->sS1.z(), nX,
+           0, 1));
+  // gather grid values into node order, keep the real part
+  const ll npde = (ll)g.nleaf * g.mi;
+  double2* tmp = c->sS3.z() + (ll)S * S;
+  CK(gather2d(st, (int)npde, 1, c->sS1.z(), npde, 0, c->dNodeGrid.i(), nullptr, tmp, npde, 0, 1.0, 1));
+  CK(complex_real_part(st, tmp, npde, q));
+}
+
+void sine_adjoint(hps_ctx* c, int S, const double* gv, double* coef) {
+  require(S >= 1 && S <= 4096 && gv && coef, HPS_EINVAL, "bad sine-model arguments");
+  sine_setup(c, S);
+  const Geometry& g = c->g;
+  const int nX = g.L * (g.p - 2);
+  hipStream_t st = c->st;
+  const ll npde = (ll)g.nleaf * g.mi;
+  double2* tmp = c->sS3.z() + (ll)S * S;
+  CK(real_to_complex(st, gv, npde, tmp));
+  // G (nX x nX grid) from node values
+  CK(scatter_rows(st, (int)npde, 1, tmp, npde, 0, c->dNodeGrid.i(), c->sS1.z(), (ll)nX * nX, 0, 1));
+  // T3 = G^T Sx (nX x S);  Out = Sy^T T3 (S x S)
+  CK(zgemm(st, OP_T, OP_N, nX, S, nX, ONE, c->sS1.z(), nX, 0, c->dSx.z(), nX, 0, ZERO, c->sS2.z(), nX,
+           0, 1));
+  CK(zgemm(st, OP_T, OP_N, S, S, nX, ONE, c->dSy.z(), nX, 0, c->sS2.z(), nX, 0, ZERO, c->sS3.z(), S, 0,
+           1));
+  CK(complex_real_part(st, c->sS3.z(), (ll)S * S, coef));
+}
+
+int64_t device_bytes(const hps_ctx* c) {
+  int64_t s = 0;
+  const DBuf* bufs[] = {&c->dA0, &c->dMout, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dY, &c->dH,
+                        &c->dRroot, &c->dZinv, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
+                        &c->sBlk, &c->sW, &c->sWinv, &c->sQ, &c->sVin, &c->sV, &c->sTmp, &c->sInfo,
+                        &c->d_dirs, &c->dG, &c->dRhs, &c->dF0, &c->dF1, &c->dF3, &c->du0, &c->dST,
+                        &c->dg, &c->dPhi, &c->sB, &c->sST2, &c->sW2, &c->dSx, &c->dSy,
+                        &c->dNodeGrid, &c->sS1, &c->sS2, &c->sS3};
+  for (const DBuf* b : bufs) s += (int64_t)b->bytes;
+  for (const auto& b : c->didx) s += (int64_t)b.bytes;
+  for (const auto& b : c->dD) s += (int64_t)b.bytes;
+  for (const auto& b : c->dU) s += (int64_t)b.bytes;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hps_default_opts(hps_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->x0 = -1.0;
+  o->x1 = 1.0;
+  o->y0 = -1.0;
+  o->y1 = 1.0;
+  o->nleaf = 4;
+  o->p = 16;
+  o->eta_scale = 1.0;
+  o->keep_derivs = 1;
+  o->precision = HPS_FP64;
+  o->host_threads = 0;
+  o->stream = nullptr;
+}
+
+hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
+  if (!opts || !out) return HPS_EINVAL;
+  *out = nullptr;
+  const hps_opts& o = *opts;
+  const double lx = o.x1 - o.x0, ly = o.y1 - o.y0;
+  if (!(lx > 0.0) || std::fabs(lx - ly) > 1e-14 * lx) return HPS_EINVAL;
+  if (o.nleaf < 1 || o.nleaf > 256 || (o.nleaf & (o.nleaf - 1))) return HPS_EINVAL;
+  if (o.p < 4 || o.p > 20) return HPS_EINVAL;
+  if (o.precision != HPS_FP64) return HPS_EINVAL;
+  hps_ctx* c = nullptr;
+  try {
+    c = new hps_ctx();
+  } catch (...) {
+    return HPS_ENOMEM;
+  }
+  hps_status s = guard(nullptr, [&] {
+    c->o = o;
+    c->st = (hipStream_t)o.stream;
+    CK(hipGetDevice(&c->device));
+    unsigned hw = std::thread::hardware_concurrency();
+    c->nthreads = o.host_threads > 0 ? o.host_threads : (int)std::min(16u, std::max(1u, hw));
+    c->g.build(o.x0, o.x1, o.y0, o.nleaf, o.p);
+    c->n = c->g.mi + c->g.ne;
+    c->nb = (int)c->g.root.size();
+    c->didx.resize(4 * (size_t)(c->g.nlev + 1));
+    for (int l = 1; l <= c->g.nlev; ++l) {
+      const LevelPattern& P = c->g.lev[l];
+      const std::vector<int>* v[4] = {&P.pos1a, &P.pos3a, &P.pos2b, &P.pos3b};
+      for (int a = 0; a < 4; ++a)
+        upload(c->didx[4 * l + a], v[a]->data(), v[a]->size() * sizeof(int), c->st);
+    }
+    for (auto& e : c->ev) CK(hipEventCreate(&e));
+  });
+  if (s != HPS_OK) {
+    hps_destroy(c);
+    return s;
+  }
+  *out = c;
+  return HPS_OK;
+}
+
+void hps_destroy(hps_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->st);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* hps_last_error(const hps_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int64_t hps_num_nodes(const hps_ctx* c) { return c ? (int64_t)c->g.nleaf * c->g.mi : 0; }
+
+int64_t hps_num_boundary_nodes(const hps_ctx* c) { return c ? (int64_t)c->nb : 0; }
+
+hps_status hps_node_coords(const hps_ctx* c, double* xy) {
+  if (!c || !xy) return HPS_EINVAL;
+  c->g.pde_coords(xy);
+  return HPS_OK;
+}
+
+hps_status hps_set_wavenumber(hps_ctx* c, double k) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { set_wavenumber(c, k); });
+}
+
+hps_status hps_factor(hps_ctx* c, const double* q, double k) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { factor(c, q, k); });
+}
+
+hps_status hps_solve(hps_ctx* c, int ndir, const double* ang) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { solve(c, ndir, ang); });
+}
+
+hps_status hps_far_field(hps_ctx* c, int nt, const double* th, double R, double* out) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { far_field(c, nt, th, R, out); });
+}
+
+hps_status hps_total_field(hps_ctx* c, double* u) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] {
+    require(c->solved, HPS_ESTATE, "hps_total_field before hps_solve");
+    require(u != nullptr, HPS_EINVAL, "NULL output");
+    CK(export_field(c->st, c->du0.z(), c->g.mi, c->ndir, c->g.nleaf, (double2*)u));
+  });
+}
+
+hps_status hps_jvp(hps_ctx* c, const double* dq, double* out) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { jvp(c, dq, out); });
+}
+
+hps_status hps_vjp(hps_ctx* c, const double* r, double* grad) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { vjp(c, r, grad); });
+}
+
+hps_status hps_sine_eval(hps_ctx* c, int S, const double* coef, double* q) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { sine_eval(c, S, coef, q); });
+}
+
+hps_status hps_sine_adjoint(hps_ctx* c, int S, const double* g, double* coef) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] { sine_adjoint(c, S, g, coef); });
+}
+
+hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
+  if (!c || !out) return HPS_EINVAL;
+  return guard(c, [&] {
+    CK(hipStreamSynchronize(c->st));
+    std::memset(out, 0, sizeof(*out));
+    out->t_wavenumber_ms = c->t_wave;
+    out->t_factor_ms = elapsed_ms(c, 0);
+    out->t_solve_ms = elapsed_ms(c, 1);
+    out->t_far_field_ms = elapsed_ms(c, 2);
+    out->t_jvp_ms = elapsed_ms(c, 3);
+    out->t_vjp_ms = elapsed_ms(c, 4);
+    out->device_bytes = device_bytes(c);
+    out->ndir = c->ndir;
+    out->singular = c->singular;
+  });
+}
+
+hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const double* alpha,
+                     const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb,
+                     int64_t sB, const double* beta, double* C, int64_t ldc, int64_t sC,
+                     int batch) {
+  if (!alpha || !beta || M < 0 || N < 0 || K < 0 || batch < 0) return HPS_EINVAL;
+  if (opA < 0 || opA > 2 || opB < 0 || opB > 2) return HPS_EINVAL;
+  if (M == 0 || N == 0 || batch == 0) return HPS_OK;
+  if (!A || !B || !C) return HPS_EINVAL;
+  const ll rowsA = opA == OP_N ? M : K, rowsB = opB == OP_N ? K : N;
+  if (lda < std::max<ll>(1, rowsA) || ldb < std::max<ll>(1, rowsB) || ldc < std::max(1, M))
+    return HPS_EINVAL;
+  const hipError_t e = zgemm((hipStream_t)stream, opA, opB, M, N, K, make_double2(alpha[0], alpha[1]),
+                             (const double2*)A, lda, sA, (const double2*)B, ldb, sB,
+                             make_double2(beta[0], beta[1]), (double2*)C, ldc, sC, batch);
+  return e == hipSuccess ? HPS_OK : HPS_EDEVICE;
+}
+
+hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv) {
+  if (n < 0 || batch < 0 || batch > 65535) return HPS_EINVAL;
+  if (n == 0 || batch == 0) return HPS_OK;
+  if (!A || !inv) return HPS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  void* ws = nullptr;
+  int* info = nullptr;
+  if (hipMalloc(&ws, zinv_workspace(n, batch)) != hipSuccess) return HPS_ENOMEM;
+  if (hipMalloc((void**)&info, sizeof(int) * batch) != hipSuccess) {
+    (void)hipFree(ws);
+    return HPS_ENOMEM;
+  }
+  hps_status s = HPS_OK;
+  std::vector<int> h(batch, 0);
+  if (hipMemsetAsync(info, 0, sizeof(int) * batch, st) != hipSuccess ||
+      zinv(st, n, (double2*)A, n, (ll)n * n, (double2*)inv, n, (ll)n * n, batch, ws, info) !=
+          hipSuccess ||
+      hipMemcpyAsync(h.data(), info, sizeof(int) * batch, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    s = HPS_EDEVICE;
+  } else {
+    for (int v : h)
+      if (v) s = HPS_ESINGULAR;
+  }
+  (void)hipFree(ws);
+  (void)hipFree(info);
+  return s;
+}
+
+}  // extern "C"

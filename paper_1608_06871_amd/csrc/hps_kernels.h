@@ -1,0 +1,35 @@
+// Launchers for the pointwise / data-movement kernels (hps_kernels.hip).
+#pragma once
+#include "common.h"
+
+namespace hps {
+
+// out[z] = A0 with -k2 q[z][r] added to the diagonal of the first mi rows.
+hipError_t leaf_assemble(hipStream_t st, const double2* A0, const double* q, double k2, int n,
+                         int mi, double2* out, ll nleaf);
+// out(i, j) = sc * in(ridx[i], cidx[j]) (null index array = identity).
+hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
+                    const int* ridx, const int* cidx, double2* out, ll ldo, ll so, double sc,
+                    int batch);
+// out(ridx[i], j) = in(i, j).
+hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
+                        const int* ridx, double2* out, ll ldo, ll so, int batch);
+// out = off everywhere, diag on the diagonal.
+hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
+                 double2 off, int batch);
+hipError_t incident(hipStream_t st, const double4* bnode, int nb, const double2* dirs, int ndir,
+                    double k, double2* G);
+hipError_t boundary_st(hipStream_t st, const double2* f, const double2* g, const double2* G,
+                       int nb, int ncol, double eta, double2* ST);
+hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, double eta,
+                           double2* fb, double2* gb);
+hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, double k2, int mi,
+                     int ndir, ll nleaf, double2* b);
+hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, double k2, int mi,
+                       int ndir, ll nleaf, double* grad);
+hipError_t export_field(hipStream_t st, const double2* u0, int mi, int ndir, ll nleaf,
+                        double2* out);
+hipError_t real_to_complex(hipStream_t st, const double* x, ll n, double2* y);
+hipError_t complex_real_part(hipStream_t st, const double2* x, ll n, double* y);
+
+}  // namespace hps

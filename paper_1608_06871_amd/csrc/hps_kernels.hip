@@ -1,0 +1,267 @@
+// Data-movement and pointwise kernels of the HPS solver.  All heavy
+// arithmetic (leaf inversions, merges, sweeps, far field) goes through the
+// complex GEMM / inverse; these kernels assemble leaf matrices, move blocks
+// between the boxes of adjacent tree levels, and form boundary data.
+#include "common.h"
+#include "hps_kernels.h"
+
+namespace hps {
+namespace {
+
+constexpr int NT = 256;
+
+inline unsigned blocks_for(ll n) {
+  ll b = (n + NT - 1) / NT;
+  if (b > 1048576) b = 1048576;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+__global__ void k_leaf_assemble(const double2* A0, const double* q, double k2, int n, int mi,
+                                double2* out, ll nleaf) {
+  const ll per = (ll)n * n;
+  const ll total = per * nleaf;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll z = idx / per;
+    const int e = (int)(idx % per);
+    double2 v = A0[e];
+    const int r = e % n, c = e / n;
+    if (r == c && r < mi) v.x -= k2 * q[z * mi + r];
+    out[idx] = v;
+  }
+}
+
+__global__ void k_gather2d(int M, int N, const double2* in, ll ldi, ll si, const int* ridx,
+                           const int* cidx, double2* out, ll ldo, ll so, double sc, int batch) {
+  const ll per = (ll)M * N;
+  const ll total = per * batch;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll b = idx / per;
+    const int e = (int)(idx % per);
+    const int i = e % M, j = e / M;
+    const int ri = ridx ? ridx[i] : i;
+    const int cj = cidx ? cidx[j] : j;
+    const double2 v = in[b * si + (ll)ri + (ll)cj * ldi];
+    out[b * so + (ll)i + (ll)j * ldo] = make_double2(sc * v.x, sc * v.y);
+  }
+}
+
+__global__ void k_scatter_rows(int M, int N, const double2* in, ll ldi, ll si, const int* ridx,
+                               double2* out, ll ldo, ll so, int batch) {
+  const ll per = (ll)M * N;
+  const ll total = per * batch;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll b = idx / per;
+    const int e = (int)(idx % per);
+    const int i = e % M, j = e / M;
+    out[b * so + (ll)ridx[i] + (ll)j * ldo] = in[b * si + (ll)i + (ll)j * ldi];
+  }
+}
+
+__global__ void k_set2d(int M, int N, double2* out, ll ldo, ll so, double2 diag, double2 off,
+                        int batch) {
+  const ll per = (ll)M * N;
+  const ll total = per * batch;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll b = idx / per;
+    const int e = (int)(idx % per);
+    const int i = e % M, j = e / M;
+    out[b * so + (ll)i + (ll)j * ldo] = (i == j) ? diag : off;
+  }
+}
+
+// Rows [0, nb): d_nu u_inc; rows [nb, 2 nb): u_inc, one column per direction.
+__global__ void k_incident(const double4* bnode, int nb, const double2* dirs, int ndir, double k,
+                           double2* G) {
+  const ll total = (ll)nb * ndir;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const int i = (int)(idx % nb), m = (int)(idx / nb);
+    const double4 b = bnode[i];
+    const double2 d = dirs[m];
+    double s, c;
+    sincos(k * (b.x * d.x + b.y * d.y), &s, &c);
+    const double kn = k * (b.z * d.x + b.w * d.y);
+    G[(ll)m * 2 * nb + i] = make_double2(-kn * s, kn * c);
+    G[(ll)m * 2 * nb + nb + i] = make_double2(c, s);
+  }
+}
+
+// From the incoming/outgoing impedance (f, g) on the outer boundary:
+//   s = (f - g) / (2 i eta) - u_inc,  t = (f + g) / 2 - d_nu u_inc
+// (the incident terms are skipped when G is null).  Output [s; t] per column.
+__global__ void k_boundary_st(const double2* f, const double2* g, const double2* G, int nb,
+                              int ncol, double eta, double2* ST) {
+  const ll total = (ll)nb * ncol;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const int i = (int)(idx % nb), m = (int)(idx / nb);
+    const double2 fv = f[(ll)m * nb + i], gv = g[(ll)m * nb + i];
+    const double2 dmin = make_double2(fv.x - gv.x, fv.y - gv.y);
+    // (a + ib) / (2 i eta) = (b - i a) / (2 eta)
+    double2 s = make_double2(dmin.y / (2.0 * eta), -dmin.x / (2.0 * eta));
+    double2 t = make_double2(0.5 * (fv.x + gv.x), 0.5 * (fv.y + gv.y));
+    if (G) {
+      const double2 du = G[(ll)m * 2 * nb + i], u = G[(ll)m * 2 * nb + nb + i];
+      s.x -= u.x;
+      s.y -= u.y;
+      t.x -= du.x;
+      t.y -= du.y;
+    }
+    ST[(ll)m * 2 * nb + i] = s;
+    ST[(ll)m * 2 * nb + nb + i] = t;
+  }
+}
+
+// Adjoint of k_boundary_st without incident terms: from (sbar, tbar)
+//   fbar = conj(1/(2 i eta)) sbar + tbar / 2,  gbar = -conj(1/(2 i eta)) sbar + tbar / 2.
+__global__ void k_boundary_st_adj(const double2* STb, int nb, int ncol, double eta, double2* fb,
+                                  double2* gb) {
+  const ll total = (ll)nb * ncol;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const int i = (int)(idx % nb), m = (int)(idx / nb);
+    const double2 sb = STb[(ll)m * 2 * nb + i], tb = STb[(ll)m * 2 * nb + nb + i];
+    // conj(1/(2 i eta)) = i / (2 eta):  i (a + ib) / (2 eta) = (-b + i a) / (2 eta)
+    const double2 c = make_double2(-sb.y / (2.0 * eta), sb.x / (2.0 * eta));
+    fb[(ll)m * nb + i] = make_double2(c.x + 0.5 * tb.x, c.y + 0.5 * tb.y);
+    gb[(ll)m * nb + i] = make_double2(-c.x + 0.5 * tb.x, -c.y + 0.5 * tb.y);
+  }
+}
+
+// b[z][n + m mi] = k^2 dq[z mi + n] u0[z][n + m mi]
+__global__ void k_body_load(const double* dq, const double2* u0, double k2, int mi, int ndir,
+                            ll nleaf, double2* b) {
+  const ll per = (ll)mi * ndir;
+  const ll total = per * nleaf;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll z = idx / per;
+    const int n = (int)(idx % per) % mi;
+    const double s = k2 * dq[z * mi + n];
+    const double2 u = u0[idx];
+    b[idx] = make_double2(s * u.x, s * u.y);
+  }
+}
+
+// grad[z mi + n] = Re sum_m k^2 conj(u0) bbar   (fixed summation order)
+__global__ void k_grad_reduce(const double2* u0, const double2* bb, double k2, int mi, int ndir,
+                              ll nleaf, double* grad) {
+  const ll total = (ll)mi * nleaf;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll z = idx / mi;
+    const int n = (int)(idx % mi);
+    const ll base = z * (ll)mi * ndir + n;
+    double acc = 0.0;
+    for (int m = 0; m < ndir; ++m) {
+      const double2 u = u0[base + (ll)m * mi], v = bb[base + (ll)m * mi];
+      acc += u.x * v.x + u.y * v.y;
+    }
+    grad[idx] = k2 * acc;
+  }
+}
+
+// out[m][z mi + n] = u0[z][n + m mi]
+__global__ void k_export_field(const double2* u0, int mi, int ndir, ll nleaf, double2* out) {
+  const ll npde = (ll)mi * nleaf;
+  const ll total = npde * ndir;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll m = idx / npde, node = idx % npde;
+    const ll z = node / mi;
+    const int n = (int)(node % mi);
+    out[idx] = u0[z * (ll)mi * ndir + m * mi + n];
+  }
+}
+
+__global__ void k_real_to_complex(const double* x, ll n, double2* y) {
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < n; idx += (ll)gridDim.x * NT)
+    y[idx] = make_double2(x[idx], 0.0);
+}
+
+__global__ void k_complex_real_part(const double2* x, ll n, double* y) {
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < n; idx += (ll)gridDim.x * NT)
+    y[idx] = x[idx].x;
+}
+
+}  // namespace
+
+hipError_t leaf_assemble(hipStream_t st, const double2* A0, const double* q, double k2, int n,
+                         int mi, double2* out, ll nleaf) {
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(blocks_for((ll)n * n * nleaf)), dim3(NT), 0, st, A0, q,
+                     k2, n, mi, out, nleaf);
+  return hipGetLastError();
+}
+
+hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
+                    const int* ridx, const int* cidx, double2* out, ll ldo, ll so, double sc,
+                    int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather2d, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, in,
+                     ldi, si, ridx, cidx, out, ldo, so, sc, batch);
+  return hipGetLastError();
+}
+
+hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
+                        const int* ridx, double2* out, ll ldo, ll so, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
+                     in, ldi, si, ridx, out, ldo, so, batch);
+  return hipGetLastError();
+}
+
+hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
+                 double2 off, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set2d, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, out, ldo,
+                     so, diag, off, batch);
+  return hipGetLastError();
+}
+
+hipError_t incident(hipStream_t st, const double4* bnode, int nb, const double2* dirs, int ndir,
+                    double k, double2* G) {
+  hipLaunchKernelGGL(k_incident, dim3(blocks_for((ll)nb * ndir)), dim3(NT), 0, st, bnode, nb, dirs,
+                     ndir, k, G);
+  return hipGetLastError();
+}
+
+hipError_t boundary_st(hipStream_t st, const double2* f, const double2* g, const double2* G,
+                       int nb, int ncol, double eta, double2* ST) {
+  hipLaunchKernelGGL(k_boundary_st, dim3(blocks_for((ll)nb * ncol)), dim3(NT), 0, st, f, g, G, nb,
+                     ncol, eta, ST);
+  return hipGetLastError();
+}
+
+hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, double eta,
+                           double2* fb, double2* gb) {
+  hipLaunchKernelGGL(k_boundary_st_adj, dim3(blocks_for((ll)nb * ncol)), dim3(NT), 0, st, STb, nb,
+                     ncol, eta, fb, gb);
+  return hipGetLastError();
+}
+
+hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, double k2, int mi,
+                     int ndir, ll nleaf, double2* b) {
+  hipLaunchKernelGGL(k_body_load, dim3(blocks_for((ll)mi * ndir * nleaf)), dim3(NT), 0, st, dq, u0,
+                     k2, mi, ndir, nleaf, b);
+  return hipGetLastError();
+}
+
+hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, double k2, int mi,
+                       int ndir, ll nleaf, double* grad) {
+  hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for((ll)mi * nleaf)), dim3(NT), 0, st, u0, bb, k2,
+                     mi, ndir, nleaf, grad);
+  return hipGetLastError();
+}
+
+hipError_t export_field(hipStream_t st, const double2* u0, int mi, int ndir, ll nleaf,
+                        double2* out) {
+  hipLaunchKernelGGL(k_export_field, dim3(blocks_for((ll)mi * ndir * nleaf)), dim3(NT), 0, st, u0,
+                     mi, ndir, nleaf, out);
+  return hipGetLastError();
+}
+
+hipError_t real_to_complex(hipStream_t st, const double* x, ll n, double2* y) {
+  hipLaunchKernelGGL(k_real_to_complex, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t complex_real_part(hipStream_t st, const double2* x, ll n, double* y) {
+  hipLaunchKernelGGL(k_complex_real_part, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+}  // namespace hps

@@ -1,0 +1,123 @@
+"""GPU parity of the HPS solver (through the C ABI) with the CPU oracle:
+forward far field, total field, Frechet derivative, adjoint, sine model."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import sine as osine
+from oracle.bie import circle_points
+from oracle.forward import Problem, directions
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+_CACHE = {}
+
+
+def _case(L, k, M, P, seed, nbumps=5, R=2.0):
+    key = (L, k, M, P, seed, nbumps, R)
+    if key not in _CACHE:
+        prob = Problem(L, k)
+        q = synth.gaussian_bumps(prob.grid.pde_coords(), nbumps, seed)
+        prob.factor(q)
+        prob.solve(directions(M))
+        _, th = circle_points(R, P)
+        prob.set_measurement(th, R)
+        _CACHE[key] = (prob, q, th)
+    return _CACHE[key]
+
+
+def _solver(L, **kw):
+    import paper_1608_06871_amd as hps
+    return hps.Solver(nleaf=L, p=16, **kw)
+
+
+def test_node_coords_match_oracle():
+    _torch()
+    for L in (1, 2, 4):
+        s = _solver(L)
+        prob = Problem.__new__(Problem)
+        from oracle.grid import Grid
+        assert np.max(np.abs(s.node_coords() - Grid(L).pde_coords())) < 1e-15
+
+
+@pytest.mark.parametrize("L,k,M,P,seed", [(1, 3.0, 3, 8, 4), (2, 5.0, 4, 16, 3), (4, 10.0, 16, 64, 1)])
+def test_forward_far_field_matches_oracle(L, k, M, P, seed):
+    torch = _torch()
+    print(f"forward L={L} k={k} M={M} P={P} seed={seed}", flush=True)
+    prob, q, th = _case(L, k, M, P, seed)
+    s = _solver(L)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    s.solve(directions(M))
+    uf = s.far_field(th, 2.0).cpu().numpy()
+    ref = prob.far_field()
+    assert _rel(uf, ref) < 1e-9
+    u = s.total_field().cpu().numpy()
+    assert _rel(u, prob.u_pde().T) < 1e-9
+
+
+def test_zero_contrast_gpu():
+    torch = _torch()
+    s = _solver(4)
+    s.factor(torch.zeros(s.npde, dtype=torch.float64, device="cuda"), 10.0)
+    s.solve(directions(8))
+    uf = s.far_field(circle_points(2.0, 32)[1], 2.0).cpu().numpy()
+    assert np.max(np.abs(uf)) < 1e-8
+
+
+def test_jvp_vjp_match_oracle():
+    torch = _torch()
+    L, k, M, P = 2, 5.0, 4, 16
+    prob, q, th = _case(L, k, M, P, 3)
+    s = _solver(L)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    s.solve(directions(M))
+    s.far_field(th, 2.0)
+    rng = np.random.default_rng(9)
+    dq = synth.gaussian_bumps(prob.grid.pde_coords(), 3, 7) + 0.1 * rng.standard_normal(prob.grid.npde)
+    jv = s.jvp(torch.from_numpy(dq).cuda()).cpu().numpy()
+    assert _rel(jv, prob.jvp(dq)) < 1e-9
+    r = rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))
+    g = s.vjp(torch.from_numpy(r).cuda()).cpu().numpy()
+    assert _rel(g, prob.vjp(r)) < 1e-9
+    # adjoint identity on the GPU results themselves
+    assert abs(np.real(np.vdot(r, jv)) - dq @ g) < 1e-10 * abs(dq @ g)
+
+
+def test_sine_maps_match_oracle():
+    torch = _torch()
+    s = _solver(4)
+    xy = s.node_coords()
+    rng = np.random.default_rng(1)
+    for S in (1, 3, 10):
+        C = rng.standard_normal((S, S))
+        q = s.sine_eval(torch.from_numpy(C.ravel()).cuda()).cpu().numpy()
+        assert np.max(np.abs(q - osine.evaluate(xy, C))) < 1e-12 * max(1.0, np.abs(C).sum())
+        gvals = rng.standard_normal(s.npde)
+        a = s.sine_adjoint(torch.from_numpy(gvals).cuda(), S).cpu().numpy().reshape(S, S)
+        ref = osine.adjoint(xy, gvals, S)
+        assert np.max(np.abs(a - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_call_order_errors():
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    s = _solver(2)
+    with pytest.raises(hps.HpsError) as e:
+        s.solve([0.0])
+    assert e.value.code == hps.HPS_ESTATE
+    q = torch.zeros(s.npde, dtype=torch.float64, device="cuda")
+    with pytest.raises(hps.HpsError) as e:
+        s.factor(q, -1.0)
+    assert e.value.code == hps.HPS_EINVAL
