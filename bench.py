@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the HPS hot path on one MI355X.
+
+Workload (default): Omega = [-1, 1]^2, 64 x 64 leaves of 16 x 16 Chebyshev
+points (N = 961^2 grid points), k = 80, contrast = 40 Gaussian bumps rescaled
+to max 0.5 (seed 3), 256 incident directions, 256 measurement angles on the
+circle R = 2, complex128 throughout.
+
+One step = the whole hot path over that input: factor(q, k) + solve(256
+directions) + far field + Frechet derivative (jvp, 256 right-hand sides) +
+adjoint (vjp, 256 right-hand sides).  value = RHS solves per second over the
+step: 3 * 256 right-hand sides (forward, derivative, adjoint) / step time,
+factorisation included.  The per-wavenumber exterior set-up (host quadrature
+of the layer potentials) is done once before timing and reported as
+t_wavenumber_ms.
+
+Prints one JSON line (see the keys below).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    # name: (nleaf, k, ndir, ntheta, nbumps, seed, amp, rescale)
+    "k80_L64_M256": (64, 80.0, 256, 256, 40, 3, (0.0, 0.5), 0.5),
+    "k10_L4_M16": (4, 10.0, 16, 64, 5, 1, (0.1, 0.3), None),
+}
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def inputs(xy, cfg):
+    import synth
+    L, k, M, P, nb, seed, amp, resc = cfg
+    q = synth.gaussian_bumps(xy, nb, seed, amp=amp, width=0.15, rescale_max=resc)
+    dq = synth.gaussian_bumps(xy, 3, seed + 100, amp=(0.01, 0.02), width=0.3)
+    rng = np.random.default_rng(seed + 200)
+    r = rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))
+    return q, dq, r
+
+
+def cpu_baseline(cfg, L_sample=8):
+    """The oracle on a bounded sample of the workload: the same k, directions,
+    angles and contrast generator on L_sample x L_sample leaves."""
+    from oracle.bie import circle_points
+    from oracle.forward import Problem, directions
+    L, k, M, P = cfg[0], cfg[1], cfg[2], cfg[3]
+    Ls = min(L, L_sample)
+    prob = Problem(Ls, k)
+    xy = prob.grid.pde_coords()
+    q, dq, r = inputs(xy, cfg)
+    _, th = circle_points(2.0, P)
+    prob.set_measurement(th, 2.0)
+    t0 = time.perf_counter()
+    prob.factor(q)
+    prob.solve(directions(M))
+    prob.far_field()
+    prob.jvp(dq)
+    prob.vjp(r)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    return {"value": 3 * M / dt, "unit": "RHS solves/s", "cores": int(blas),
+            "kind": "oracle",
+            "sample": f"oracle step (factor + {M}-direction solve + far field + jvp + vjp) at k={k:g}, "
+                      f"{Ls}x{Ls} leaves (1/{(L // Ls) ** 2} of the workload's leaves), "
+                      f"{P} angles: {dt:.1f} s; SuperLU on 1 thread, dense parts on {blas} BLAS threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="k80_L64_M256", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (--gpus {args.gpus} "
+              "requested). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1608_06871_amd as hps
+    import synth
+
+    cfg = CONFIGS[args.config]
+    L, k, M, P = cfg[0], cfg[1], cfg[2], cfg[3]
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    log(f"config {args.config}: L={L} k={k} M={M} P={P}")
+    s = hps.Solver(nleaf=L, p=16, keep_derivs=True)
+    xy = s.node_coords()
+    q_np, dq_np, r_np = inputs(xy, cfg)
+    q = torch.from_numpy(q_np).cuda()
+    dq = torch.from_numpy(dq_np).cuda()
+    r = torch.from_numpy(r_np).cuda()
+    dirs = synth.equispaced_angles(M)
+    th = synth.equispaced_angles(P)
+    R = 2.0
+    t0 = time.perf_counter()
+    s.set_wavenumber(k)
+    t_wave = (time.perf_counter() - t0) * 1e3
+    log(f"exterior set-up (host quadrature) {t_wave:.0f} ms")
+    ufar = torch.empty((M, P), dtype=torch.complex128, device="cuda")
+    dfar = torch.empty((M, P), dtype=torch.complex128, device="cuda")
+    grad = torch.empty(s.npde, dtype=torch.float64, device="cuda")
+
+    def step():
+        s.factor(q, k)
+        s.solve(dirs)
+        s.far_field(th, R, out=ufar)
+        s.jvp(dq, out=dfar)
+        s.vjp(r, out=grad)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    phases = {"factor": [], "solve": [], "far_field": [], "jvp": [], "vjp": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        st = s.stats()
+        for ph in phases:
+            phases[ph].append(st[f"t_{ph}_ms"])
+        log(f"step {i + 1}/{args.steps}: factor {st['t_factor_ms']:.1f} ms, solve {st['t_solve_ms']:.1f} ms, "
+            f"jvp {st['t_jvp_ms']:.1f} ms, vjp {st['t_vjp_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = 3 * M * args.steps / dt
+    dev_bytes = s.stats()["device_bytes"]
+
+    roofline = None
+    kernels = None
+    if not args.no_profile:
+        # one more step with every kernel launch bracketed by HIP events on
+        # the launch stream; the dominant kernel class gives the roofline
+        torch.cuda.synchronize()
+        hps.profile_start()
+        step()
+        kernels = hps.profile_stop()
+        dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
+        kd = kernels[dom]
+        per_launch_ms = kd["total_ms"] / kd["launches"]
+        if kd["flops"] > 0:
+            achieved = kd["flops"] / (kd["total_ms"] * 1e-3) / 1e12
+            roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                        "launches": kd["launches"], "avg_launch_ms": per_launch_ms,
+                        "flops_per_launch": kd["flops"] / kd["launches"]}
+        else:
+            achieved = kd["bytes"] / (kd["total_ms"] * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
+                        "launches": kd["launches"], "avg_launch_ms": per_launch_ms,
+                        "bytes_per_launch": kd["bytes"] / kd["launches"]}
+        log("kernel classes: " + ", ".join(f"{n} {v['total_ms']:.1f} ms/{v['launches']}" for n, v in kernels.items()))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(cfg)
+        log(f"cpu baseline: {cpu['value']:.2f} RHS solves/s")
+
+    med = {ph: float(np.median(v)) for ph, v in phases.items()}
+    out = {
+        "metric": "RHS solves/sec + factor time at k=80, mixed vs FP64 at <=1e-8 rel far-field err",
+        "value": value,
+        "unit": "RHS solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"HPS forward+jvp+vjp, k={k:g}, {L}x{L} leaves of 16x16, "
+                               f"{M} directions, {P} angles, R={R:g}, FP64",
+                   "k": k, "nleaf": L, "p": 16, "ndir": M, "ntheta": P, "precision": "fp64"},
+        "factor_ms": med["factor"],
+        "solve_ms": med["solve"],
+        "far_field_ms": med["far_field"],
+        "jvp_ms": med["jvp"],
+        "vjp_ms": med["vjp"],
+        "solve_only_rhs_per_s": M / (med["solve"] * 1e-3) if med["solve"] > 0 else None,
+        "t_wavenumber_ms": t_wave,
+        "device_bytes": dev_bytes,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

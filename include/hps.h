@@ -191,6 +191,26 @@ hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const 
  * pivot.  Allocates its own workspace. */
 hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
 
+/* ---- launch profiler (measurement support) ---- */
+
+typedef struct hps_kernel_stat {
+  char name[32];     /* kernel class: zgemm, gj_panel, gj_permute, gather_scatter,
+                        leaf_assemble, pointwise */
+  int64_t launches;  /* launches timed */
+  double total_ms;   /* sum of per-launch durations (HIP events on the launch stream) */
+  double flops;      /* sum of algorithmic flops (complex multiply-add = 8) */
+  double bytes;      /* sum of algorithmic bytes read + written */
+} hps_kernel_stat;
+
+/* Clears the records and times every following kernel launch of the library
+ * (process-wide) until hps_profile_stop.  Adds two event records per launch. */
+hps_status hps_profile_start(void);
+
+/* Stops timing, synchronises the device and writes up to `max` per-class
+ * totals to out (host array); returns their number (or a negative
+ * hps_status). */
+int hps_profile_stop(hps_kernel_stat* out, int max);
+
 #ifdef __cplusplus
 }
 #endif

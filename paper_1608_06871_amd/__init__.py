@@ -41,6 +41,11 @@ class Stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 # (name, restype, argtypes) of every exported entry point
 _P, _D, _I, _L = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
 SIGNATURES = [
@@ -63,6 +68,8 @@ SIGNATURES = [
     ("hps_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
     ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
     ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
+    ("hps_profile_start", _I, []),
+    ("hps_profile_stop", _I, [ctypes.POINTER(KernelStat), _I]),
 ]
 
 
@@ -254,3 +261,20 @@ def zinv(A, stream=None):
     if rc != HPS_OK:
         raise HpsError(rc, "hps_zinv")
     return inv
+
+
+def profile_start():
+    """Times every following kernel launch of the library (HIP events)."""
+    rc = lib().hps_profile_start()
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_profile_start")
+
+
+def profile_stop():
+    """Stops timing; returns {kernel class: {launches, total_ms, flops, bytes}}."""
+    buf = (KernelStat * 16)()
+    n = lib().hps_profile_stop(buf, 16)
+    if n < 0:
+        raise HpsError(n, "hps_profile_stop")
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                                   "flops": buf[i].flops, "bytes": buf[i].bytes} for i in range(n)}

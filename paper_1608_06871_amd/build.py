@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhps.so")
-SOURCES = ["zgemm.hip", "zinv.hip", "hps_kernels.hip", "geometry.cpp", "hps.cpp"]
+SOURCES = ["zgemm.hip", "zinv.hip", "hps_kernels.hip", "geometry.cpp", "hps.cpp", "profiler.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # no packed FP32 instructions anywhere in the device code

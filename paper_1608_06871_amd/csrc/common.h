@@ -28,6 +28,23 @@ size_t zinv_workspace(int n, int batch);
 hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo,
                 ll sO, int batch, void* ws, int* info);
 
+// Kernel classes of the optional launch profiler.
+enum KernelKind { K_ZGEMM = 0, K_GJ_PANEL, K_GJ_PERM, K_MOVE, K_LEAF, K_POINT, KIND_COUNT };
+
+// RAII: when profiling is on, records HIP events around the kernel launched
+// inside its scope, with that launch's algorithmic flops and bytes.
+class KernelTimer {
+ public:
+  KernelTimer(hipStream_t st, int kind, double flops, double bytes);
+  ~KernelTimer();
+  KernelTimer(const KernelTimer&) = delete;
+  KernelTimer& operator=(const KernelTimer&) = delete;
+
+ private:
+  hipStream_t st_;
+  long idx_;
+};
+
 }  // namespace hps
 
 #define HPS_HIP_TRY(expr)                            \

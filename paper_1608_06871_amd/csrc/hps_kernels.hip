@@ -182,6 +182,7 @@ __global__ void k_complex_real_part(const double2* x, ll n, double* y) {
 
 hipError_t leaf_assemble(hipStream_t st, const double2* A0, const double* q, double k2, int n,
                          int mi, double2* out, ll nleaf) {
+  KernelTimer kt(st, K_LEAF, 0.0, 16.0 * (double)n * n * nleaf + 8.0 * mi * (double)nleaf);
   hipLaunchKernelGGL(k_leaf_assemble, dim3(blocks_for((ll)n * n * nleaf)), dim3(NT), 0, st, A0, q,
                      k2, n, mi, out, nleaf);
   return hipGetLastError();
@@ -191,6 +192,7 @@ hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll 
                     const int* ridx, const int* cidx, double2* out, ll ldo, ll so, double sc,
                     int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
   hipLaunchKernelGGL(k_gather2d, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, in,
                      ldi, si, ridx, cidx, out, ldo, so, sc, batch);
   return hipGetLastError();
@@ -199,6 +201,7 @@ hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll 
 hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
                         const int* ridx, double2* out, ll ldo, ll so, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
   hipLaunchKernelGGL(k_scatter_rows, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
                      in, ldi, si, ridx, out, ldo, so, batch);
   return hipGetLastError();
@@ -207,6 +210,7 @@ hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi,
 hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
                  double2 off, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 0.0, 16.0 * (double)M * N * batch);
   hipLaunchKernelGGL(k_set2d, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, out, ldo,
                      so, diag, off, batch);
   return hipGetLastError();
@@ -214,6 +218,7 @@ hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, doub
 
 hipError_t incident(hipStream_t st, const double4* bnode, int nb, const double2* dirs, int ndir,
                     double k, double2* G) {
+  KernelTimer kt(st, K_POINT, 0.0, (32.0 + 32.0 * ndir) * (double)nb);
   hipLaunchKernelGGL(k_incident, dim3(blocks_for((ll)nb * ndir)), dim3(NT), 0, st, bnode, nb, dirs,
                      ndir, k, G);
   return hipGetLastError();
@@ -221,6 +226,7 @@ hipError_t incident(hipStream_t st, const double4* bnode, int nb, const double2*
 
 hipError_t boundary_st(hipStream_t st, const double2* f, const double2* g, const double2* G,
                        int nb, int ncol, double eta, double2* ST) {
+  KernelTimer kt(st, K_POINT, 0.0, 16.0 * 5.0 * nb * (double)ncol);
   hipLaunchKernelGGL(k_boundary_st, dim3(blocks_for((ll)nb * ncol)), dim3(NT), 0, st, f, g, G, nb,
                      ncol, eta, ST);
   return hipGetLastError();
@@ -228,6 +234,7 @@ hipError_t boundary_st(hipStream_t st, const double2* f, const double2* g, const
 
 hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, double eta,
                            double2* fb, double2* gb) {
+  KernelTimer kt(st, K_POINT, 0.0, 16.0 * 4.0 * nb * (double)ncol);
   hipLaunchKernelGGL(k_boundary_st_adj, dim3(blocks_for((ll)nb * ncol)), dim3(NT), 0, st, STb, nb,
                      ncol, eta, fb, gb);
   return hipGetLastError();
@@ -235,6 +242,7 @@ hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol,
 
 hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, double k2, int mi,
                      int ndir, ll nleaf, double2* b) {
+  KernelTimer kt(st, K_POINT, 6.0 * mi * (double)ndir * nleaf, (8.0 + 32.0 * ndir) * mi * (double)nleaf);
   hipLaunchKernelGGL(k_body_load, dim3(blocks_for((ll)mi * ndir * nleaf)), dim3(NT), 0, st, dq, u0,
                      k2, mi, ndir, nleaf, b);
   return hipGetLastError();
@@ -242,6 +250,7 @@ hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, double
 
 hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, double k2, int mi,
                        int ndir, ll nleaf, double* grad) {
+  KernelTimer kt(st, K_POINT, 4.0 * mi * (double)ndir * nleaf, (8.0 + 32.0 * ndir) * mi * (double)nleaf);
   hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for((ll)mi * nleaf)), dim3(NT), 0, st, u0, bb, k2,
                      mi, ndir, nleaf, grad);
   return hipGetLastError();
@@ -249,17 +258,20 @@ hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, dou
 
 hipError_t export_field(hipStream_t st, const double2* u0, int mi, int ndir, ll nleaf,
                         double2* out) {
+  KernelTimer kt(st, K_POINT, 0.0, 32.0 * mi * (double)ndir * nleaf);
   hipLaunchKernelGGL(k_export_field, dim3(blocks_for((ll)mi * ndir * nleaf)), dim3(NT), 0, st, u0,
                      mi, ndir, nleaf, out);
   return hipGetLastError();
 }
 
 hipError_t real_to_complex(hipStream_t st, const double* x, ll n, double2* y) {
+  KernelTimer kt(st, K_POINT, 0.0, 24.0 * (double)n);
   hipLaunchKernelGGL(k_real_to_complex, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
   return hipGetLastError();
 }
 
 hipError_t complex_real_part(hipStream_t st, const double2* x, ll n, double* y) {
+  KernelTimer kt(st, K_POINT, 0.0, 24.0 * (double)n);
   hipLaunchKernelGGL(k_complex_real_part, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
   return hipGetLastError();
 }

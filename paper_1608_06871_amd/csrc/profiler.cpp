@@ -1,0 +1,96 @@
+// Optional per-launch timing of the library's kernels with HIP events on the
+// launch stream, accumulated per kernel class with the launch's algorithmic
+// flops and bytes.  Disabled unless hps_profile_start() was called.
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/hps.h"
+#include "common.h"
+
+namespace hps {
+namespace {
+
+struct Rec {
+  hipEvent_t a, b;
+  int kind;
+  double flops, bytes;
+};
+
+std::atomic<bool> g_on{false};
+std::mutex g_mu;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+size_t g_used = 0;
+
+const char* const KIND_NAMES[KIND_COUNT] = {"zgemm", "gj_panel", "gj_permute", "gather_scatter",
+                                             "leaf_assemble", "pointwise"};
+
+hipEvent_t take() {
+  if (g_used == g_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_pool.push_back(e);
+  }
+  return g_pool[g_used++];
+}
+
+}  // namespace
+
+KernelTimer::KernelTimer(hipStream_t st, int kind, double flops, double bytes) {
+  st_ = st;
+  idx_ = -1;
+  if (!g_on.load(std::memory_order_relaxed)) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipEvent_t a = take(), b = take();
+  if (!a || !b) return;
+  if (hipEventRecord(a, st) != hipSuccess) return;
+  g_recs.push_back(Rec{a, b, kind, flops, bytes});
+  idx_ = (long)g_recs.size() - 1;
+}
+
+KernelTimer::~KernelTimer() {
+  if (idx_ < 0) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (idx_ < (long)g_recs.size()) (void)hipEventRecord(g_recs[idx_].b, st_);
+}
+
+}  // namespace hps
+
+extern "C" {
+
+hps_status hps_profile_start(void) {
+  std::lock_guard<std::mutex> lk(hps::g_mu);
+  hps::g_recs.clear();
+  hps::g_used = 0;
+  hps::g_on.store(true);
+  return HPS_OK;
+}
+
+int hps_profile_stop(hps_kernel_stat* out, int max) {
+  hps::g_on.store(false);
+  if (hipDeviceSynchronize() != hipSuccess) return HPS_EDEVICE;
+  std::lock_guard<std::mutex> lk(hps::g_mu);
+  hps_kernel_stat acc[hps::KIND_COUNT];
+  std::memset(acc, 0, sizeof(acc));
+  for (int k = 0; k < hps::KIND_COUNT; ++k)
+    std::strncpy(acc[k].name, hps::KIND_NAMES[k], sizeof(acc[k].name) - 1);
+  for (const auto& r : hps::g_recs) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    hps_kernel_stat& s = acc[r.kind];
+    s.launches += 1;
+    s.total_ms += ms;
+    s.flops += r.flops;
+    s.bytes += r.bytes;
+  }
+  int n = 0;
+  for (int k = 0; k < hps::KIND_COUNT && n < max; ++k)
+    if (acc[k].launches > 0 && out) out[n++] = acc[k];
+  hps::g_recs.clear();
+  hps::g_used = 0;
+  return n;
+}
+
+}  // extern "C"

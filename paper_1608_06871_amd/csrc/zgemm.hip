@@ -216,6 +216,9 @@ hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 
   const ll tiles = (ll)((M + TM - 1) / TM) * ((N + TN - 1) / TN);
   if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles, (unsigned)batch);
+  const bool rb = (beta.x != 0.0 || beta.y != 0.0);
+  KernelTimer kt(st, K_ZGEMM, 8.0 * M * N * (double)a.K * batch,
+                 16.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);
   hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }

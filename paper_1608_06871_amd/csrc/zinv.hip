@@ -233,6 +233,7 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
   }
   for (int c0 = 0; c0 < n; c0 += b) {
     const int bw = (n - c0) < b ? (n - c0) : b;
+    KernelTimer kt(st, K_GJ_PANEL, 8.0 * n * (double)bw * bw * batch, 64.0 * n * (double)bw * batch);
     if (in_lds) {
       hipLaunchKernelGGL(gj_panel<true>, dim3(batch), dim3(NT), (size_t)n * bw * sizeof(double2),
                          st, work, lda, sA, n, c0, bw, bmax, ipiv, E, T, info);
@@ -246,9 +247,15 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
                         (ll)n * bmax, make_double2(1.0, 0.0), work, lda, sA, batch));
     }
   }
-  hipLaunchKernelGGL(gj_perm, dim3((batch + 63) / 64), dim3(64), 0, st, ipiv, perm, n, batch);
+  {
+    KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * n * batch);
+    hipLaunchKernelGGL(gj_perm, dim3((batch + 63) / 64), dim3(64), 0, st, ipiv, perm, n, batch);
+  }
   HPS_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(gj_gather, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, perm, n);
+  {
+    KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
+    hipLaunchKernelGGL(gj_gather, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, perm, n);
+  }
   return hipGetLastError();
 }
 
