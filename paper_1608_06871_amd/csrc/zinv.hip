@@ -30,6 +30,35 @@ __device__ inline double2 crecip(double2 a) {
   return make_double2(a.x / d, -a.y / d);
 }
 
+// Arg-max of (value, index) over the workgroup: wave shuffles, then one
+// exchange of the per-wave winners through LDS.  Ties go to the lower index.
+// rv / ri hold NT / 64 entries; the caller synchronises before reusing them.
+__device__ inline int block_argmax(double v, int i, double* rv, int* ri, double* best) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(i, off, 64);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rv[w] = v;
+    ri[w] = i;
+  }
+  __syncthreads();
+  double bv = rv[0];
+  int bi = ri[0];
+  for (int q = 1; q < NT / 64; ++q)
+    if (rv[q] > bv || (rv[q] == bv && ri[q] < bi)) {
+      bv = rv[q];
+      bi = ri[q];
+    }
+  *best = bv;
+  return bi;
+}
+
 template <bool L>
 __device__ inline double2& pel(double2* sm, double2* A, ll lda, int n, int c0, int r, int c) {
   if constexpr (L)
@@ -73,23 +102,9 @@ __global__ __launch_bounds__(NT) void gj_panel(double2* Aall, ll lda, ll sA, int
         bidx = r;
       }
     }
-    rv[t] = best;
-    ri[t] = bidx;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (t < s) {
-        const double o = rv[t + s];
-        const int oi = ri[t + s];
-        if (o > rv[t] || (o == rv[t] && oi < ri[t])) {
-          rv[t] = o;
-          ri[t] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int p = ri[0];
-    const bool zero = !(rv[0] > 0.0);
-    __syncthreads();
+    double bestv;
+    const int p = block_argmax(best, bidx, rv, ri, &bestv);
+    const bool zero = !(bestv > 0.0);
     if (t == 0) {
       ipiv[gc] = p;
       if (zero) info[bi] = 1;
@@ -182,6 +197,271 @@ __global__ __launch_bounds__(NT) void gj_gather(const double2* W, ll lda, ll sA,
   for (int r = threadIdx.x; r < n; r += NT) dst[r] = src[r];
 }
 
+// ---------------------------------------------------------------------------
+// Tournament pivoting for matrices whose panels do not fit in LDS
+// (communication-avoiding LU, Grigori, Demmel and Xiang 2011): the candidate
+// rows [c0, n) are split into chunks of TR rows; each chunk picks b pivot
+// candidates by partial-pivoting elimination of its panel rows; groups of TF
+// candidate sets are reduced the same way until one set of b rows remains.
+// Those rows become the pivot rows of the block step, which is then all
+// matrix products.
+
+constexpr int TR = 256;  // rows per tournament leaf (one per thread)
+constexpr int TF = 4;    // candidate sets merged per reduction workgroup
+
+// Partial-pivoting elimination of an nr x b block in LDS (column-major,
+// leading dimension ld); ids[] follows the row interchanges.  After it the
+// first min(nr, b) entries of ids are the selected rows.
+__device__ void select_rows(double2* blk, int ld, int nr, int b, int* ids, double* rv, int* ri) {
+  const int t = threadIdx.x;
+  const int steps = nr < b ? nr : b;
+  for (int c = 0; c < steps; ++c) {
+    double best = -1.0;
+    int bidx = c;
+    for (int r = c + t; r < nr; r += NT) {
+      const double2 v = blk[r + c * ld];
+      const double m = fabs(v.x) + fabs(v.y);
+      if (m > best) {
+        best = m;
+        bidx = r;
+      }
+    }
+    double bestv;
+    const int p = block_argmax(best, bidx, rv, ri, &bestv);
+    const bool zero = !(bestv > 0.0);
+    __syncthreads();
+    if (p != c) {
+      for (int j = t; j < b; j += NT) {
+        const double2 x = blk[c + j * ld];
+        blk[c + j * ld] = blk[p + j * ld];
+        blk[p + j * ld] = x;
+      }
+      if (t == 0) {
+        const int x = ids[c];
+        ids[c] = ids[p];
+        ids[p] = x;
+      }
+    }
+    __syncthreads();
+    if (!zero) {
+      const double2 inv = crecip(blk[c + c * ld]);
+      for (int r = c + 1 + t; r < nr; r += NT) {
+        const double2 l = cmul(blk[r + c * ld], inv);
+        for (int j = c + 1; j < b; ++j) {
+          const double2 d = cmul(l, blk[c + j * ld]);
+          blk[r + j * ld].x -= d.x;
+          blk[r + j * ld].y -= d.y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Leaves: chunk g of rows [c0, n) selects up to b candidate rows.
+__global__ __launch_bounds__(NT) void tp_leaf(const double2* Aall, ll lda, ll sA, int n, int c0,
+                                              int b, int G, int* cand_all) {
+  extern __shared__ double2 blk[];
+  __shared__ double rv[NT];
+  __shared__ int ri[NT];
+  __shared__ int ids[TR];
+  const ll bi = blockIdx.y;
+  const int g = blockIdx.x, t = threadIdx.x;
+  const double2* A = Aall + bi * sA;
+  const int r0 = c0 + g * TR;
+  const int nr = (n - r0) < TR ? (n - r0) : TR;
+  for (int idx = t; idx < nr * b; idx += NT) {
+    const int r = idx % nr, c = idx / nr;
+    blk[r + c * TR] = A[(ll)(r0 + r) + (ll)(c0 + c) * lda];
+  }
+  for (int r = t; r < TR; r += NT) ids[r] = (r < nr) ? r0 + r : -1;
+  __syncthreads();
+  select_rows(blk, TR, nr, b, ids, rv, ri);
+  int* cand = cand_all + (bi * G + g) * (ll)b;
+  for (int i = t; i < b; i += NT) cand[i] = (i < nr) ? ids[i] : -1;
+}
+
+// Reduction: workgroup g merges candidate sets [TF g, TF g + TF) of Gin
+// (entries -1 mark missing candidates of short chunks).
+__global__ __launch_bounds__(NT) void tp_reduce(const double2* Aall, ll lda, ll sA, int c0, int b,
+                                                int Gin, const int* cin_all, int Gout,
+                                                int* cout_all) {
+  extern __shared__ double2 blk[];
+  __shared__ double rv[NT];
+  __shared__ int ri[NT];
+  __shared__ int ids[TF * BMAX];
+  __shared__ int nsel;
+  const ll bi = blockIdx.y;
+  const int g = blockIdx.x, t = threadIdx.x;
+  const double2* A = Aall + bi * sA;
+  const int* cin = cin_all + bi * (ll)Gin * b;
+  if (t == 0) {
+    int k = 0;
+    for (int s = TF * g; s < TF * g + TF && s < Gin; ++s)
+      for (int i = 0; i < b; ++i)
+        if (cin[(ll)s * b + i] >= 0) ids[k++] = cin[(ll)s * b + i];
+    nsel = k;
+  }
+  __syncthreads();
+  const int nr = nsel;
+  const int ld = TF * BMAX;
+  for (int idx = t; idx < nr * b; idx += NT) {
+    const int r = idx % nr, c = idx / nr;
+    blk[r + c * ld] = A[(ll)ids[r] + (ll)(c0 + c) * lda];
+  }
+  __syncthreads();
+  select_rows(blk, ld, nr, b, ids, rv, ri);
+  int* cout = cout_all + (bi * Gout + g) * (ll)b;
+  for (int i = t; i < b; i += NT) cout[i] = (i < nr) ? ids[i] : -1;
+}
+
+// Plans the interchanges that bring the selected rows (in order) to rows
+// c0..c0+b-1: the sequence of swaps is recorded in ipiv (same convention as
+// the unblocked panel), and their net effect -- a permutation of at most 2b
+// rows -- as (destination, source) pairs for tp_apply.  One workgroup per
+// matrix; dense maps over the rows [c0, n) live in LDS.
+__global__ __launch_bounds__(NT) void tp_plan(int n, int c0, int b, const int* sel_all,
+                                              int* ipiv_all, int* plan_all) {
+  extern __shared__ int maps[];  // row_at[n - c0], pos_of[n - c0]
+  __shared__ int touched[2 * BMAX];
+  const ll bi = blockIdx.x;
+  const int t = threadIdx.x, nr = n - c0;
+  const int* sel = sel_all + bi * b;
+  int* plan = plan_all + bi * (1 + 4 * BMAX);
+  int* row_at = maps;
+  int* pos_of = maps + nr;
+  for (int x = t; x < nr; x += NT) {
+    row_at[x] = x;
+    pos_of[x] = x;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int i = 0; i < b; ++i) {
+      const int want = sel[i] - c0, tgt = i;
+      // always in range: the tournament returns >= b rows of [c0, n)
+      const int s = (want >= 0 && want < nr) ? pos_of[want] : tgt;
+      ipiv_all[bi * n + c0 + tgt] = c0 + s;
+      touched[2 * i] = tgt;
+      touched[2 * i + 1] = s;
+      if (s == tgt) continue;
+      const int rt = row_at[tgt], rs = row_at[s];
+      row_at[tgt] = rs;
+      row_at[s] = rt;
+      pos_of[rs] = tgt;
+      pos_of[rt] = s;
+    }
+    int m = 0;
+    for (int q = 0; q < 2 * b; ++q) {
+      const int x = touched[q];
+      if (row_at[x] != x) {
+        plan[1 + 2 * m] = c0 + x;
+        plan[2 + 2 * m] = c0 + row_at[x];
+        row_at[x] = x;  // emitted
+        ++m;
+      }
+    }
+    plan[0] = m;
+  }
+}
+
+// Applies the planned row permutation to 64 columns per workgroup: all moved
+// rows are read into LDS first, then written to their destinations.
+__global__ __launch_bounds__(NT) void tp_apply(double2* Aall, ll lda, ll sA, int n,
+                                               const int* plan_all) {
+  __shared__ double2 buf[2 * BMAX][64];
+  const ll bi = blockIdx.y;
+  const int t = threadIdx.x;
+  double2* A = Aall + bi * sA;
+  const int* plan = plan_all + bi * (1 + 4 * BMAX);
+  const int m = plan[0];
+  const int j0 = blockIdx.x * 64;
+  for (int idx = t; idx < m * 64; idx += NT) {
+    const int q = idx % m, jj = idx / m;
+    const int j = j0 + jj;
+    if (j < n) buf[q][jj] = A[(ll)plan[2 + 2 * q] + (ll)j * lda];
+  }
+  __syncthreads();
+  for (int idx = t; idx < m * 64; idx += NT) {
+    const int q = idx % m, jj = idx / m;
+    const int j = j0 + jj;
+    if (j < n) A[(ll)plan[1 + 2 * q] + (ll)j * lda] = buf[q][jj];
+  }
+}
+
+// Inverse of the b x b pivot block by Gauss-Jordan elimination without
+// interchanges: the tournament ordered the pivot rows by partial pivoting, so
+// elimination in that order makes the same pivot choices.  BMAX x BMAX
+// threads, one element each (the block padded with the identity); the
+// matrix is exchanged through LDS once per elimination step.
+__global__ __launch_bounds__(BMAX * BMAX) void tp_block(const double2* Aall, ll lda, ll sA, int c0,
+                                                        int b, double2* IB_all, int* info) {
+  __shared__ double2 m[BMAX * BMAX];  // column-major: (r, j) at r + j * BMAX
+  const ll bi = blockIdx.x;
+  const int t = threadIdx.x;
+  const int r = t % BMAX, j = t / BMAX;
+  const double2* A = Aall + bi * sA;
+  double2* IB = IB_all + bi * (ll)BMAX * BMAX;
+  const bool act = (r < b && j < b);
+  double2 v = act ? A[(ll)(c0 + r) + (ll)(c0 + j) * lda] : make_double2((r == j) ? 1.0 : 0.0, 0.0);
+  bool singular = false;
+  for (int c = 0; c < b; ++c) {
+    m[t] = v;
+    __syncthreads();
+    const double2 piv = m[c + c * BMAX], f = m[r + c * BMAX], pc = m[c + j * BMAX];
+    __syncthreads();
+    const bool zero = (piv.x == 0.0 && piv.y == 0.0);
+    singular |= zero;
+    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(piv);
+    if (r == c) {
+      v = (j == c) ? inv : cmul(pc, inv);
+    } else if (j == c) {
+      const double2 nf = cmul(f, inv);
+      v = make_double2(-nf.x, -nf.y);
+    } else {
+      const double2 d = cmul(f, cmul(pc, inv));
+      v.x -= d.x;
+      v.y -= d.y;
+    }
+  }
+  if (act) IB[r + j * b] = v;
+  if (t == 0 && singular) info[bi] = 1;
+}
+
+// T = pivot rows c0.. of A, with the panel columns zeroed (b x n, ld b).
+__global__ __launch_bounds__(NT) void tp_copy_t(const double2* Aall, ll lda, ll sA, int n, int c0,
+                                                int b, int bstride, double2* Tall) {
+  const ll bi = blockIdx.y;
+  const double2* A = Aall + bi * sA;
+  double2* T = Tall + bi * (ll)n * bstride;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < (ll)n * b; idx += (ll)gridDim.x * NT) {
+    const int i = (int)(idx % b);
+    const int j = (int)(idx / b);
+    T[idx] = (j >= c0 && j < c0 + b) ? make_double2(0.0, 0.0) : A[(ll)(c0 + i) + (ll)j * lda];
+  }
+}
+
+// After E = -A[:, panel] IB: pivot rows of E become IB - I, and the panel
+// columns of A take their eliminated values (IB on the pivot rows, E
+// elsewhere).
+__global__ __launch_bounds__(NT) void tp_fix(double2* Aall, ll lda, ll sA, int n, int c0, int b,
+                                             int bstride, const double2* IB_all, double2* Eall) {
+  const ll bi = blockIdx.y;
+  double2* A = Aall + bi * sA;
+  double2* E = Eall + bi * (ll)n * bstride;
+  const double2* IB = IB_all + bi * (ll)BMAX * BMAX;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < (ll)n * b; idx += (ll)gridDim.x * NT) {
+    const int r = (int)(idx % n);
+    const int c = (int)(idx / n);
+    if (r >= c0 && r < c0 + b) {
+      const double2 v = IB[(r - c0) + c * b];
+      A[(ll)r + (ll)(c0 + c) * lda] = v;
+      E[idx] = make_double2(v.x - ((r - c0) == c ? 1.0 : 0.0), v.y);
+    } else {
+      A[(ll)r + (ll)(c0 + c) * lda] = E[idx];
+    }
+  }
+}
+
 int panel_width(int n) { return n < BMAX ? n : BMAX; }
 
 // Dynamic LDS available to one workgroup of the panel kernel (bytes).
@@ -203,12 +483,19 @@ size_t lds_limit() {
 
 }  // namespace
 
+constexpr int TOURNAMENT_MIN_N = 512;
+
+size_t cand_ints(int n, int batch) { return (size_t)batch * ((n + TR - 1) / TR) * BMAX; }
+
 size_t zinv_workspace(int n, int batch) {
   const int b = panel_width(n);
   size_t bytes = 0;
   bytes += (size_t)batch * n * sizeof(int) * 2;         // ipiv + perm
   bytes = (bytes + 255) & ~(size_t)255;
   bytes += (size_t)batch * n * b * sizeof(double2) * 2;  // E + T
+  bytes += (size_t)batch * BMAX * BMAX * sizeof(double2);  // pivot-block inverses
+  bytes += 2 * cand_ints(n, batch) * sizeof(int);          // tournament candidates
+  bytes += (size_t)batch * (1 + 4 * BMAX) * sizeof(int);   // row-permutation plans
   return bytes;
 }
 
@@ -226,6 +513,92 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
   size_t off = ((size_t)batch * n * sizeof(int) * 2 + 255) & ~(size_t)255;
   double2* E = (double2*)((char*)ws + off);
   double2* T = E + (size_t)batch * n * bmax;
+  if (n > TOURNAMENT_MIN_N) {
+    double2* IB = T + (size_t)batch * n * bmax;
+    int* candA = (int*)(IB + (size_t)batch * BMAX * BMAX);
+    int* candB = candA + cand_ints(n, batch);
+    int* plan = candB + cand_ints(n, batch);
+    const int bt = bmax;
+    HPS_HIP_TRY(hipFuncSetAttribute((const void*)tp_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(TR * bt * sizeof(double2))));
+    HPS_HIP_TRY(hipFuncSetAttribute((const void*)tp_reduce,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(TF * BMAX * bt * sizeof(double2))));
+    HPS_HIP_TRY(hipFuncSetAttribute((const void*)tp_plan, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(2 * n * sizeof(int))));
+    const unsigned eblocks = (unsigned)(((ll)n * bt + NT - 1) / NT);
+    for (int c0 = 0; c0 < n; c0 += bt) {
+      const int bw = (n - c0) < bt ? (n - c0) : bt;
+      const int G = (n - c0 + TR - 1) / TR;
+      {
+        KernelTimer kt(st, K_GJ_PANEL, 8.0 * (n - c0) * (double)bw * bw * batch,
+                       16.0 * (n - c0) * (double)bw * batch);
+        hipLaunchKernelGGL(tp_leaf, dim3(G, batch), dim3(NT), TR * bw * sizeof(double2), st, work, lda,
+                           sA, n, c0, bw, G, candA);
+      }
+      HPS_HIP_TRY(hipGetLastError());
+      int* cin = candA;
+      int* cout = candB;
+      int Gin = G;
+      while (Gin > 1) {
+        const int Gout = (Gin + TF - 1) / TF;
+        KernelTimer kt(st, K_GJ_PANEL, 8.0 * Gin * (double)bw * bw * bw * batch,
+                       16.0 * Gin * (double)bw * bw * batch);
+        hipLaunchKernelGGL(tp_reduce, dim3(Gout, batch), dim3(NT), TF * BMAX * bw * sizeof(double2), st,
+                           work, lda, sA, c0, bw, Gin, cin, Gout, cout);
+        HPS_HIP_TRY(hipGetLastError());
+        int* tmp = cin;
+        cin = cout;
+        cout = tmp;
+        Gin = Gout;
+      }
+      {
+        KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * bw * (double)batch);
+        hipLaunchKernelGGL(tp_plan, dim3(batch), dim3(NT), 2 * (n - c0) * sizeof(int), st, n, c0, bw, cin,
+                           ipiv, plan);
+      }
+      HPS_HIP_TRY(hipGetLastError());
+      {
+        KernelTimer kt(st, K_GJ_PERM, 0.0, 64.0 * n * (double)bw * batch);
+        hipLaunchKernelGGL(tp_apply, dim3((n + 63) / 64, batch), dim3(NT), 0, st, work, lda, sA, n, plan);
+      }
+      HPS_HIP_TRY(hipGetLastError());
+      {
+        KernelTimer kt(st, K_GJ_PANEL, 8.0 * bw * (double)bw * bw * batch, 32.0 * bw * (double)bw * batch);
+        hipLaunchKernelGGL(tp_block, dim3(batch), dim3(BMAX * BMAX), 0, st, work, lda, sA, c0, bw, IB,
+                           info);
+      }
+      HPS_HIP_TRY(hipGetLastError());
+      {
+        KernelTimer kt(st, K_MOVE, 0.0, 32.0 * n * (double)bw * batch);
+        hipLaunchKernelGGL(tp_copy_t, dim3(eblocks, batch), dim3(NT), 0, st, work, lda, sA, n, c0, bw, bmax,
+                           T);
+      }
+      HPS_HIP_TRY(hipGetLastError());
+      HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, bw, bw, make_double2(-1.0, 0.0), work + (ll)c0 * lda, lda, sA,
+                        IB, bw, (ll)BMAX * BMAX, make_double2(0.0, 0.0), E, n, (ll)n * bmax, batch));
+      {
+        KernelTimer kt(st, K_MOVE, 0.0, 48.0 * n * (double)bw * batch);
+        hipLaunchKernelGGL(tp_fix, dim3(eblocks, batch), dim3(NT), 0, st, work, lda, sA, n, c0, bw, bmax,
+                           IB, E);
+      }
+      HPS_HIP_TRY(hipGetLastError());
+      if (bw < n) {
+        HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, n, bw, make_double2(1.0, 0.0), E, n, (ll)n * bmax, T, bw,
+                          (ll)n * bmax, make_double2(1.0, 0.0), work, lda, sA, batch));
+      }
+    }
+    {
+      KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * n * batch);
+      hipLaunchKernelGGL(gj_perm, dim3((batch + 63) / 64), dim3(64), 0, st, ipiv, perm, n, batch);
+    }
+    HPS_HIP_TRY(hipGetLastError());
+    {
+      KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
+      hipLaunchKernelGGL(gj_gather, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, perm, n);
+    }
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)n * b * sizeof(double2);
   if (in_lds) {
     HPS_HIP_TRY(hipFuncSetAttribute((const void*)gj_panel<true>,

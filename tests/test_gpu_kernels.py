@@ -61,7 +61,7 @@ def test_zgemm_beta_zero_ignores_nan():
 
 
 @pytest.mark.parametrize("n,batch", [(1, 3), (5, 4), (14, 7), (33, 2), (64, 3), (100, 2), (252, 3),
-                                     (300, 1), (700, 1)])
+                                     (300, 1), (513, 1), (700, 1), (1100, 2)])
 def test_zinv_matches_numpy(n, batch):
     torch = _torch()
     import paper_1608_06871_amd as hps
