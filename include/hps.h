@@ -159,6 +159,25 @@ hps_status hps_sine_eval(hps_ctx* ctx, int S, const double* coef, double* q_node
 /* Transpose of hps_sine_eval: coef = E^T g for g (device, npde doubles). */
 hps_status hps_sine_adjoint(hps_ctx* ctx, int S, const double* g, double* coef);
 
+/* One Gauss-Newton step of the Newton iteration of Section 3.3 on the sine
+ * model (eq. normaleq; real unknowns, so the normal equations are taken in
+ * their real part):
+ *   q = E coef;  factor(q, k);  solve(ndir directions);
+ *   r = data - F[q]  (data: device complex128 [ndir][ntheta], at R, theta);
+ *   solve Re(E^T J^H J E) dc = Re(E^T J^H r) by conjugate gradients from
+ *   dc = 0 (each iteration = one hps_jvp + one hps_vjp over all directions),
+ *   stopping after max_iter iterations or when the CG residual falls to
+ *   tol times its initial norm;
+ *   coef_out = coef + dc.
+ * coef, coef_out: device, S*S doubles (layout of hps_sine_eval).  Host
+ * outputs (may be NULL): CG iterations, final relative CG residual, and the
+ * data misfit ||r|| before the step.  Leaves the context factored and solved
+ * at q = E coef.  Synchronous.  Requires keep_derivs. */
+hps_status hps_gn_step(hps_ctx* ctx, double k, int ndir, const double* dir_angle_host, int ntheta,
+                       const double* theta_host, double R, int S, const double* coef,
+                       const double* data, int max_iter, double tol, double* coef_out,
+                       int* iters_host, double* cg_rel_res_host, double* misfit_host);
+
 typedef struct hps_stats {
   double t_wavenumber_ms; /* last hps_set_wavenumber (host quadrature + upload) */
   double t_factor_ms;     /* last hps_factor, device time between events */
@@ -174,7 +193,15 @@ typedef struct hps_stats {
 /* Timings of the last calls (synchronises the stream) and memory use. */
 hps_status hps_get_stats(hps_ctx* ctx, hps_stats* out);
 
-/* ---- dense building blocks, exposed for testing the kernels ---- */
+/* ---- host-side operators and dense building blocks, exposed for testing ---- */
+
+/* Host-only (no device work): the single- and double-layer matrices S and K
+ * (row-major complex128 [nb][nb], nb = 4 nleaf (p-2)) of hps_set_wavenumber
+ * for the geometry in *opts at wavenumber k, in the library's root order of
+ * the outer-boundary nodes, whose coordinates go to xy_host ([nb][2], may be
+ * NULL). */
+hps_status hps_boundary_operators(const hps_opts* opts, double k, double* xy_host, double* S_host,
+                                  double* K_host);
 
 /* Batched complex GEMM C_b = alpha op(A_b) op(B_b) + beta C_b, b < batch,
  * column-major; op: 0 = none, 1 = transpose, 2 = conjugate transpose.

@@ -66,6 +66,8 @@ SIGNATURES = [
     ("hps_sine_eval", _I, [_P, _I, _P, _P]),
     ("hps_sine_adjoint", _I, [_P, _I, _P, _P]),
     ("hps_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
+    ("hps_gn_step", _I, [_P, _D, _I, _P, _I, _P, _D, _I, _P, _P, _I, _D, _P, _P, _P, _P]),
+    ("hps_boundary_operators", _I, [ctypes.POINTER(Opts), _D, _P, _P, _P]),
     ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
     ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
     ("hps_profile_start", _I, []),
@@ -136,6 +138,7 @@ class Solver:
         self.nb = int(L.hps_num_boundary_nodes(h))
         self.ndir = 0
         self.ntheta = 0
+        self.generation = 0
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -162,11 +165,13 @@ class Solver:
         self._q = q
         self._check(lib().hps_factor(self._h, _dev(q, torch.float64, self.npde, "q"), float(k)), "factor")
         self.k = float(k)
+        self.generation += 1
 
     def solve(self, angles):
         a = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
         self._check(lib().hps_solve(self._h, int(a.size), a.ctypes.data_as(ctypes.c_void_p)), "solve")
         self.ndir = int(a.size)
+        self.generation += 1
 
     def far_field(self, thetas, R, out=None):
         torch = _torch()
@@ -220,10 +225,50 @@ class Solver:
                                            _dev(out, torch.float64, S * S, "coef")), "sine_adjoint")
         return out
 
+    def gn_step(self, k, dirs, thetas, R, coef, data, max_iter=50, tol=1e-12, out=None):
+        """One Gauss-Newton step on the sine model; returns (coef_out, info)."""
+        torch = _torch()
+        a = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).ravel())
+        th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).ravel())
+        S = int(round(np.sqrt(coef.numel())))
+        if out is None:
+            out = torch.empty(S * S, dtype=torch.float64, device="cuda")
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        mis = ctypes.c_double(0.0)
+        self._check(lib().hps_gn_step(self._h, float(k), int(a.size), a.ctypes.data_as(ctypes.c_void_p),
+                                      int(th.size), th.ctypes.data_as(ctypes.c_void_p), float(R), S,
+                                      _dev(coef, torch.float64, S * S, "coef"),
+                                      _dev(data, torch.complex128, a.size * th.size, "data"),
+                                      int(max_iter), float(tol), _dev(out, torch.float64, S * S, "coef_out"),
+                                      ctypes.byref(it), ctypes.byref(rel), ctypes.byref(mis)), "gn_step")
+        self.ndir, self.ntheta, self.k = int(a.size), int(th.size), float(k)
+        self.generation += 1
+        return out, {"cg_iters": it.value, "cg_rel_res": rel.value, "misfit": mis.value}
+
     def stats(self):
         s = Stats()
         self._check(lib().hps_get_stats(self._h, ctypes.byref(s)), "stats")
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+def boundary_operators(nleaf, p, k, box=(-1.0, 1.0, -1.0, 1.0)):
+    """Host-side S, K ([nb, nb] complex128 numpy) and boundary-node
+    coordinates ([nb, 2]) in the library's root order (no GPU needed)."""
+    L = lib()
+    o = Opts()
+    L.hps_default_opts(ctypes.byref(o))
+    o.x0, o.x1, o.y0, o.y1 = map(float, box)
+    o.nleaf, o.p = int(nleaf), int(p)
+    nb = 4 * o.nleaf * (o.p - 2)
+    xy = np.zeros((nb, 2))
+    S = np.zeros((nb, nb), dtype=np.complex128)
+    K = np.zeros((nb, nb), dtype=np.complex128)
+    rc = L.hps_boundary_operators(ctypes.byref(o), float(k), xy.ctypes.data_as(ctypes.c_void_p),
+                                  S.ctypes.data_as(ctypes.c_void_p), K.ctypes.data_as(ctypes.c_void_p))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_boundary_operators")
+    return xy, S, K
 
 
 def zgemm(A, B, C=None, opA=0, opB=0, alpha=1.0, beta=0.0, stream=None):

@@ -128,6 +128,8 @@ struct hps_ctx {
 
   // derivative scratch
   DBuf sB, sST2, sW2;
+  // Gauss-Newton scratch
+  DBuf sGn, sGnZ;
 
   // sine model
   int sine_S = 0;
@@ -658,6 +660,88 @@ void sine_adjoint(hps_ctx* c, int S, const double* gv, double* coef) {
   CK(complex_real_part(st, c->sS3.z(), (ll)S * S, coef));
 }
 
+// One Gauss-Newton step on the sine model (Section 3.3, eq. normaleq, with
+// conjugate gradients on the normal equations in place of LSQR).
+struct GnResult {
+  int iters;
+  double cg_rel_res;
+  double misfit;
+};
+
+GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const double* th, double R,
+                 int S, const double* coef, const double* data, int max_iter, double tol,
+                 double* coef_out) {
+  require(c->o.keep_derivs != 0, HPS_ESTATE, "context created without keep_derivs");
+  require(S >= 1 && coef && data && coef_out && max_iter >= 0 && tol >= 0.0, HPS_EINVAL,
+          "bad Gauss-Newton arguments");
+  const ll npde = (ll)c->g.nleaf * c->g.mi, ns = (ll)S * S, nd = (ll)M * nt;
+  hipStream_t st = c->st;
+  // work vectors: q | g | x r p Ap | partial(256) | scalars(4)
+  c->sGn.ensure(sizeof(double) * (2 * npde + 4 * ns + 256 + 4));
+  c->sGnZ.ensure(zb(2 * nd));
+  double* q = c->sGn.d();
+  double* gv = q + npde;
+  double* x = gv + npde;
+  double* r = x + ns;
+  double* pv = r + ns;
+  double* Ap = pv + ns;
+  double* partial = Ap + ns;
+  double* sc = partial + 256;
+  double2* res = c->sGnZ.z();
+  double2* jv = res + nd;
+  auto dotv = [&](const double* a, const double* b) {
+    double h = 0.0;
+    CK(dot(st, a, b, ns, partial, sc));
+    CK(hipMemcpyAsync(&h, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    return h;
+  };
+  sine_eval(c, S, coef, q);
+  factor(c, q, k);
+  solve(c, M, ang);
+  far_field(c, nt, th, R, (double*)jv);
+  CK(zsub(st, (const double2*)data, jv, res, nd));
+  // misfit ||data - F[q]||
+  double misfit = 0.0;
+  {
+    CK(dot(st, (const double*)res, (const double*)res, 2 * nd, partial, sc));
+    CK(hipMemcpyAsync(&misfit, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    misfit = std::sqrt(misfit);
+  }
+  // b = E^T Re(J^H res)
+  vjp(c, (const double*)res, gv);
+  sine_adjoint(c, S, gv, r);
+  CK(hipMemsetAsync(x, 0, sizeof(double) * ns, st));
+  CK(hipMemcpyAsync(pv, r, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
+  double rr = dotv(r, r);
+  const double bnorm = std::sqrt(rr);
+  int it = 0;
+  double rel = bnorm > 0.0 ? 1.0 : 0.0;
+  while (it < max_iter && rel > tol) {
+    // Ap = E^T Re(J^H J E p)
+    sine_eval(c, S, pv, q);
+    jvp(c, q, (double*)jv);
+    vjp(c, (const double*)jv, gv);
+    sine_adjoint(c, S, gv, Ap);
+    const double pAp = dotv(pv, Ap);
+    if (!(pAp > 0.0)) break;
+    const double alpha = rr / pAp;
+    CK(axpby(st, alpha, pv, 1.0, x, ns));
+    CK(axpby(st, -alpha, Ap, 1.0, r, ns));
+    const double rr_new = dotv(r, r);
+    ++it;
+    rel = std::sqrt(rr_new) / bnorm;
+    if (rel <= tol) break;
+    CK(axpby(st, 1.0, r, rr_new / rr, pv, ns));
+    rr = rr_new;
+  }
+  CK(hipMemcpyAsync(coef_out, coef, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
+  CK(axpby(st, 1.0, x, 1.0, coef_out, ns));
+  CK(hipStreamSynchronize(st));
+  return GnResult{it, rel, misfit};
+}
+
 int64_t device_bytes(const hps_ctx* c) {
   int64_t s = 0;
   const DBuf* bufs[] = {&c->dA0, &c->dMout, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dY, &c->dH,
@@ -665,7 +749,7 @@ int64_t device_bytes(const hps_ctx* c) {
                         &c->sBlk, &c->sW, &c->sWinv, &c->sQ, &c->sVin, &c->sV, &c->sTmp, &c->sInfo,
                         &c->d_dirs, &c->dG, &c->dRhs, &c->dF0, &c->dF1, &c->dF3, &c->du0, &c->dST,
                         &c->dg, &c->dPhi, &c->sB, &c->sST2, &c->sW2, &c->dSx, &c->dSy,
-                        &c->dNodeGrid, &c->sS1, &c->sS2, &c->sS3};
+                        &c->dNodeGrid, &c->sS1, &c->sS2, &c->sS3, &c->sGn, &c->sGnZ};
   for (const DBuf* b : bufs) s += (int64_t)b->bytes;
   for (const auto& b : c->didx) s += (int64_t)b.bytes;
   for (const auto& b : c->dD) s += (int64_t)b.bytes;
@@ -804,6 +888,20 @@ hps_status hps_sine_adjoint(hps_ctx* c, int S, const double* g, double* coef) {
   return guard(c, [&] { sine_adjoint(c, S, g, coef); });
 }
 
+hps_status hps_gn_step(hps_ctx* c, double k, int ndir, const double* dir_angle_host, int ntheta,
+                       const double* theta_host, double R, int S, const double* coef,
+                       const double* data, int max_iter, double tol, double* coef_out,
+                       int* iters_host, double* cg_rel_res_host, double* misfit_host) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] {
+    const GnResult g = gn_step(c, k, ndir, dir_angle_host, ntheta, theta_host, R, S, coef, data,
+                               max_iter, tol, coef_out);
+    if (iters_host) *iters_host = g.iters;
+    if (cg_rel_res_host) *cg_rel_res_host = g.cg_rel_res;
+    if (misfit_host) *misfit_host = g.misfit;
+  });
+}
+
 hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
   if (!c || !out) return HPS_EINVAL;
   return guard(c, [&] {
@@ -819,6 +917,34 @@ hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
     out->ndir = c->ndir;
     out->singular = c->singular;
   });
+}
+
+hps_status hps_boundary_operators(const hps_opts* opts, double k, double* xy_host, double* S_host,
+                                  double* K_host) {
+  if (!opts || !(k > 0.0) || !S_host || !K_host) return HPS_EINVAL;
+  try {
+    Geometry g;
+    g.build(opts->x0, opts->x1, opts->y0, opts->nleaf, opts->p);
+    const int nb = (int)g.root.size();
+    std::vector<double> tx(nb), ty(nb);
+    for (int i = 0; i < nb; ++i) {
+      tx[i] = g.root[i].x;
+      ty[i] = g.root[i].y;
+      if (xy_host) {
+        xy_host[2 * i] = tx[i];
+        xy_host[2 * i + 1] = ty[i];
+      }
+    }
+    std::vector<cplx> S, K;
+    unsigned hw = std::thread::hardware_concurrency();
+    const int nth = opts->host_threads > 0 ? opts->host_threads : (int)std::min(16u, std::max(1u, hw));
+    layer_moments(g, k, tx, ty, S, K, nth);
+    std::memcpy(S_host, S.data(), S.size() * sizeof(cplx));
+    std::memcpy(K_host, K.data(), K.size() * sizeof(cplx));
+  } catch (...) {
+    return HPS_EINVAL;
+  }
+  return HPS_OK;
 }
 
 hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const double* alpha,

@@ -31,5 +31,11 @@ hipError_t export_field(hipStream_t st, const double2* u0, int mi, int ndir, ll 
                         double2* out);
 hipError_t real_to_complex(hipStream_t st, const double* x, ll n, double2* y);
 hipError_t complex_real_part(hipStream_t st, const double2* x, ll n, double* y);
+// *out = sum x[i] y[i] (deterministic two-stage reduction; partial holds 256 doubles).
+hipError_t dot(hipStream_t st, const double* x, const double* y, ll n, double* partial, double* out);
+// y = a x + b y
+hipError_t axpby(hipStream_t st, double a, const double* x, double b, double* y, ll n);
+// z = x - y (complex)
+hipError_t zsub(hipStream_t st, const double2* x, const double2* y, double2* z, ll n);
 
 }  // namespace hps

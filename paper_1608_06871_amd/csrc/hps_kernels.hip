@@ -178,7 +178,70 @@ __global__ void k_complex_real_part(const double2* x, ll n, double* y) {
     y[idx] = x[idx].x;
 }
 
+// partial[block] = sum of x[i] y[i] over the block's grid-stride share
+__global__ void k_dot_partial(const double* x, const double* y, ll n, double* partial) {
+  __shared__ double sh[NT];
+  double acc = 0.0;
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT) acc += x[i] * y[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_partials(const double* partial, int nb, double* out) {
+  __shared__ double sh[NT];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// y = a x + b y
+__global__ void k_axpby(double a, const double* x, double b, double* y, ll n) {
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT) y[i] = a * x[i] + b * y[i];
+}
+
+// z = x - y (complex)
+__global__ void k_zsub(const double2* x, const double2* y, double2* z, ll n) {
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT)
+    z[i] = make_double2(x[i].x - y[i].x, x[i].y - y[i].y);
+}
+
 }  // namespace
+
+constexpr int DOT_BLOCKS = 256;
+
+hipError_t dot(hipStream_t st, const double* x, const double* y, ll n, double* partial, double* out) {
+  {
+    KernelTimer kt(st, K_POINT, 2.0 * n, 16.0 * n);
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(NT), 0, st, x, y, n, partial);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  KernelTimer kt(st, K_POINT, (double)DOT_BLOCKS, 8.0 * DOT_BLOCKS);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(NT), 0, st, partial, DOT_BLOCKS, out);
+  return hipGetLastError();
+}
+
+hipError_t axpby(hipStream_t st, double a, const double* x, double b, double* y, ll n) {
+  KernelTimer kt(st, K_POINT, 3.0 * n, 24.0 * n);
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(NT), 0, st, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t zsub(hipStream_t st, const double2* x, const double2* y, double2* z, ll n) {
+  KernelTimer kt(st, K_POINT, 2.0 * n, 48.0 * n);
+  hipLaunchKernelGGL(k_zsub, dim3(blocks_for(n)), dim3(NT), 0, st, x, y, z, n);
+  return hipGetLastError();
+}
 
 hipError_t leaf_assemble(hipStream_t st, const double2* A0, const double* q, double k2, int n,
                          int mi, double2* out, ll nleaf) {

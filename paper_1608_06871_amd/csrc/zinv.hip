@@ -6,10 +6,14 @@
 //      columns in place: pivot search over the rows not yet used, a full-row
 //      swap, and the in-place inverse update of the panel columns, which
 //      leaves inv(A_PP) in the pivot rows and -A_QP inv(A_PP) in the others.
-//      It then emits E = panel - [0; I; 0] and T = pivot rows with the panel
+//      It then emits E = that panel and T = the pivot rows with the panel
 //      columns zeroed;
-//   2. the rank-b update A += E T on all other columns is one batched
-//      complex GEMM on the matrix cores.
+//   2. the other columns are updated by batched complex GEMMs on the matrix
+//      cores: A_Q += E_Q T for the non-pivot rows (two row ranges) and
+//      A_P = inv(A_PP) T on the non-panel columns of the pivot rows (two
+//      column ranges, overwriting).  The pivot rows are never formed as
+//      A_P + (inv - I) A_P, which would cancel catastrophically when the
+//      pivots are large.
 // The row interchanges turn into a column permutation of the result, applied
 // out of place at the end.  Panels of matrices up to ~300 rows live in LDS;
 // larger ones are updated in global memory.
@@ -158,9 +162,7 @@ __global__ __launch_bounds__(NT) void gj_panel(double2* Aall, ll lda, ll sA, int
   }
   for (int idx = t; idx < n * b; idx += NT) {
     const int r = idx % n, c = idx / n;
-    double2 v = pel<L>(sm, A, lda, n, c0, r, c);
-    if (r == c0 + c) v.x -= 1.0;
-    E[idx] = v;
+    E[idx] = pel<L>(sm, A, lda, n, c0, r, c);
   }
   __syncthreads();
   for (int idx = t; idx < n * b; idx += NT) {
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(NT) void tp_copy_t(const double2* Aall, ll lda, ll 
   }
 }
 
-// After E = -A[:, panel] IB: pivot rows of E become IB - I, and the panel
+// After E = -A[:, panel] IB: the pivot rows of E become IB, and the panel
 // columns of A take their eliminated values (IB on the pivot rows, E
 // elsewhere).
 __global__ __launch_bounds__(NT) void tp_fix(double2* Aall, ll lda, ll sA, int n, int c0, int b,
@@ -455,7 +457,7 @@ __global__ __launch_bounds__(NT) void tp_fix(double2* Aall, ll lda, ll sA, int n
     if (r >= c0 && r < c0 + b) {
       const double2 v = IB[(r - c0) + c * b];
       A[(ll)r + (ll)(c0 + c) * lda] = v;
-      E[idx] = make_double2(v.x - ((r - c0) == c ? 1.0 : 0.0), v.y);
+      E[idx] = v;
     } else {
       A[(ll)r + (ll)(c0 + c) * lda] = E[idx];
     }
@@ -479,6 +481,26 @@ size_t lds_limit() {
     cached = lim < LDS_BUDGET ? lim : LDS_BUDGET;
   }
   return cached;
+}
+
+// Applies the eliminations of panel [c0, c0 + bw) to the other columns (see
+// the file comment): rows outside the panel accumulate E_Q T, the pivot rows
+// are overwritten by inv(A_PP) T outside the panel columns.
+hipError_t apply_panel(hipStream_t st, int n, int c0, int bw, int bmax, double2* work, ll lda, ll sA,
+                       const double2* E, const double2* T, int batch) {
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  const ll se = (ll)n * bmax;
+  const int c1 = c0 + bw;
+  // non-pivot rows [0, c0) and [c1, n), all columns (T is zero on the panel)
+  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, c0, n, bw, one, E, n, se, T, bw, se, one, work, lda, sA, batch));
+  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n - c1, n, bw, one, E + c1, n, se, T, bw, se, one, work + c1, lda,
+                    sA, batch));
+  // pivot rows, columns [0, c0) and [c1, n)
+  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, bw, c0, bw, one, E + c0, n, se, T, bw, se, zero, work + c0, lda, sA,
+                    batch));
+  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, bw, n - c1, bw, one, E + c0, n, se, T + (ll)c1 * bw, bw, se, zero,
+                    work + c0 + (ll)c1 * lda, lda, sA, batch));
+  return hipSuccess;
 }
 
 }  // namespace
@@ -583,10 +605,7 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
                            IB, E);
       }
       HPS_HIP_TRY(hipGetLastError());
-      if (bw < n) {
-        HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, n, bw, make_double2(1.0, 0.0), E, n, (ll)n * bmax, T, bw,
-                          (ll)n * bmax, make_double2(1.0, 0.0), work, lda, sA, batch));
-      }
+      if (bw < n) HPS_HIP_TRY(apply_panel(st, n, c0, bw, bmax, work, lda, sA, E, T, batch));
     }
     {
       KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * n * batch);
@@ -615,10 +634,7 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
                          bmax, ipiv, E, T, info);
     }
     HPS_HIP_TRY(hipGetLastError());
-    if (bw < n) {
-      HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, n, bw, make_double2(1.0, 0.0), E, n, (ll)n * bmax, T, bw,
-                        (ll)n * bmax, make_double2(1.0, 0.0), work, lda, sA, batch));
-    }
+    if (bw < n) HPS_HIP_TRY(apply_panel(st, n, c0, bw, bmax, work, lda, sA, E, T, batch));
   }
   {
     KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * n * batch);

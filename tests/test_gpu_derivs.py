@@ -1,0 +1,163 @@
+"""GPU checks of the derivative path: the autograd wrapper (gradcheck, and
+its gradient vs the oracle's adjoint), central finite differences and the
+adjoint identity at the differentiation workload's size (k = 70, 140 x 140
+sine modes, 32 x 32 leaves, 128 directions x 256 angles), and the
+Gauss-Newton step / recursive linearization against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import gn as ogn
+from oracle import sine as osine
+from oracle.bie import circle_points
+from oracle.forward import Problem, directions
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_autograd_gradcheck_tiny():
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    from paper_1608_06871_amd.autograd import far_field
+    s = hps.Solver(nleaf=1, p=8)
+    xy = s.node_coords()
+    q = torch.from_numpy(synth.gaussian_bumps(xy, 2, 5)).cuda().requires_grad_(True)
+    dirs, th = directions(2), circle_points(2.0, 4)[1]
+    assert torch.autograd.gradcheck(lambda qq: far_field(qq, s, 3.0, dirs, th, 2.0), (q,),
+                                    eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+def test_autograd_gradient_matches_oracle():
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    from paper_1608_06871_amd.autograd import far_field
+    L, k, M, P = 2, 5.0, 4, 16
+    prob = Problem(L, k)
+    xy = prob.grid.pde_coords()
+    qn = synth.gaussian_bumps(xy, 5, 3)
+    prob.factor(qn)
+    prob.solve(directions(M))
+    th = circle_points(2.0, P)[1]
+    prob.set_measurement(th, 2.0)
+    rng = np.random.default_rng(4)
+    d = rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))
+    # loss = sum |u - d|^2: dL/dq = Re(J^H 2 (u - d))
+    ref = prob.vjp(2.0 * (prob.far_field() - d))
+    s = hps.Solver(nleaf=L, p=16)
+    q = torch.from_numpy(qn).cuda().requires_grad_(True)
+    u = far_field(q, s, k, directions(M), th, 2.0)
+    loss = torch.sum(torch.abs(u - torch.from_numpy(d).cuda()) ** 2)
+    loss.backward()
+    g = q.grad.cpu().numpy()
+    assert np.max(np.abs(g - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    k, L, S, M, P = 70.0, 32, 140, 128, 256
+    s = hps.Solver(nleaf=L, p=16)
+    s.set_wavenumber(k)
+    c = synth.sine_coefficients(S, 4)
+    # rescale so that max q <= 0.5 at the nodes
+    q = osine.evaluate(s.node_coords(), c)
+    c *= 0.5 / np.max(np.abs(q))
+    return s, torch.from_numpy(c.ravel()).cuda(), (k, S, synth.equispaced_angles(M), synth.equispaced_angles(P))
+
+
+def _F(s, coef, k, dirs, th):
+    q = s.sine_eval(coef)
+    s.factor(q, k)
+    s.solve(dirs)
+    return s.far_field(th, 2.0).clone()
+
+
+def test_differentiation_workload_fd_and_adjoint(cfg4):
+    torch = _torch()
+    s, c, (k, S, dirs, th) = cfg4
+    print("k=70, 32x32 leaves, 19600 sine coefficients, 128 x 256", flush=True)
+    rng = np.random.default_rng(8)
+    h = 1e-6
+    base = _F(s, c, k, dirs, th)
+    worst = 0.0
+    for trial in range(8):
+        v = rng.standard_normal(S * S)
+        v /= np.linalg.norm(v)
+        vt = torch.from_numpy(v).cuda()
+        _F(s, c, k, dirs, th)
+        jv = s.jvp(s.sine_eval(vt)).cpu().numpy()
+        fd = ((_F(s, c + h * vt, k, dirs, th) - _F(s, c - h * vt, k, dirs, th)) / (2 * h)).cpu().numpy()
+        worst = max(worst, np.max(np.abs(fd - jv)) / np.max(np.abs(jv)))
+    print(f"worst FD relative error {worst:.2e}", flush=True)
+    assert worst < 1e-5
+    # adjoint identity through the sine model
+    _F(s, c, k, dirs, th)
+    v = torch.from_numpy(rng.standard_normal(S * S)).cuda()
+    r = torch.from_numpy(rng.standard_normal((len(dirs), len(th))) + 1j * rng.standard_normal((len(dirs), len(th)))).cuda()
+    jv = s.jvp(s.sine_eval(v))
+    lhs = torch.real(torch.vdot(r.ravel(), jv.ravel())).item()
+    rhs = torch.dot(v, s.sine_adjoint(s.vjp(r), S)).item()
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    assert torch.allclose(base, _F(s, c, k, dirs, th), rtol=0, atol=0)  # deterministic
+
+
+def test_gn_step_matches_oracle():
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    L, k, M, P, S = 4, 4.0, 8, 16, 4
+    prob = Problem(L, k)
+    xy = prob.grid.pde_coords()
+    _, th = circle_points(2.0, P)
+    prob.set_measurement(th, 2.0)
+    prob.factor(synth.gaussian_bumps(xy, 5, 2))
+    prob.solve(directions(M))
+    data = np.ascontiguousarray(prob.far_field())
+    rng = np.random.default_rng(6)
+    C0 = 0.05 * rng.standard_normal((S, S))
+    C1, r0, Jc, _ = ogn.gauss_newton_step(L, k, C0, data, directions(M), P, 2.0)
+    s = hps.Solver(nleaf=L, p=16)
+    out, info = s.gn_step(k, directions(M), th, 2.0, torch.from_numpy(C0.ravel()).cuda(),
+                          torch.from_numpy(data).cuda(), max_iter=200, tol=1e-14)
+    assert abs(info["misfit"] - np.linalg.norm(r0)) < 1e-9 * np.linalg.norm(r0)
+    got = out.cpu().numpy().reshape(S, S)
+    assert np.max(np.abs(got - C1)) < 1e-9 * np.max(np.abs(C1 - C0))
+
+
+def test_recursive_linearization_small_matches_oracle():
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    from paper_1608_06871_amd.drivers import recursive_linearization
+    L, M, P = 4, 32, 64
+    ks = [1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0, 9.0, 10.0]
+    bands = [int(k) for k in ks]
+    dirs = directions(M)
+    _, th = circle_points(2.0, P)
+    from oracle.grid import Grid
+    qtrue = synth.gaussian_bumps(Grid(L).pde_coords(), 5, 2)
+    data, ref = [], []
+    C = np.zeros((0, 0))
+    for k, S in zip(ks, bands):
+        prob = Problem(L, k)
+        prob.set_measurement(th, 2.0)
+        prob.factor(qtrue)
+        prob.solve(dirs)
+        d = np.ascontiguousarray(prob.far_field())
+        data.append(d)
+        Cn = np.zeros((S, S))
+        Cn[:C.shape[0], :C.shape[1]] = C
+        C, _, _, _ = ogn.gauss_newton_step(L, k, Cn, d, dirs, P, 2.0)
+        ref.append(C.copy())
+    s = hps.Solver(nleaf=L, p=16)
+    coef, log = recursive_linearization(s, ks, bands, [torch.from_numpy(d).cuda() for d in data], dirs, th,
+                                        2.0, max_iter=300, tol=1e-14)
+    got = coef.cpu().numpy().reshape(bands[-1], bands[-1])
+    print("misfits per k:", [f"{e['misfit']:.3e}" for e in log], flush=True)
+    assert np.max(np.abs(got - ref[-1])) < 1e-8 * np.max(np.abs(ref[-1]))

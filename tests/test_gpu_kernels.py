@@ -87,3 +87,22 @@ def test_zinv_reports_singular():
     with pytest.raises(hps.HpsError) as e:
         hps.zinv(_colmajor(torch, A))
     assert e.value.code == hps.HPS_ESINGULAR
+
+
+@pytest.mark.parametrize("n", [252, 700])
+def test_zinv_row_scaled_keeps_accuracy(n):
+    """Rows scaled by 1e6 (like the PDE rows of a small leaf next to its
+    impedance rows): the inverse keeps the accuracy of the unscaled matrix
+    (row scaling only rescales the columns of the inverse)."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    rng = np.random.default_rng(n)
+    B = _rand(rng, (1, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    d = np.where(np.arange(n) % 2 == 0, 1e6, 1.0)
+    A = d[None, :, None] * B
+    inv = _back(hps.zinv(_colmajor(torch, A)))[0]
+    ref = np.linalg.inv(B[0]) / d[None, :]
+    cond = np.linalg.cond(B[0])
+    # compare column by column relative to each column's scale
+    err = np.max(np.abs(inv - ref), axis=0) / np.max(np.abs(ref), axis=0)
+    assert np.max(err) < 1e-13 * cond
