@@ -12,8 +12,9 @@ of kernel x Lagrange basis over the panel,
 and the same integrals with the target on the measurement circle give the
 far-field (finite-R) matrices.  The integrals are computed by composite
 Gauss-Legendre quadrature on panel pieces refined dyadically until each piece
-is no longer than its distance to the target (graded towards the target for
-the weakly singular self-panel integrals).
+is no longer than its distance to the target and short on the wavelength
+scale (k * length <= 4), graded towards the target for the weakly singular
+self-panel integrals.
 
 Pinned by tests/test_oracle_bie.py: exterior Calderon identity and Green's
 representation for an interior point source, interior Calderon identity for
@@ -52,10 +53,11 @@ def _lagrange_rows(nodes, w, tau):
     return c / c.sum(axis=1, keepdims=True)
 
 
-def _pieces(x, A, B):
+def _pieces(x, A, B, k):
     """Dyadic pieces [a, b] of the parameter interval [-1, 1] of panel A -> B,
-    each no longer than its distance to x (pieces that touch x are split
-    until shorter than a tiny length and then dropped)."""
+    each no longer than its distance to x and with kernel phase k * length
+    at most 4 (pieces that touch x are split until shorter than a tiny
+    length and then dropped)."""
     ax, ay = float(A[0]), float(A[1])
     vx, vy = float(B[0]) - ax, float(B[1]) - ay
     L2 = vx * vx + vy * vy
@@ -71,7 +73,7 @@ def _pieces(x, A, B):
         along = 0.0 if s0 <= sx <= s1 else min(abs(sx - s0), abs(sx - s1)) * 2 * half
         d = math.hypot(along, perp)
         length = (b - a) * half
-        if d >= length:
+        if d >= length and k * length <= 4.0:
             out.append((a, b))
         elif d == 0.0 and length < _MIN_LEN:
             continue
@@ -85,7 +87,7 @@ def _pieces(x, A, B):
 def panel_moments(k, x, A, B, n, nodes):
     """Integrals over one panel of kernel(x, y) * ell_j(y) for all basis
     functions j: returns (S moments, D moments)."""
-    pieces, half = _pieces(x, A, B)
+    pieces, half = _pieces(x, A, B, k)
     a = np.array([p[0] for p in pieces])
     b = np.array([p[1] for p in pieces])
     tau = (0.5 * (a + b))[:, None] + (0.5 * (b - a))[:, None] * _GX[None, :]
@@ -117,7 +119,7 @@ def _moments_all_panels(k, x, A, B, N, nodes, lag_far):
     c = A + s[:, None] * v
     dist = np.hypot(x[0] - c[:, 0], x[1] - c[:, 1])
     length = np.sqrt(L2)
-    far = dist >= length
+    far = (dist >= length) & (k * length <= 4.0)
     nloc = nodes.size
     MS = np.zeros((len(A), nloc), dtype=np.complex128)
     MD = np.zeros_like(MS)

@@ -134,7 +134,8 @@ inline void lagrange(const Quad& Q, double tau, double* out) {
 }
 
 // Accumulates moments over the parameter piece [a, b] of panel P, refining
-// until each piece is no longer than 4/3 of its distance to the target.
+// until each piece is no longer than 4/3 of its distance to the target and
+// short on the wavelength scale.
 void piece(const Quad& Q, const Panel& P, double x, double y, double a, double b, int depth,
            cplx* mS, cplx* mD) {
   const double vx = P.bx - P.ax, vy = P.by - P.ay;
@@ -146,7 +147,10 @@ void piece(const Quad& Q, const Panel& P, double x, double y, double a, double b
   const double tc = std::min(std::max(tp, a), b);
   const double cx = P.ax + vx * 0.5 * (1.0 + tc), cy = P.ay + vy * 0.5 * (1.0 + tc);
   const double d = std::hypot(x - cx, y - cy);
-  if (d >= 0.75 * len || depth > 200) {
+  // accept a piece when it is no longer than 4/3 of its distance to the
+  // target and the kernel's phase k * len across it is at most 4 (a 16-point
+  // rule then resolves the oscillation of the Hankel functions)
+  if ((d >= 0.75 * len && Q.k * len <= 4.0) || depth > 200) {
     const double half = 0.5 * (b - a), mid = 0.5 * (a + b);
     double lag[64];
     for (size_t g = 0; g < Q.gx.size(); ++g) {
