@@ -1,14 +1,19 @@
 // Batched complex FP64 GEMM on CDNA4 matrix cores.
 //
-// Complex products are done as real split products on the FP64 MFMA
-// (v_mfma_f64_16x16x4f64): Re += ar*br - ai*bi, Im += ar*bi + ai*br.
-// A 256-thread workgroup (4 wave64s) owns a 64 x 64 tile of C; each wave
-// owns a 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16.  The K loop steps
-// by 16: the A (64 x 16) and B (16 x 64) tiles are loaded from HBM with
-// coalesced 16-byte accesses, split into real/imaginary planes in LDS, and
-// the next tile is prefetched into registers while the current one is
-// multiplied.  Operands may be used as stored (N), transposed (T) or
-// conjugate-transposed (C); all shapes are bounds-checked (zero fill).
+// Complex products run on the FP64 MFMA (v_mfma_f64_16x16x4f64) as real
+// products on split real/imaginary planes, with the 3M method
+// (Re = ArBr - AiBi, Im = (Ar + Ai)(Br + Bi) - ArBr - AiBi: three matrix-core
+// operations per complex multiply-add, the sums formed in registers from the
+// LDS planes; Higham analyses its accuracy) or the four direct products.
+// A 256-thread workgroup (4 wave64s, 2 x 2) owns a (32 WM) x (32 WN) tile of
+// C; each wave owns (16 WM) x (16 WN) as WM x WN MFMA blocks of 16 x 16.  The
+// K loop steps by 16: the A and B tiles are loaded from HBM with coalesced
+// 16-byte accesses into real/imaginary planes in LDS, and the next tile is
+// prefetched into registers while the current one is multiplied.  Operands
+// may be used as stored (N), transposed (T) or conjugate-transposed (C); all
+// shapes are bounds-checked (zero fill).  The tile shape is chosen per call.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace hps {
@@ -16,10 +21,8 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 64;
-constexpr int TN = 64;
-constexpr int TK = 16;
 constexpr int PAD = 1;
+constexpr int NT = 256;
 
 struct Args {
   int M, N, K, opA, opB;
@@ -38,86 +41,46 @@ __device__ inline double2 ld_op(const double2* p, bool conj) {
   return v;
 }
 
-// Loads this thread's 4 elements of the A tile (rows m0.., cols k0..).
-__device__ inline void load_a(const Args& a, const double2* A, int m0, int k0, int t,
-                              double2 r[4]) {
-  if (a.opA == OP_N) {
-    const int m = m0 + (t & 63);
+// Loads / stores of a TR x TK tile of a matrix X viewed as rows x K: A as
+// op(A) (M x K), B through the transpose of op(B) (N x K).  `contig` means
+// consecutive rows are adjacent in memory, so threads run along the rows.
+template <int TR, int TK>
+struct TileIO {
+  static constexpr int PER = TR * TK / NT;
+  __device__ static void load(const double2* X, ll ld, int nrow, int ncol, int r0, int k0, bool contig,
+                              bool conj, int t, double2* reg) {
+    if (contig) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + (t >> 6) + 4 * j;
-      r[j] = (m < a.M && k < a.K) ? A[(ll)m + (ll)k * a.lda] : make_double2(0.0, 0.0);
-    }
-  } else {
-    const int k = k0 + (t & 15);
-    const bool cj = a.opA == OP_C;
+      for (int j = 0; j < PER; ++j) {
+        const int idx = t + j * NT;
+        const int r = r0 + idx % TR, k = k0 + idx / TR;
+        reg[j] = (r < nrow && k < ncol) ? ld_op(X + (ll)r + (ll)k * ld, conj) : make_double2(0.0, 0.0);
+      }
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = m0 + (t >> 4) + 16 * j;
-      r[j] = (m < a.M && k < a.K) ? ld_op(A + (ll)k + (ll)m * a.lda, cj) : make_double2(0.0, 0.0);
-    }
-  }
-}
-
-__device__ inline void store_a(const Args& a, double (*Are)[TM + PAD], double (*Aim)[TM + PAD],
-                               int t, const double2 r[4]) {
-  if (a.opA == OP_N) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int kk = (t >> 6) + 4 * j, mm = t & 63;
-      Are[kk][mm] = r[j].x;
-      Aim[kk][mm] = r[j].y;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int kk = t & 15, mm = (t >> 4) + 16 * j;
-      Are[kk][mm] = r[j].x;
-      Aim[kk][mm] = r[j].y;
+      for (int j = 0; j < PER; ++j) {
+        const int idx = t + j * NT;
+        const int k = k0 + idx % TK, r = r0 + idx / TK;
+        reg[j] = (r < nrow && k < ncol) ? ld_op(X + (ll)k + (ll)r * ld, conj) : make_double2(0.0, 0.0);
+      }
     }
   }
-}
-
-__device__ inline void load_b(const Args& a, const double2* B, int n0, int k0, int t,
-                              double2 r[4]) {
-  if (a.opB == OP_N) {
-    const int k = k0 + (t & 15);
+  __device__ static void store(double (*re)[TR + PAD], double (*im)[TR + PAD], bool contig, int t,
+                               const double2* reg) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + (t >> 4) + 16 * j;
-      r[j] = (n < a.N && k < a.K) ? B[(ll)k + (ll)n * a.ldb] : make_double2(0.0, 0.0);
-    }
-  } else {
-    const int n = n0 + (t & 63);
-    const bool cj = a.opB == OP_C;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + (t >> 6) + 4 * j;
-      r[j] = (n < a.N && k < a.K) ? ld_op(B + (ll)n + (ll)k * a.ldb, cj) : make_double2(0.0, 0.0);
+    for (int j = 0; j < PER; ++j) {
+      const int idx = t + j * NT;
+      const int r = contig ? idx % TR : idx / TK;
+      const int k = contig ? idx / TR : idx % TK;
+      re[k][r] = reg[j].x;
+      im[k][r] = reg[j].y;
     }
   }
-}
+};
 
-__device__ inline void store_b(const Args& a, double (*Bre)[TN + PAD], double (*Bim)[TN + PAD],
-                               int t, const double2 r[4]) {
-  if (a.opB == OP_N) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int kk = t & 15, nn = (t >> 4) + 16 * j;
-      Bre[kk][nn] = r[j].x;
-      Bim[kk][nn] = r[j].y;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int kk = (t >> 6) + 4 * j, nn = t & 63;
-      Bre[kk][nn] = r[j].x;
-      Bim[kk][nn] = r[j].y;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void zgemm_kernel(Args a) {
+template <int WM, int WN, bool M3, int TK, int WAVES>
+__global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
+  constexpr int TM = 32 * WM, TN = 32 * WN;
   __shared__ double Are[TK][TM + PAD], Aim[TK][TM + PAD];
   __shared__ double Bre[TK][TN + PAD], Bim[TK][TN + PAD];
 
@@ -131,51 +94,70 @@ __global__ __launch_bounds__(256) void zgemm_kernel(Args a) {
 
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
-  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int wm = (w & 1) * 16 * WM, wn = (w >> 1) * 16 * WN;
   const int lr = lane & 15, lk = lane >> 4;
+  const bool a_rows = a.opA == OP_N, a_conj = a.opA == OP_C;
+  const bool b_rows = a.opB != OP_N, b_conj = a.opB == OP_C;
 
-  v4d acc_re[2][2], acc_im[2][2];
+  // M3: p1 = ArBr, p2 = AiBi, p3 = (Ar+Ai)(Br+Bi); otherwise p1 = Re, p3 = Im
+  v4d p1[WM][WN], p2[WM][WN], p3[WM][WN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      acc_re[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-      acc_im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < WN; ++j) {
+      p1[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      p2[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      p3[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
     }
 
-  double2 ra[4], rb[4];
-  load_a(a, A, m0, 0, t, ra);
-  load_b(a, B, n0, 0, t, rb);
+  double2 ra[TileIO<TM, TK>::PER], rb[TileIO<TN, TK>::PER];
+  TileIO<TM, TK>::load(A, a.lda, a.M, a.K, m0, 0, a_rows, a_conj, t, ra);
+  TileIO<TN, TK>::load(B, a.ldb, a.N, a.K, n0, 0, b_rows, b_conj, t, rb);
   const int nk = (a.K + TK - 1) / TK;
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
-    store_a(a, Are, Aim, t, ra);
-    store_b(a, Bre, Bim, t, rb);
+    TileIO<TM, TK>::store(Are, Aim, a_rows, t, ra);
+    TileIO<TN, TK>::store(Bre, Bim, b_rows, t, rb);
     __syncthreads();
     if (kt + 1 < nk) {
-      load_a(a, A, m0, (kt + 1) * TK, t, ra);
-      load_b(a, B, n0, (kt + 1) * TK, t, rb);
+      TileIO<TM, TK>::load(A, a.lda, a.M, a.K, m0, (kt + 1) * TK, a_rows, a_conj, t, ra);
+      TileIO<TN, TK>::load(B, a.ldb, a.N, a.K, n0, (kt + 1) * TK, b_rows, b_conj, t, rb);
     }
 #pragma unroll
     for (int ks = 0; ks < TK / 4; ++ks) {
       const int kk = ks * 4 + lk;
-      double ar[2], ai[2], br[2], bi[2];
+      double ar[WM], ai[WM], br[WN], bi[WN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < WM; ++i) {
         ar[i] = Are[kk][wm + 16 * i + lr];
         ai[i] = Aim[kk][wm + 16 * i + lr];
-        br[i] = Bre[kk][wn + 16 * i + lr];
-        bi[i] = Bim[kk][wn + 16 * i + lr];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < WN; ++j) {
+        br[j] = Bre[kk][wn + 16 * j + lr];
+        bi[j] = Bim[kk][wn + 16 * j + lr];
+      }
+      if constexpr (M3) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc_re[i][j], 0, 0, 0);
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], acc_re[i][j], 0, 0, 0);
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc_im[i][j], 0, 0, 0);
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc_im[i][j], 0, 0, 0);
-        }
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
+            p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], p2[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i] + ai[i], br[j] + bi[j], p3[i][j], 0,
+                                                            0, 0);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
+            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], p1[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], p3[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], p3[i][j], 0, 0, 0);
+          }
+      }
     }
   }
 
@@ -183,16 +165,17 @@ __global__ __launch_bounds__(256) void zgemm_kernel(Args a) {
   // column lane % 16.
   const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < WN; ++j) {
       const int col = n0 + wn + 16 * j + lr;
       if (col >= a.N) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + 16 * i + lk + 4 * r;
         if (row >= a.M) continue;
-        const double xr = acc_re[i][j][r], xi = acc_im[i][j][r];
+        const double xr = M3 ? p1[i][j][r] - p2[i][j][r] : p1[i][j][r];
+        const double xi = M3 ? p3[i][j][r] - p1[i][j][r] - p2[i][j][r] : p3[i][j][r];
         double2 v = make_double2(a.alpha.x * xr - a.alpha.y * xi, a.alpha.x * xi + a.alpha.y * xr);
         double2* pc = C + (ll)row + (ll)col * a.ldc;
         if (use_beta) {
@@ -205,6 +188,49 @@ __global__ __launch_bounds__(256) void zgemm_kernel(Args a) {
     }
 }
 
+template <int WM, int WN, bool M3, int TK, int WAVES>
+hipError_t launch(hipStream_t st, const Args& a, int batch) {
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  const ll tiles = (ll)((a.M + TM - 1) / TM) * ((a.N + TN - 1) / TN);
+  if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((zgemm_kernel<WM, WN, M3, TK, WAVES>), dim3((unsigned)tiles, (unsigned)batch), dim3(NT),
+                     0, st, a);
+  return hipGetLastError();
+}
+
+// Kernel variants (tile WM x WN, 3M or four products, K step, waves per
+// SIMD); HPS_ZGEMM_VARIANT=<index> forces one for tuning runs.
+typedef hipError_t (*LaunchFn)(hipStream_t, const Args&, int);
+const LaunchFn VARIANTS[] = {
+    launch<2, 2, false, 16, 2>,  // 0
+    launch<2, 2, true, 16, 2>,   // 1
+    launch<2, 2, false, 32, 2>,  // 2
+    launch<2, 2, true, 32, 2>,   // 3
+    launch<2, 2, true, 16, 1>,   // 4
+    launch<2, 1, false, 16, 2>,  // 5
+    launch<1, 2, false, 16, 2>,  // 6
+    launch<2, 2, false, 8, 2>,   // 7
+    launch<2, 1, true, 16, 2>,   // 8
+    launch<1, 2, true, 16, 2>,   // 9
+    launch<2, 2, true, 8, 2>,    // 10
+    launch<2, 1, true, 16, 3>,   // 11
+    launch<2, 1, true, 8, 3>,    // 12
+};
+constexpr int NVARIANT = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
+
+int forced_variant() {
+  static int v = -2;
+  if (v == -2) {
+    const char* e = std::getenv("HPS_ZGEMM_VARIANT");
+    v = -1;
+    if (e && *e) {
+      const int x = std::atoi(e);
+      if (x >= 0 && x < NVARIANT) v = x;
+    }
+  }
+  return v;
+}
+
 }  // namespace
 
 hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
@@ -213,14 +239,16 @@ hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
   Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta};
-  const ll tiles = (ll)((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-  if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  dim3 grid((unsigned)tiles, (unsigned)batch);
   const bool rb = (beta.x != 0.0 || beta.y != 0.0);
   KernelTimer kt(st, K_ZGEMM, 8.0 * M * N * (double)a.K * batch,
                  16.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);
-  hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, st, a);
-  return hipGetLastError();
+  const int fv = forced_variant();
+  if (fv >= 0) return VARIANTS[fv](st, a, batch);
+  // Tuned on MI355X over the solver's shapes (rank-32 updates of the
+  // inverses, leaf sweeps, merge products, top solve): all 3M.
+  if (a.K <= 64) return launch<2, 1, true, 8, 3>(st, a, batch);
+  if (M >= 1024 && N >= 1024 && a.K >= 512) return launch<2, 2, true, 16, 2>(st, a, batch);
+  return launch<2, 1, true, 16, 2>(st, a, batch);
 }
 
 }  // namespace hps
