@@ -221,8 +221,8 @@ hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
 /* ---- launch profiler (measurement support) ---- */
 
 typedef struct hps_kernel_stat {
-  char name[32];     /* kernel class: zgemm, gj_panel, gj_permute, gather_scatter,
-                        leaf_assemble, pointwise */
+  char name[32];     /* kernel class: zgemm, gj_panel, tp_select, tp_block,
+                        gj_permute, gather_scatter, leaf_assemble, pointwise */
   int64_t launches;  /* launches timed */
   double total_ms;   /* sum of per-launch durations (HIP events on the launch stream) */
   double flops;      /* sum of algorithmic flops (complex multiply-add = 8) */

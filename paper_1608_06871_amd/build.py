@@ -8,6 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhps.so")
 SOURCES = ["zgemm.hip", "zinv.hip", "hps_kernels.hip", "geometry.cpp", "hps.cpp", "profiler.cpp"]
+# per-source extra compiler flags
+EXTRA = {}
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # no packed FP32 instructions anywhere in the device code
@@ -33,7 +35,7 @@ def build(verbose=False, jobs=None):
         src = os.path.join(SRC, s)
         obj = os.path.join(objdir, s + ".o")
         lang = ["-x", "hip"] if s.endswith(".hip") else []
-        cmd = [cc] + FLAGS + lang + ["-c", src, "-o", obj]
+        cmd = [cc] + FLAGS + EXTRA.get(s, []) + lang + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

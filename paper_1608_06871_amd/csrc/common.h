@@ -17,11 +17,18 @@ hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 
                  const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB,
                  double2 beta, double2* C, ll ldc, ll sC, int batch);
 
+// zgemm in which the rows r of C_b with plo <= rpos[b * srp + r] < phi are
+// overwritten (beta taken as 0 there), the others updated with beta.
+hipError_t zgemm_rowmask(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
+                         const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB,
+                         double2 beta, double2* C, ll ldc, ll sC, const int* rpos, ll srp,
+                         int plo, int phi, int batch);
+
 // Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
 size_t zinv_workspace(int n, int batch);
 
-// Batched in-place-elimination inverse with partial pivoting (Gauss-Jordan,
-// blocked: panel eliminations followed by rank-b GEMM updates).  `work`
+// Batched inverse by swap-free Gauss-Jordan elimination with partial
+// pivoting (recursive column blocking: panel eliminations and GEMM updates).  `work`
 // (order n, lda, stride sA) is destroyed; the inverse is written to `out`.
 // info[b] (device, one int per matrix) is set non-zero when a zero pivot was
 // met.  `ws` must hold zinv_workspace(n, batch) bytes.
@@ -29,7 +36,17 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
                 ll sO, int batch, void* ws, int* info);
 
 // Kernel classes of the optional launch profiler.
-enum KernelKind { K_ZGEMM = 0, K_GJ_PANEL, K_GJ_PERM, K_MOVE, K_LEAF, K_POINT, KIND_COUNT };
+enum KernelKind {
+  K_ZGEMM = 0,
+  K_GJ_PANEL,   // Gauss-Jordan panel elimination (register / LDS / global panel)
+  K_TP_SELECT,  // tournament pivot selection (leaves and reductions)
+  K_TP_BLOCK,   // pivot-block inverse of the tournament path
+  K_GJ_PERM,
+  K_MOVE,
+  K_LEAF,
+  K_POINT,
+  KIND_COUNT
+};
 
 // RAII: when profiling is on, records HIP events around the kernel launched
 // inside its scope, with that launch's algorithmic flops and bytes.

@@ -33,6 +33,9 @@ struct Args {
   double2* C;
   ll ldc, sC;
   double2 alpha, beta;
+  const int* rpos;  // optional: rows r with plo <= rpos[r] < phi take beta = 0
+  ll srp;
+  int plo, phi;
 };
 
 __device__ inline double2 ld_op(const double2* p, bool conj) {
@@ -164,6 +167,7 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   // D layout of the 16x16x4 f64 MFMA: item r of a lane is row lane/16 + 4 r,
   // column lane % 16.
   const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
+  const int* rp = a.rpos ? a.rpos + (ll)blockIdx.y * a.srp : nullptr;
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
         const double xi = M3 ? p3[i][j][r] - p1[i][j][r] - p2[i][j][r] : p3[i][j][r];
         double2 v = make_double2(a.alpha.x * xr - a.alpha.y * xi, a.alpha.x * xi + a.alpha.y * xr);
         double2* pc = C + (ll)row + (ll)col * a.ldc;
-        if (use_beta) {
+        if (use_beta && !(rp && rp[row] >= a.plo && rp[row] < a.phi)) {
           const double2 c = *pc;
           v.x += a.beta.x * c.x - a.beta.y * c.y;
           v.y += a.beta.x * c.y + a.beta.y * c.x;
@@ -236,9 +240,16 @@ int forced_variant() {
 hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
                  const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB, double2 beta,
                  double2* C, ll ldc, ll sC, int batch) {
+  return zgemm_rowmask(st, opA, opB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, nullptr, 0, 0,
+                       0, batch);
+}
+
+hipError_t zgemm_rowmask(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
+                         const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB, double2 beta,
+                         double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
-  Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta};
+  Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, rpos, srp, plo, phi};
   const bool rb = (beta.x != 0.0 || beta.y != 0.0);
   KernelTimer kt(st, K_ZGEMM, 8.0 * M * N * (double)a.K * batch,
                  16.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);

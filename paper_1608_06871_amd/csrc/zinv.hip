@@ -1,301 +1,384 @@
-// Batched complex FP64 matrix inverse by blocked Gauss-Jordan elimination with
-// partial (row) pivoting.
+// Batched complex FP64 matrix inverse: swap-free Gauss-Jordan elimination
+// with partial pivoting, blocked recursively over the columns.
 //
-// For each column panel [c0, c0 + b):
-//   1. a panel kernel (one workgroup per matrix) eliminates the b pivot
-//      columns in place: pivot search over the rows not yet used, a full-row
-//      swap, and the in-place inverse update of the panel columns, which
-//      leaves inv(A_PP) in the pivot rows and -A_QP inv(A_PP) in the others.
-//      It then emits E = that panel and T = the pivot rows with the panel
-//      columns zeroed;
-//   2. the other columns are updated by batched complex GEMMs on the matrix
-//      cores: A_Q += E_Q T for the non-pivot rows (two row ranges) and
-//      A_P = inv(A_PP) T on the non-panel columns of the pivot rows (two
-//      column ranges, overwriting).  The pivot rows are never formed as
-//      A_P + (inv - I) A_P, which would cancel catastrophically when the
-//      pivots are large.
-// The row interchanges turn into a column permutation of the result, applied
-// out of place at the end.  Panels of matrices up to ~300 rows live in LDS;
-// larger ones are updated in global memory.
+// Rows are never interchanged.  The pivot of column c is chosen among the
+// rows not used yet; sig[c] records that row and pos[sig[c]] = c.  Each
+// Jordan exchange is done in place at (sig[c], c), so after all n columns the
+// array M holds the inverse up to a permutation of both indices,
+//   inv[c][k] = M[sig[c]][pos[k]],
+// undone by one out-of-place gather.
+//
+// Blocking.  The columns [c0, c1) of a block are processed by recursion: the
+// left half first (which updates only its own columns), then one GEMM applies
+// its exchanges to the right half, then the right half, then one GEMM applies
+// those to the left half.  For a block S of columns with pivot rows P
+// (= sig over S) and target columns D, the update is
+//   M[:, D] <- M[:, D] + M[:, S] T   on the rows not in P,
+//   M[:, D] <- M[:, S] T             on the rows in P (overwritten),
+// with T = M[P, D] copied out first.  The pivot rows are never formed as
+// M_P + (inv - I) M_P, which would cancel when the pivots are large.  Each
+// level of the recursion reads and writes the matrix once, so an order-n
+// matrix costs about log2(n / 32) passes instead of n / 32, and the GEMMs
+// have inner dimensions up to n / 2.
+//
+// Leaves of the recursion are panels of at most 32 columns:
+//   - n <= 512: one workgroup per matrix, thread r holding row r of the panel
+//     in registers; per column a wave arg-max (DPP), one LDS exchange of the
+//     wave winners (one barrier) and the register update;
+//   - n > 512: tournament pivoting (communication-avoiding LU, Grigori,
+//     Demmel and Xiang 2011): chunks of rows pick candidate pivot rows by
+//     partial pivoting, candidate sets are reduced the same way until the
+//     panel's pivot rows remain, whose block is inverted (tp_block); the
+//     panel columns are then exchanged with one GEMM.
 #include "common.h"
 
 namespace hps {
 namespace {
 
 constexpr int NT = 256;
-constexpr int BMAX = 32;
-constexpr size_t LDS_BUDGET = 150 * 1024;
+constexpr int BMAX = 32;      // panel width
+constexpr int NS_MAX_N = 512;  // largest order handled by the register panel
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// Pivot magnitude |re| + |im|; NaN ranks as +inf so that the arg-max always
+// lands on an eligible row.
+__device__ inline double pivmag(double2 a) {
+  const double m = fabs(a.x) + fabs(a.y);
+  return m == m ? m : INFINITY;
 }
 __device__ inline double2 crecip(double2 a) {
   const double d = a.x * a.x + a.y * a.y;
   return make_double2(a.x / d, -a.y / d);
 }
 
-// Arg-max of (value, index) over the workgroup: wave shuffles, then one
-// exchange of the per-wave winners through LDS.  Ties go to the lower index.
-// rv / ri hold NT / 64 entries; the caller synchronises before reusing them.
-__device__ inline int block_argmax(double v, int i, double* rv, int* ri, double* best) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int oi = __shfl_xor(i, off, 64);
-    if (ov > v || (ov == v && oi < i)) {
-      v = ov;
-      i = oi;
+// x - g p with four fused multiply-adds.
+__device__ __forceinline__ double2 cfms(double2 x, double2 g, double2 p) {
+  double2 r;
+  r.x = fma(-g.x, p.x, x.x);
+  r.x = fma(g.y, p.y, r.x);
+  r.y = fma(-g.x, p.y, x.y);
+  r.y = fma(-g.y, p.x, r.y);
+  return r;
+}
+
+// Register-row access with a run-time column c inside a block of 8 columns
+// known at compile time (B0): one-hot selects, so every register index stays
+// static.  These are macros, not functions: a helper taking the row by
+// reference is optimised on its own first, and there the selects of loads
+// become loads from selected addresses, which then pin the caller's row array
+// in scratch memory.
+#define HPS_GET8(ROW, HOT, B0, OUT)                  \
+  do {                                               \
+    OUT = ROW[B0];                                   \
+    _Pragma("unroll") for (int k_ = 1; k_ < 8; ++k_) \
+      if (((HOT) >> ((B0) + k_)) & 1u) OUT = ROW[(B0) + k_]; \
+  } while (0)
+#define HPS_SET8(ROW, HOT, B0, V)                             \
+  do {                                                        \
+    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_)          \
+      if (((HOT) >> ((B0) + k_)) & 1u) ROW[(B0) + k_] = (V);  \
+  } while (0)
+// ROW[j] -= G PR[j] for the columns of block B0 (PR in LDS; the scheduling
+// barrier keeps the reads of later blocks from being hoisted, which would
+// double the register footprint)
+#define HPS_UPD8(ROW, G, PR, B0)                     \
+  do {                                               \
+    __builtin_amdgcn_sched_barrier(0);               \
+    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) \
+      ROW[(B0) + k_] = cfms(ROW[(B0) + k_], G, PR[(B0) + k_]); \
+  } while (0)
+
+// Wave-wide arg-max of (v, i) by DPP moves inside each 16-lane row (quad
+// exchanges, then rotations by 4 and 8) and lane reads across the four
+// rows.  Every lane returns the winner; ties go to the lower index.
+template <int CTRL>
+__device__ __forceinline__ void amax_dpp(double& v, int& i) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  const double ov = __hiloint2double(hi, lo);
+  if (ov > v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int wave_argmax(double v, int i, double* best) {
+  amax_dpp<0xB1>(v, i);   // quad_perm [1, 0, 3, 2]
+  amax_dpp<0x4E>(v, i);   // quad_perm [2, 3, 0, 1]
+  amax_dpp<0x124>(v, i);  // row_ror:4
+  amax_dpp<0x128>(v, i);  // row_ror:8
+  double bv = readlane_f64(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) {
+    const double rv = readlane_f64(v, r);
+    const int ri = __builtin_amdgcn_readlane(i, r);
+    if (rv > bv || (rv == bv && ri < bi)) {
+      bv = rv;
+      bi = ri;
     }
   }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    rv[w] = v;
-    ri[w] = i;
-  }
-  __syncthreads();
-  double bv = rv[0];
-  int bi = ri[0];
-  for (int q = 1; q < NT / 64; ++q)
-    if (rv[q] > bv || (rv[q] == bv && ri[q] < bi)) {
-      bv = rv[q];
-      bi = ri[q];
-    }
   *best = bv;
   return bi;
 }
 
-template <bool L>
-__device__ inline double2& pel(double2* sm, double2* A, ll lda, int n, int c0, int r, int c) {
-  if constexpr (L)
-    return sm[r + c * n];
-  else
-    return A[(ll)r + (ll)(c0 + c) * lda];
+// Overall winner among the per-wave winners posted in LDS.
+template <int W>
+__device__ __forceinline__ int pick_winner(const double* cval, const int* cidx, double* best, int* wave) {
+  double bv = cval[0];
+  int p = cidx[0], pw = 0;
+#pragma unroll
+  for (int q = 1; q < W; ++q) {
+    const double v = cval[q];
+    const int i = cidx[q];
+    if (v > bv || (v == bv && i < p)) {
+      bv = v;
+      p = i;
+      pw = q;
+    }
+  }
+  *best = bv;
+  *wave = pw;
+  return p;
 }
 
-template <bool L>
-__global__ __launch_bounds__(NT) void gj_panel(double2* Aall, ll lda, ll sA, int n, int c0, int b,
-                                              int bstride, int* ipiv_all, double2* Eall,
-                                              double2* Tall, int* info) {
-  extern __shared__ double2 sm[];
-  __shared__ double2 prow[BMAX];
-  __shared__ double rv[NT];
-  __shared__ int ri[NT];
+__global__ void gj_init(int* pos_all, int n) {
+  const ll bi = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) pos_all[bi * n + r] = -1;
+}
+
+// Panel [c0, c0 + b) for n <= 64 W.  Thread r owns row r of the panel in
+// registers.  Per column: a wave arg-max over the unused rows; each wave's
+// winner posts its row to LDS (double-buffered by column parity, so one
+// barrier per column suffices); every thread picks the overall winner p and
+// applies the Jordan exchange at (p, c).  The column loop is not unrolled
+// (one copy of the step stays in the instruction cache); the current column
+// is picked from the register row by one-hot selects, so every register index
+// stays static.
+template <int W>
+__global__ __launch_bounds__(64 * W) void gj_panel(double2* Aall, ll lda, ll sA, int n, int c0, int b,
+                                                   int* sig_all, int* pos_all, int* info) {
+  __shared__ double2 cand[2][W][BMAX];
+  __shared__ double cval[2][W];
+  __shared__ int cidx[2][W];
   const ll bi = blockIdx.x;
   const int t = threadIdx.x;
+  const int w = t >> 6;
   double2* A = Aall + bi * sA;
-  int* ipiv = ipiv_all + bi * n;
-  double2* E = Eall + bi * (ll)n * bstride;
-  double2* T = Tall + bi * (ll)n * bstride;
-
-  if constexpr (L) {
-    for (int idx = t; idx < n * b; idx += NT) {
-      const int r = idx % n, c = idx / n;
-      sm[idx] = A[(ll)r + (ll)(c0 + c) * lda];
-    }
-    __syncthreads();
-  }
-
-  for (int c = 0; c < b; ++c) {
-    const int gc = c0 + c;
-    double best = -1.0;
-    int bidx = gc;
-    for (int r = gc + t; r < n; r += NT) {
-      const double2 v = pel<L>(sm, A, lda, n, c0, r, c);
-      const double m = fabs(v.x) + fabs(v.y);
-      if (m > best) {
-        best = m;
-        bidx = r;
-      }
-    }
-    double bestv;
-    const int p = block_argmax(best, bidx, rv, ri, &bestv);
-    const bool zero = !(bestv > 0.0);
-    if (t == 0) {
-      ipiv[gc] = p;
-      if (zero) info[bi] = 1;
-    }
-    if (p != gc) {
-      for (int j = t; j < n; j += NT) {
-        if (L && j >= c0 && j < c0 + b) {
-          double2& x = pel<L>(sm, A, lda, n, c0, gc, j - c0);
-          double2& y = pel<L>(sm, A, lda, n, c0, p, j - c0);
-          const double2 tmp = x;
-          x = y;
-          y = tmp;
-        } else {
-          double2* x = A + (ll)gc + (ll)j * lda;
-          double2* y = A + (ll)p + (ll)j * lda;
-          const double2 tmp = *x;
-          *x = *y;
-          *y = tmp;
-        }
-      }
-      __syncthreads();
-    }
-    const double2 piv = pel<L>(sm, A, lda, n, c0, gc, c);
-    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(piv);
-    if (t < b) prow[t] = (t == c) ? inv : cmul(pel<L>(sm, A, lda, n, c0, gc, t), inv);
-    __syncthreads();
-    for (int r = t; r < n; r += NT) {
-      if (r == gc) {
-        for (int j = 0; j < b; ++j) pel<L>(sm, A, lda, n, c0, gc, j) = prow[j];
-        continue;
-      }
-      const double2 f = pel<L>(sm, A, lda, n, c0, r, c);
-      for (int j = 0; j < b; ++j) {
-        if (j == c) continue;
-        double2& x = pel<L>(sm, A, lda, n, c0, r, j);
-        const double2 d = cmul(f, prow[j]);
-        x.x -= d.x;
-        x.y -= d.y;
-      }
-      const double2 nf = cmul(f, inv);
-      pel<L>(sm, A, lda, n, c0, r, c) = make_double2(-nf.x, -nf.y);
-    }
-    __syncthreads();
-  }
-
-  if constexpr (L) {
-    for (int idx = t; idx < n * b; idx += NT) {
-      const int r = idx % n, c = idx / n;
-      A[(ll)r + (ll)(c0 + c) * lda] = sm[idx];
-    }
-  }
-  for (int idx = t; idx < n * b; idx += NT) {
-    const int r = idx % n, c = idx / n;
-    E[idx] = pel<L>(sm, A, lda, n, c0, r, c);
-  }
-  __syncthreads();
-  for (int idx = t; idx < n * b; idx += NT) {
-    const int i = idx % b, j = idx / b;
-    T[idx] = (j >= c0 && j < c0 + b) ? make_double2(0.0, 0.0) : A[(ll)(c0 + i) + (ll)j * lda];
+  int* sig = sig_all + bi * n;
+  int* pos = pos_all + bi * n;
+  const bool own = t < n;
+  bool isused = own ? (pos[t] >= 0) : true;
+  int mycol = -1;
+  double2 row[BMAX];
+#pragma unroll
+  for (int j = 0; j < BMAX; ++j)
+    row[j] = (own && j < b) ? A[(ll)t + (ll)(c0 + j) * lda] : make_double2(0.0, 0.0);
+  // The column loop is split into four rolled loops, one per block of 8
+  // columns, so that the block of the current column is a compile-time
+  // constant (B0) while one copy of each step stays in the instruction cache.
+#define HPS_GJ_STEP(B0)                                                        \
+  do {                                                                         \
+    const int par = c & 1;                                                     \
+    const unsigned hot = 1u << c;                                              \
+    double2 rc;                                                                \
+    HPS_GET8(row, hot, B0, rc);                                                \
+    double wbest;                                                              \
+    const int wi = wave_argmax(isused ? -1.0 : pivmag(rc), t, &wbest);         \
+    if (t == wi) {                                                             \
+      _Pragma("unroll") for (int j = 0; j < BMAX; ++j) cand[par][w][j] = row[j]; \
+      cval[par][w] = wbest;                                                    \
+      cidx[par][w] = wi;                                                       \
+    }                                                                          \
+    __syncthreads();                                                           \
+    double bv;                                                                 \
+    int pw;                                                                    \
+    const int p = pick_winner<W>(cval[par], cidx[par], &bv, &pw);              \
+    const bool zero = !(bv > 0.0);                                             \
+    const double2* pr = cand[par][pw];                                         \
+    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(pr[c]);         \
+    if (t == 0) {                                                              \
+      sig[c0 + c] = p;                                                         \
+      if (zero) info[bi] = 1;                                                  \
+    }                                                                          \
+    /* other rows: row - g pr with -g in column c (g = row[c] inv); the       \
+       pivot row: pr inv with inv in column c (one wave takes that branch) */ \
+    const bool piv = (t == p);                                                 \
+    const double2 g = (own && !piv) ? cmul(rc, inv) : make_double2(0.0, 0.0);  \
+    HPS_UPD8(row, g, pr, 0);                                                   \
+    HPS_UPD8(row, g, pr, 8);                                                   \
+    HPS_UPD8(row, g, pr, 16);                                                  \
+    HPS_UPD8(row, g, pr, 24);                                                  \
+    if ((p >> 6) == w) {                                                       \
+      if (piv) {                                                               \
+        isused = true;                                                         \
+        mycol = c0 + c;                                                        \
+        _Pragma("unroll") for (int j = 0; j < BMAX; ++j) row[j] = cmul(pr[j], inv); \
+      }                                                                        \
+    }                                                                          \
+    const double2 nv = piv ? inv : make_double2(-g.x, -g.y);                   \
+    HPS_SET8(row, hot, B0, nv);                                                \
+  } while (0)
+#pragma unroll 1
+  for (int c = 0; c < (b < 8 ? b : 8); ++c) HPS_GJ_STEP(0);
+#pragma unroll 1
+  for (int c = 8; c < (b < 16 ? b : 16); ++c) HPS_GJ_STEP(8);
+#pragma unroll 1
+  for (int c = 16; c < (b < 24 ? b : 24); ++c) HPS_GJ_STEP(16);
+#pragma unroll 1
+  for (int c = 24; c < b; ++c) HPS_GJ_STEP(24);
+#undef HPS_GJ_STEP
+  if (own) {
+#pragma unroll
+    for (int j = 0; j < BMAX; ++j)
+      if (j < b) A[(ll)t + (ll)(c0 + j) * lda] = row[j];
+    if (mycol >= 0) pos[t] = mycol;
   }
 }
 
-// perm[j] = original column that ends up in column j after undoing the row
-// interchanges (column swaps applied in reverse pivot order).
-__global__ void gj_perm(const int* ipiv_all, int* perm_all, int n, int batch) {
-  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bi >= batch) return;
-  const int* ipiv = ipiv_all + (ll)bi * n;
-  int* perm = perm_all + (ll)bi * n;
-  for (int j = 0; j < n; ++j) perm[j] = j;
-  for (int c = n - 1; c >= 0; --c) {
-    const int p = ipiv[c];
-    if (p != c) {
-      const int tmp = perm[c];
-      perm[c] = perm[p];
-      perm[p] = tmp;
-    }
-  }
-}
-
-__global__ __launch_bounds__(NT) void gj_gather(const double2* W, ll lda, ll sA, double2* O,
-                                                ll ldo, ll sO, const int* perm_all, int n) {
+// T (w x nd, column-major) = M[sig[s0 + i], d0 + j].
+__global__ __launch_bounds__(NT) void gj_pivot_rows(const double2* Aall, ll lda, ll sA, const int* sig_all,
+                                                    int n, int s0, int w, int d0, int nd, double2* Tall,
+                                                    ll sT) {
   const ll bi = blockIdx.y;
-  const int* perm = perm_all + bi * n;
-  const int j = blockIdx.x;
-  const double2* src = W + bi * sA + (ll)perm[j] * lda;
-  double2* dst = O + bi * sO + (ll)j * ldo;
-  for (int r = threadIdx.x; r < n; r += NT) dst[r] = src[r];
+  const ll idx = (ll)blockIdx.x * NT + threadIdx.x;
+  if (idx >= (ll)w * nd) return;
+  const int i = (int)(idx % w), j = (int)(idx / w);
+  const int r = sig_all[bi * n + s0 + i];
+  Tall[bi * sT + idx] =
+      ((unsigned)r < (unsigned)n) ? Aall[bi * sA + (ll)r + (ll)(d0 + j) * lda] : make_double2(0.0, 0.0);
+}
+
+// out[c][k] = M[sig[c]][pos[k]]: one workgroup per output column.
+__global__ __launch_bounds__(NT) void gj_unpermute(const double2* M, ll lda, ll sA, double2* O, ll ldo,
+                                                   ll sO, const int* sig_all, const int* pos_all, int n) {
+  const ll bi = blockIdx.y;
+  const int k = blockIdx.x;
+  const int* sig = sig_all + bi * n;
+  const int pk = pos_all[bi * n + k];
+  const double2* src = M + bi * sA + (ll)pk * lda;
+  double2* dst = O + bi * sO + (ll)k * ldo;
+  const bool okk = (unsigned)pk < (unsigned)n;
+  for (int c = threadIdx.x; c < n; c += NT) {
+    const int r = sig[c];
+    dst[c] = (okk && (unsigned)r < (unsigned)n) ? src[r] : make_double2(0.0, 0.0);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Tournament pivoting for matrices whose panels do not fit in LDS
-// (communication-avoiding LU, Grigori, Demmel and Xiang 2011): the candidate
-// rows [c0, n) are split into chunks of TR rows; each chunk picks b pivot
-// candidates by partial-pivoting elimination of its panel rows; groups of TF
-// candidate sets are reduced the same way until one set of b rows remains.
-// Those rows become the pivot rows of the block step, which is then all
-// matrix products.
+// Tournament pivoting for n > 512.
 
-constexpr int TR = 256;  // rows per tournament leaf (one per thread)
-constexpr int TF = 4;    // candidate sets merged per reduction workgroup
+constexpr int TLW = 8;         // waves of a tournament leaf workgroup
+constexpr int TR = 64 * TLW;   // rows per tournament leaf (one per thread)
+constexpr int TF = 8;          // candidate sets merged per reduction workgroup
+constexpr int TRW = TF * BMAX / 64;  // waves of a reduction workgroup
 
-// Partial-pivoting elimination of an nr x b block in LDS (column-major,
-// leading dimension ld); ids[] follows the row interchanges.  After it the
-// first min(nr, b) entries of ids are the selected rows.
-__device__ void select_rows(double2* blk, int ld, int nr, int b, int* ids, double* rv, int* ri) {
-  const int t = threadIdx.x;
-  const int steps = nr < b ? nr : b;
-  for (int c = 0; c < steps; ++c) {
-    double best = -1.0;
-    int bidx = c;
-    for (int r = c + t; r < nr; r += NT) {
-      const double2 v = blk[r + c * ld];
-      const double m = fabs(v.x) + fabs(v.y);
-      if (m > best) {
-        best = m;
-        bidx = r;
-      }
-    }
-    double bestv;
-    const int p = block_argmax(best, bidx, rv, ri, &bestv);
-    const bool zero = !(bestv > 0.0);
-    __syncthreads();
-    if (p != c) {
-      for (int j = t; j < b; j += NT) {
-        const double2 x = blk[c + j * ld];
-        blk[c + j * ld] = blk[p + j * ld];
-        blk[p + j * ld] = x;
-      }
-      if (t == 0) {
-        const int x = ids[c];
-        ids[c] = ids[p];
-        ids[p] = x;
-      }
-    }
-    __syncthreads();
-    if (!zero) {
-      const double2 inv = crecip(blk[c + c * ld]);
-      for (int r = c + 1 + t; r < nr; r += NT) {
-        const double2 l = cmul(blk[r + c * ld], inv);
-        for (int j = c + 1; j < b; ++j) {
-          const double2 d = cmul(l, blk[c + j * ld]);
-          blk[r + j * ld].x -= d.x;
-          blk[r + j * ld].y -= d.y;
-        }
-      }
-    }
-    __syncthreads();
-  }
+// Partial-pivoting elimination of up to 64 SW candidate rows of the panel
+// [c0, c0 + b): thread t holds row `id` (id < 0: no row) in registers.  Rows
+// never move; the pivot of each column is the largest remaining entry, its
+// row is posted to LDS (double-buffered, one barrier per column) and the
+// other remaining rows are eliminated against it (only the blocks of 8
+// columns that still matter).  selid[c] receives the id of the c-th pivot
+// row, -1 once the candidates are exhausted.
+template <int SW>
+__device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, int id, int b,
+                                            double2 (*cand)[SW][BMAX], double (*cval)[SW],
+                                            int (*cidx)[SW], int* selid) {
+  const int t = threadIdx.x, w = t >> 6;
+  double2 row[BMAX];
+#pragma unroll
+  for (int j = 0; j < BMAX; ++j)
+    row[j] = (id >= 0 && j < b) ? A[(ll)id + (ll)(c0 + j) * lda] : make_double2(0.0, 0.0);
+  bool done = id < 0;
+  bool out = false;  // candidates exhausted
+  // four rolled loops, one per block of 8 columns (see gj_panel); blocks left
+  // of the current one are dead and not updated
+#define HPS_SEL_STEP(B0)                                                       \
+  do {                                                                         \
+    const int par = c & 1;                                                     \
+    const unsigned hot = 1u << c;                                              \
+    double2 rc;                                                                \
+    HPS_GET8(row, hot, B0, rc);                                                \
+    double wbest;                                                              \
+    const int wi = wave_argmax(done ? -1.0 : pivmag(rc), t, &wbest);           \
+    if (t == wi) {                                                             \
+      _Pragma("unroll") for (int j = 0; j < BMAX; ++j) cand[par][w][j] = row[j]; \
+      cval[par][w] = wbest;                                                    \
+      cidx[par][w] = wi;                                                       \
+    }                                                                          \
+    __syncthreads();                                                           \
+    double bv;                                                                 \
+    int pw;                                                                    \
+    const int p = pick_winner<SW>(cval[par], cidx[par], &bv, &pw);             \
+    out = bv < 0.0; /* no candidate rows left (uniform) */                     \
+    const double2* pr = cand[par][pw];                                         \
+    const bool upd = (t != p) && !done && bv > 0.0;                            \
+    if (t == p && !out) {                                                      \
+      selid[c] = id;                                                           \
+      done = true;                                                             \
+    }                                                                          \
+    /* l = 0 leaves the row unchanged */                                       \
+    const double2 l = upd ? cmul(rc, crecip(pr[c])) : make_double2(0.0, 0.0);  \
+    if ((B0) <= 0) HPS_UPD8(row, l, pr, 0);                                    \
+    if ((B0) <= 8) HPS_UPD8(row, l, pr, 8);                                    \
+    if ((B0) <= 16) HPS_UPD8(row, l, pr, 16);                                  \
+    HPS_UPD8(row, l, pr, 24);                                                  \
+  } while (0)
+  int c = 0;
+#pragma unroll 1
+  for (; c < (b < 8 ? b : 8) && !out; ++c) HPS_SEL_STEP(0);
+#pragma unroll 1
+  for (; c < (b < 16 ? b : 16) && !out; ++c) HPS_SEL_STEP(8);
+#pragma unroll 1
+  for (; c < (b < 24 ? b : 24) && !out; ++c) HPS_SEL_STEP(16);
+#pragma unroll 1
+  for (; c < b && !out; ++c) HPS_SEL_STEP(24);
+#undef HPS_SEL_STEP
+  // the column at which the candidates ran out (if any) and the rest: none
+  if (out)
+    for (int k = c - 1 + t; k < b; k += 64 * SW) selid[k] = -1;
+  __syncthreads();
 }
 
-// Leaves: chunk g of rows [c0, n) selects up to b candidate rows.
-__global__ __launch_bounds__(NT) void tp_leaf(const double2* Aall, ll lda, ll sA, int n, int c0,
-                                              int b, int G, int* cand_all) {
-  extern __shared__ double2 blk[];
-  __shared__ double rv[NT];
-  __shared__ int ri[NT];
-  __shared__ int ids[TR];
+// Leaves: chunk g of the rows (those not used as pivots yet) selects up to b
+// candidate rows.
+__global__ __launch_bounds__(TR) void tp_leaf(const double2* Aall, ll lda, ll sA, int n, int c0, int b,
+                                              int G, const int* pos_all, int* cand_all) {
+  __shared__ double2 cand[2][TLW][BMAX];
+  __shared__ double cval[2][TLW];
+  __shared__ int cidx[2][TLW];
+  __shared__ int selid[BMAX];
   const ll bi = blockIdx.y;
   const int g = blockIdx.x, t = threadIdx.x;
-  const double2* A = Aall + bi * sA;
-  const int r0 = c0 + g * TR;
-  const int nr = (n - r0) < TR ? (n - r0) : TR;
-  for (int idx = t; idx < nr * b; idx += NT) {
-    const int r = idx % nr, c = idx / nr;
-    blk[r + c * TR] = A[(ll)(r0 + r) + (ll)(c0 + c) * lda];
-  }
-  for (int r = t; r < TR; r += NT) ids[r] = (r < nr) ? r0 + r : -1;
-  __syncthreads();
-  select_rows(blk, TR, nr, b, ids, rv, ri);
-  int* cand = cand_all + (bi * G + g) * (ll)b;
-  for (int i = t; i < b; i += NT) cand[i] = (i < nr) ? ids[i] : -1;
+  const int r = g * TR + t;
+  const int id = (r < n && pos_all[bi * n + r] < 0) ? r : -1;
+  select_rows<TLW>(Aall + bi * sA, lda, c0, id, b, cand, cval, cidx, selid);
+  int* out = cand_all + (bi * G + g) * (ll)b;
+  if (t < b) out[t] = selid[t];
 }
 
 // Reduction: workgroup g merges candidate sets [TF g, TF g + TF) of Gin
-// (entries -1 mark missing candidates of short chunks).
-__global__ __launch_bounds__(NT) void tp_reduce(const double2* Aall, ll lda, ll sA, int c0, int b,
-                                                int Gin, const int* cin_all, int Gout,
-                                                int* cout_all) {
-  extern __shared__ double2 blk[];
-  __shared__ double rv[NT];
-  __shared__ int ri[NT];
+// (entries -1 mark missing candidates).
+__global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll lda, ll sA, int c0, int b,
+                                                      int Gin, const int* cin_all, int Gout, int* cout_all) {
+  __shared__ double2 cand[2][TRW][BMAX];
+  __shared__ double cval[2][TRW];
+  __shared__ int cidx[2][TRW];
+  __shared__ int selid[BMAX];
   __shared__ int ids[TF * BMAX];
   __shared__ int nsel;
   const ll bi = blockIdx.y;
   const int g = blockIdx.x, t = threadIdx.x;
-  const double2* A = Aall + bi * sA;
   const int* cin = cin_all + bi * (ll)Gin * b;
   if (t == 0) {
     int k = 0;
@@ -305,106 +388,32 @@ __global__ __launch_bounds__(NT) void tp_reduce(const double2* Aall, ll lda, ll 
     nsel = k;
   }
   __syncthreads();
-  const int nr = nsel;
-  const int ld = TF * BMAX;
-  for (int idx = t; idx < nr * b; idx += NT) {
-    const int r = idx % nr, c = idx / nr;
-    blk[r + c * ld] = A[(ll)ids[r] + (ll)(c0 + c) * lda];
-  }
-  __syncthreads();
-  select_rows(blk, ld, nr, b, ids, rv, ri);
-  int* cout = cout_all + (bi * Gout + g) * (ll)b;
-  for (int i = t; i < b; i += NT) cout[i] = (i < nr) ? ids[i] : -1;
+  const int id = (t < nsel) ? ids[t] : -1;
+  select_rows<TRW>(Aall + bi * sA, lda, c0, id, b, cand, cval, cidx, selid);
+  int* out = cout_all + (bi * Gout + g) * (ll)b;
+  if (t < b) out[t] = selid[t];
 }
 
-// Plans the interchanges that bring the selected rows (in order) to rows
-// c0..c0+b-1: the sequence of swaps is recorded in ipiv (same convention as
-// the unblocked panel), and their net effect -- a permutation of at most 2b
-// rows -- as (destination, source) pairs for tp_apply.  One workgroup per
-// matrix; dense maps over the rows [c0, n) live in LDS.
-__global__ __launch_bounds__(NT) void tp_plan(int n, int c0, int b, const int* sel_all,
-                                              int* ipiv_all, int* plan_all) {
-  extern __shared__ int maps[];  // row_at[n - c0], pos_of[n - c0]
-  __shared__ int touched[2 * BMAX];
-  const ll bi = blockIdx.x;
-  const int t = threadIdx.x, nr = n - c0;
-  const int* sel = sel_all + bi * b;
-  int* plan = plan_all + bi * (1 + 4 * BMAX);
-  int* row_at = maps;
-  int* pos_of = maps + nr;
-  for (int x = t; x < nr; x += NT) {
-    row_at[x] = x;
-    pos_of[x] = x;
-  }
-  __syncthreads();
-  if (t == 0) {
-    for (int i = 0; i < b; ++i) {
-      const int want = sel[i] - c0, tgt = i;
-      // always in range: the tournament returns >= b rows of [c0, n)
-      const int s = (want >= 0 && want < nr) ? pos_of[want] : tgt;
-      ipiv_all[bi * n + c0 + tgt] = c0 + s;
-      touched[2 * i] = tgt;
-      touched[2 * i + 1] = s;
-      if (s == tgt) continue;
-      const int rt = row_at[tgt], rs = row_at[s];
-      row_at[tgt] = rs;
-      row_at[s] = rt;
-      pos_of[rs] = tgt;
-      pos_of[rt] = s;
-    }
-    int m = 0;
-    for (int q = 0; q < 2 * b; ++q) {
-      const int x = touched[q];
-      if (row_at[x] != x) {
-        plan[1 + 2 * m] = c0 + x;
-        plan[2 + 2 * m] = c0 + row_at[x];
-        row_at[x] = x;  // emitted
-        ++m;
-      }
-    }
-    plan[0] = m;
-  }
-}
-
-// Applies the planned row permutation to 64 columns per workgroup: all moved
-// rows are read into LDS first, then written to their destinations.
-__global__ __launch_bounds__(NT) void tp_apply(double2* Aall, ll lda, ll sA, int n,
-                                               const int* plan_all) {
-  __shared__ double2 buf[2 * BMAX][64];
-  const ll bi = blockIdx.y;
-  const int t = threadIdx.x;
-  double2* A = Aall + bi * sA;
-  const int* plan = plan_all + bi * (1 + 4 * BMAX);
-  const int m = plan[0];
-  const int j0 = blockIdx.x * 64;
-  for (int idx = t; idx < m * 64; idx += NT) {
-    const int q = idx % m, jj = idx / m;
-    const int j = j0 + jj;
-    if (j < n) buf[q][jj] = A[(ll)plan[2 + 2 * q] + (ll)j * lda];
-  }
-  __syncthreads();
-  for (int idx = t; idx < m * 64; idx += NT) {
-    const int q = idx % m, jj = idx / m;
-    const int j = j0 + jj;
-    if (j < n) A[(ll)plan[1 + 2 * q] + (ll)j * lda] = buf[q][jj];
-  }
-}
-
-// Inverse of the b x b pivot block by Gauss-Jordan elimination without
-// interchanges: the tournament ordered the pivot rows by partial pivoting, so
+// Inverse IB of the b x b block of the selected pivot rows (in selection
+// order) and the panel columns, by Gauss-Jordan elimination without
+// interchanges: the tournament ordered the rows by partial pivoting, so
 // elimination in that order makes the same pivot choices.  BMAX x BMAX
-// threads, one element each (the block padded with the identity); the
-// matrix is exchanged through LDS once per elimination step.
-__global__ __launch_bounds__(BMAX * BMAX) void tp_block(const double2* Aall, ll lda, ll sA, int c0,
-                                                        int b, double2* IB_all, int* info) {
+// threads, one element each (the block padded with the identity).  Also
+// records sig / pos for the panel.
+__global__ __launch_bounds__(BMAX * BMAX) void tp_block(const double2* Aall, ll lda, ll sA, int n, int c0,
+                                                        int b, const int* sel_all, double2* IB_all,
+                                                        int* sig_all, int* pos_all, int* info) {
   __shared__ double2 m[BMAX * BMAX];  // column-major: (r, j) at r + j * BMAX
   const ll bi = blockIdx.x;
   const int t = threadIdx.x;
   const int r = t % BMAX, j = t / BMAX;
   const double2* A = Aall + bi * sA;
+  const int* sel = sel_all + bi * b;
   double2* IB = IB_all + bi * (ll)BMAX * BMAX;
+  const int pr = (r < b) ? sel[r] : -1;
   const bool act = (r < b && j < b);
-  double2 v = act ? A[(ll)(c0 + r) + (ll)(c0 + j) * lda] : make_double2((r == j) ? 1.0 : 0.0, 0.0);
+  double2 v = act ? (pr >= 0 ? A[(ll)pr + (ll)(c0 + j) * lda] : make_double2(0.0, 0.0))
+                  : make_double2((r == j) ? 1.0 : 0.0, 0.0);
   bool singular = false;
   for (int c = 0; c < b; ++c) {
     m[t] = v;
@@ -426,224 +435,212 @@ __global__ __launch_bounds__(BMAX * BMAX) void tp_block(const double2* Aall, ll 
     }
   }
   if (act) IB[r + j * b] = v;
+  if (j == 0 && r < b && pr >= 0) {
+    sig_all[bi * n + c0 + r] = pr;
+    pos_all[bi * n + pr] = c0 + r;
+  }
   if (t == 0 && singular) info[bi] = 1;
 }
 
-// T = pivot rows c0.. of A, with the panel columns zeroed (b x n, ld b).
-__global__ __launch_bounds__(NT) void tp_copy_t(const double2* Aall, ll lda, ll sA, int n, int c0,
-                                                int b, int bstride, double2* Tall) {
-  const ll bi = blockIdx.y;
-  const double2* A = Aall + bi * sA;
-  double2* T = Tall + bi * (ll)n * bstride;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < (ll)n * b; idx += (ll)gridDim.x * NT) {
-    const int i = (int)(idx % b);
-    const int j = (int)(idx / b);
-    T[idx] = (j >= c0 && j < c0 + b) ? make_double2(0.0, 0.0) : A[(ll)(c0 + i) + (ll)j * lda];
-  }
-}
-
-// After E = -A[:, panel] IB: the pivot rows of E become IB, and the panel
-// columns of A take their eliminated values (IB on the pivot rows, E
-// elsewhere).
+// Panel columns after the block exchange: IB on the pivot rows, -A_Q IB
+// (Et = A[:, panel] IB) elsewhere.
 __global__ __launch_bounds__(NT) void tp_fix(double2* Aall, ll lda, ll sA, int n, int c0, int b,
-                                             int bstride, const double2* IB_all, double2* Eall) {
+                                             const double2* IB_all, const double2* Et_all,
+                                             const int* pos_all) {
   const ll bi = blockIdx.y;
-  double2* A = Aall + bi * sA;
-  double2* E = Eall + bi * (ll)n * bstride;
-  const double2* IB = IB_all + bi * (ll)BMAX * BMAX;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < (ll)n * b; idx += (ll)gridDim.x * NT) {
-    const int r = (int)(idx % n);
-    const int c = (int)(idx / n);
-    if (r >= c0 && r < c0 + b) {
-      const double2 v = IB[(r - c0) + c * b];
-      A[(ll)r + (ll)(c0 + c) * lda] = v;
-      E[idx] = v;
-    } else {
-      A[(ll)r + (ll)(c0 + c) * lda] = E[idx];
+  const ll idx = (ll)blockIdx.x * NT + threadIdx.x;
+  if (idx >= (ll)n * b) return;
+  const int r = (int)(idx % n), c = (int)(idx / n);
+  const int pr = pos_all[bi * n + r];
+  double2 v;
+  if (pr >= c0 && pr < c0 + b) {
+    v = IB_all[bi * (ll)BMAX * BMAX + (pr - c0) + c * b];
+  } else {
+    const double2 e = Et_all[bi * (ll)n * BMAX + idx];
+    v = make_double2(-e.x, -e.y);
+  }
+  Aall[bi * sA + (ll)r + (ll)(c0 + c) * lda] = v;
+}
+
+size_t cand_ints(int n, int batch) { return (size_t)batch * ((n + TR - 1) / TR) * BMAX; }
+
+// Split point of a block of w > BMAX columns: half of its panels, rounded up.
+int split_at(int c0, int w) {
+  const int np = (w + BMAX - 1) / BMAX;
+  return c0 + BMAX * ((np + 1) / 2);
+}
+
+// Largest w x nd product over the recursion on a block of w columns.
+size_t t_elems_block(int w) {
+  if (w <= BMAX) return 0;
+  const int m = split_at(0, w);
+  size_t e = (size_t)m * (w - m);
+  const size_t l = t_elems_block(m), r = t_elems_block(w - m);
+  if (l > e) e = l;
+  if (r > e) e = r;
+  return e;
+}
+size_t t_elems(int n) { return t_elems_block(n); }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Inv {
+  hipStream_t st;
+  int n, batch;
+  double2* work;
+  ll lda, sA;
+  int* sig;
+  int* pos;
+  double2* T;
+  ll sT;
+  double2* Et;
+  double2* IB;
+  int* candA;
+  int* candB;
+  int* info;
+};
+
+hipError_t launch_panel(const Inv& v, int c0, int bw) {
+  const int waves = (v.n + 63) / 64;
+#define HPS_PANEL(WV)                                                                                     \
+  hipLaunchKernelGGL(gj_panel<WV>, dim3(v.batch), dim3(64 * WV), 0, v.st, v.work, v.lda, v.sA, v.n, c0, \
+                     bw, v.sig, v.pos, v.info)
+  if (waves <= 1)
+    HPS_PANEL(1);
+  else if (waves <= 2)
+    HPS_PANEL(2);
+  else if (waves <= 4)
+    HPS_PANEL(4);
+  else
+    HPS_PANEL(8);
+#undef HPS_PANEL
+  return hipGetLastError();
+}
+
+// Tournament panel: candidate selection, pivot-block inverse, exchange of
+// the panel columns.
+hipError_t tournament_panel(const Inv& v, int c0, int bw) {
+  const int n = v.n, batch = v.batch;
+  const int G = (n + TR - 1) / TR;
+  {
+    KernelTimer kt(v.st, K_TP_SELECT, 8.0 * n * (double)bw * bw * batch, 16.0 * n * (double)bw * batch);
+    hipLaunchKernelGGL(tp_leaf, dim3(G, batch), dim3(TR), 0, v.st, v.work, v.lda, v.sA, n, c0, bw, G, v.pos,
+                       v.candA);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  int* cin = v.candA;
+  int* cout = v.candB;
+  int Gin = G;
+  while (Gin > 1) {
+    const int Gout = (Gin + TF - 1) / TF;
+    {
+      KernelTimer kt(v.st, K_TP_SELECT, 8.0 * Gin * (double)bw * bw * bw * batch,
+                     16.0 * Gin * (double)bw * bw * batch);
+      hipLaunchKernelGGL(tp_reduce, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, c0, bw,
+                         Gin, cin, Gout, cout);
     }
+    HPS_HIP_TRY(hipGetLastError());
+    int* tmp = cin;
+    cin = cout;
+    cout = tmp;
+    Gin = Gout;
   }
+  {
+    KernelTimer kt(v.st, K_TP_BLOCK, 8.0 * bw * (double)bw * bw * batch, 32.0 * bw * (double)bw * batch);
+    hipLaunchKernelGGL(tp_block, dim3(batch), dim3(BMAX * BMAX), 0, v.st, v.work, v.lda, v.sA, n, c0, bw, cin,
+                       v.IB, v.sig, v.pos, v.info);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  HPS_HIP_TRY(zgemm(v.st, OP_N, OP_N, n, bw, bw, make_double2(1.0, 0.0), v.work + (ll)c0 * v.lda, v.lda, v.sA,
+                    v.IB, bw, (ll)BMAX * BMAX, make_double2(0.0, 0.0), v.Et, n, (ll)n * BMAX, batch));
+  {
+    KernelTimer kt(v.st, K_MOVE, 0.0, 48.0 * n * (double)bw * batch);
+    hipLaunchKernelGGL(tp_fix, dim3((unsigned)(((ll)n * bw + NT - 1) / NT), batch), dim3(NT), 0, v.st, v.work,
+                       v.lda, v.sA, n, c0, bw, v.IB, v.Et, v.pos);
+  }
+  return hipGetLastError();
 }
 
-int panel_width(int n) { return n < BMAX ? n : BMAX; }
-
-// Dynamic LDS available to one workgroup of the panel kernel (bytes).
-size_t lds_limit() {
-  static size_t cached = 0;
-  if (cached == 0) {
-    int dev = 0, v = 0;
-    size_t lim = 64 * 1024;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-        v > 0)
-      lim = (size_t)v;
-    const size_t static_lds = BMAX * sizeof(double2) + NT * (sizeof(double) + sizeof(int));
-    lim = lim > static_lds + 512 ? lim - static_lds - 512 : 0;
-    cached = lim < LDS_BUDGET ? lim : LDS_BUDGET;
+// Applies the exchanges of columns [s0, s1) to columns [d0, d1).
+hipError_t block_update(const Inv& v, int s0, int s1, int d0, int d1) {
+  const int w = s1 - s0, nd = d1 - d0;
+  if (w <= 0 || nd <= 0) return hipSuccess;
+  {
+    KernelTimer kt(v.st, K_MOVE, 0.0, 32.0 * w * (double)nd * v.batch);
+    hipLaunchKernelGGL(gj_pivot_rows, dim3((unsigned)(((ll)w * nd + NT - 1) / NT), v.batch), dim3(NT), 0, v.st,
+                       v.work, v.lda, v.sA, v.sig, v.n, s0, w, d0, nd, v.T, v.sT);
   }
-  return cached;
+  HPS_HIP_TRY(hipGetLastError());
+  return zgemm_rowmask(v.st, OP_N, OP_N, v.n, nd, w, make_double2(1.0, 0.0), v.work + (ll)s0 * v.lda, v.lda,
+                       v.sA, v.T, w, v.sT, make_double2(1.0, 0.0), v.work + (ll)d0 * v.lda, v.lda, v.sA, v.pos,
+                       v.n, s0, s1, v.batch);
 }
 
-// Applies the eliminations of panel [c0, c0 + bw) to the other columns (see
-// the file comment): rows outside the panel accumulate E_Q T, the pivot rows
-// are overwritten by inv(A_PP) T outside the panel columns.
-hipError_t apply_panel(hipStream_t st, int n, int c0, int bw, int bmax, double2* work, ll lda, ll sA,
-                       const double2* E, const double2* T, int batch) {
-  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
-  const ll se = (ll)n * bmax;
-  const int c1 = c0 + bw;
-  // non-pivot rows [0, c0) and [c1, n), all columns (T is zero on the panel)
-  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, c0, n, bw, one, E, n, se, T, bw, se, one, work, lda, sA, batch));
-  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n - c1, n, bw, one, E + c1, n, se, T, bw, se, one, work + c1, lda,
-                    sA, batch));
-  // pivot rows, columns [0, c0) and [c1, n)
-  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, bw, c0, bw, one, E + c0, n, se, T, bw, se, zero, work + c0, lda, sA,
-                    batch));
-  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, bw, n - c1, bw, one, E + c0, n, se, T + (ll)c1 * bw, bw, se, zero,
-                    work + c0 + (ll)c1 * lda, lda, sA, batch));
-  return hipSuccess;
+hipError_t process_block(const Inv& v, int c0, int c1) {
+  const int w = c1 - c0;
+  if (w <= BMAX) {
+    if (v.n > NS_MAX_N) return tournament_panel(v, c0, w);
+    KernelTimer kt(v.st, K_GJ_PANEL, 8.0 * v.n * (double)w * w * v.batch, 32.0 * v.n * (double)w * v.batch);
+    return launch_panel(v, c0, w);
+  }
+  const int m = split_at(c0, w);
+  HPS_HIP_TRY(process_block(v, c0, m));
+  HPS_HIP_TRY(block_update(v, c0, m, m, c1));
+  HPS_HIP_TRY(process_block(v, m, c1));
+  return block_update(v, m, c1, c0, m);
 }
 
 }  // namespace
 
-constexpr int TOURNAMENT_MIN_N = 512;
-
-size_t cand_ints(int n, int batch) { return (size_t)batch * ((n + TR - 1) / TR) * BMAX; }
-
 size_t zinv_workspace(int n, int batch) {
-  const int b = panel_width(n);
-  size_t bytes = 0;
-  bytes += (size_t)batch * n * sizeof(int) * 2;         // ipiv + perm
-  bytes = (bytes + 255) & ~(size_t)255;
-  bytes += (size_t)batch * n * b * sizeof(double2) * 2;  // E + T
-  bytes += (size_t)batch * BMAX * BMAX * sizeof(double2);  // pivot-block inverses
-  bytes += 2 * cand_ints(n, batch) * sizeof(int);          // tournament candidates
-  bytes += (size_t)batch * (1 + 4 * BMAX) * sizeof(int);   // row-permutation plans
+  size_t bytes = align256((size_t)batch * n * sizeof(int) * 2);   // sig + pos
+  bytes += align256((size_t)batch * t_elems(n) * sizeof(double2));  // pivot rows T
+  if (n > NS_MAX_N) {
+    bytes += align256((size_t)batch * n * BMAX * sizeof(double2));    // Et
+    bytes += align256((size_t)batch * BMAX * BMAX * sizeof(double2));  // IB
+    bytes += 2 * align256(cand_ints(n, batch) * sizeof(int));          // candidates
+  }
   return bytes;
 }
 
-hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO,
-                int batch, void* ws, int* info) {
+hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO, int batch,
+                void* ws, int* info) {
   if (n <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
-  const int bmax = panel_width(n);
-  // panel in LDS when at least min(8, n) columns fit, else in global memory
-  const int b_lds = (int)(lds_limit() / ((size_t)n * sizeof(double2)));
-  const bool in_lds = b_lds >= (n < 8 ? n : 8);
-  const int b = in_lds ? (b_lds < bmax ? b_lds : bmax) : bmax;
-  int* ipiv = (int*)ws;
-  int* perm = ipiv + (size_t)batch * n;
-  size_t off = ((size_t)batch * n * sizeof(int) * 2 + 255) & ~(size_t)255;
-  double2* E = (double2*)((char*)ws + off);
-  double2* T = E + (size_t)batch * n * bmax;
-  if (n > TOURNAMENT_MIN_N) {
-    double2* IB = T + (size_t)batch * n * bmax;
-    int* candA = (int*)(IB + (size_t)batch * BMAX * BMAX);
-    int* candB = candA + cand_ints(n, batch);
-    int* plan = candB + cand_ints(n, batch);
-    const int bt = bmax;
-    HPS_HIP_TRY(hipFuncSetAttribute((const void*)tp_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(TR * bt * sizeof(double2))));
-    HPS_HIP_TRY(hipFuncSetAttribute((const void*)tp_reduce,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(TF * BMAX * bt * sizeof(double2))));
-    HPS_HIP_TRY(hipFuncSetAttribute((const void*)tp_plan, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(2 * n * sizeof(int))));
-    const unsigned eblocks = (unsigned)(((ll)n * bt + NT - 1) / NT);
-    for (int c0 = 0; c0 < n; c0 += bt) {
-      const int bw = (n - c0) < bt ? (n - c0) : bt;
-      const int G = (n - c0 + TR - 1) / TR;
-      {
-        KernelTimer kt(st, K_GJ_PANEL, 8.0 * (n - c0) * (double)bw * bw * batch,
-                       16.0 * (n - c0) * (double)bw * batch);
-        hipLaunchKernelGGL(tp_leaf, dim3(G, batch), dim3(NT), TR * bw * sizeof(double2), st, work, lda,
-                           sA, n, c0, bw, G, candA);
-      }
-      HPS_HIP_TRY(hipGetLastError());
-      int* cin = candA;
-      int* cout = candB;
-      int Gin = G;
-      while (Gin > 1) {
-        const int Gout = (Gin + TF - 1) / TF;
-        KernelTimer kt(st, K_GJ_PANEL, 8.0 * Gin * (double)bw * bw * bw * batch,
-                       16.0 * Gin * (double)bw * bw * batch);
-        hipLaunchKernelGGL(tp_reduce, dim3(Gout, batch), dim3(NT), TF * BMAX * bw * sizeof(double2), st,
-                           work, lda, sA, c0, bw, Gin, cin, Gout, cout);
-        HPS_HIP_TRY(hipGetLastError());
-        int* tmp = cin;
-        cin = cout;
-        cout = tmp;
-        Gin = Gout;
-      }
-      {
-        KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * bw * (double)batch);
-        hipLaunchKernelGGL(tp_plan, dim3(batch), dim3(NT), 2 * (n - c0) * sizeof(int), st, n, c0, bw, cin,
-                           ipiv, plan);
-      }
-      HPS_HIP_TRY(hipGetLastError());
-      {
-        KernelTimer kt(st, K_GJ_PERM, 0.0, 64.0 * n * (double)bw * batch);
-        hipLaunchKernelGGL(tp_apply, dim3((n + 63) / 64, batch), dim3(NT), 0, st, work, lda, sA, n, plan);
-      }
-      HPS_HIP_TRY(hipGetLastError());
-      {
-        KernelTimer kt(st, K_GJ_PANEL, 8.0 * bw * (double)bw * bw * batch, 32.0 * bw * (double)bw * batch);
-        hipLaunchKernelGGL(tp_block, dim3(batch), dim3(BMAX * BMAX), 0, st, work, lda, sA, c0, bw, IB,
-                           info);
-      }
-      HPS_HIP_TRY(hipGetLastError());
-      {
-        KernelTimer kt(st, K_MOVE, 0.0, 32.0 * n * (double)bw * batch);
-        hipLaunchKernelGGL(tp_copy_t, dim3(eblocks, batch), dim3(NT), 0, st, work, lda, sA, n, c0, bw, bmax,
-                           T);
-      }
-      HPS_HIP_TRY(hipGetLastError());
-      HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, bw, bw, make_double2(-1.0, 0.0), work + (ll)c0 * lda, lda, sA,
-                        IB, bw, (ll)BMAX * BMAX, make_double2(0.0, 0.0), E, n, (ll)n * bmax, batch));
-      {
-        KernelTimer kt(st, K_MOVE, 0.0, 48.0 * n * (double)bw * batch);
-        hipLaunchKernelGGL(tp_fix, dim3(eblocks, batch), dim3(NT), 0, st, work, lda, sA, n, c0, bw, bmax,
-                           IB, E);
-      }
-      HPS_HIP_TRY(hipGetLastError());
-      if (bw < n) HPS_HIP_TRY(apply_panel(st, n, c0, bw, bmax, work, lda, sA, E, T, batch));
-    }
-    {
-      KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * n * batch);
-      hipLaunchKernelGGL(gj_perm, dim3((batch + 63) / 64), dim3(64), 0, st, ipiv, perm, n, batch);
-    }
-    HPS_HIP_TRY(hipGetLastError());
-    {
-      KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
-      hipLaunchKernelGGL(gj_gather, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, perm, n);
-    }
-    return hipGetLastError();
-  }
-  const size_t lds = (size_t)n * b * sizeof(double2);
-  if (in_lds) {
-    HPS_HIP_TRY(hipFuncSetAttribute((const void*)gj_panel<true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  }
-  for (int c0 = 0; c0 < n; c0 += b) {
-    const int bw = (n - c0) < b ? (n - c0) : b;
-    KernelTimer kt(st, K_GJ_PANEL, 8.0 * n * (double)bw * bw * batch, 64.0 * n * (double)bw * batch);
-    if (in_lds) {
-      hipLaunchKernelGGL(gj_panel<true>, dim3(batch), dim3(NT), (size_t)n * bw * sizeof(double2),
-                         st, work, lda, sA, n, c0, bw, bmax, ipiv, E, T, info);
-    } else {
-      hipLaunchKernelGGL(gj_panel<false>, dim3(batch), dim3(NT), 0, st, work, lda, sA, n, c0, bw,
-                         bmax, ipiv, E, T, info);
-    }
-    HPS_HIP_TRY(hipGetLastError());
-    if (bw < n) HPS_HIP_TRY(apply_panel(st, n, c0, bw, bmax, work, lda, sA, E, T, batch));
+  char* p = (char*)ws;
+  Inv v{};
+  v.st = st;
+  v.n = n;
+  v.batch = batch;
+  v.work = work;
+  v.lda = lda;
+  v.sA = sA;
+  v.info = info;
+  v.sig = (int*)p;
+  v.pos = v.sig + (size_t)batch * n;
+  p += align256((size_t)batch * n * sizeof(int) * 2);
+  v.T = (double2*)p;
+  v.sT = (ll)t_elems(n);
+  p += align256((size_t)batch * t_elems(n) * sizeof(double2));
+  if (n > NS_MAX_N) {
+    v.Et = (double2*)p;
+    p += align256((size_t)batch * n * BMAX * sizeof(double2));
+    v.IB = (double2*)p;
+    p += align256((size_t)batch * BMAX * BMAX * sizeof(double2));
+    v.candA = (int*)p;
+    p += align256(cand_ints(n, batch) * sizeof(int));
+    v.candB = (int*)p;
   }
   {
-    KernelTimer kt(st, K_GJ_PERM, 0.0, 8.0 * n * batch);
-    hipLaunchKernelGGL(gj_perm, dim3((batch + 63) / 64), dim3(64), 0, st, ipiv, perm, n, batch);
+    KernelTimer kt(st, K_GJ_PERM, 0.0, 4.0 * n * batch);
+    hipLaunchKernelGGL(gj_init, dim3((n + 255) / 256, batch), dim3(256), 0, st, v.pos, n);
   }
   HPS_HIP_TRY(hipGetLastError());
+  HPS_HIP_TRY(process_block(v, 0, n));
   {
     KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
-    hipLaunchKernelGGL(gj_gather, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, perm, n);
+    hipLaunchKernelGGL(gj_unpermute, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, v.sig, v.pos,
+                       n);
   }
   return hipGetLastError();
 }
