@@ -47,6 +47,15 @@
  *  - Every call returns an hps_status; on failure hps_last_error() holds a
  *    message.  A failed call leaves the context usable; the results of a
  *    failed call are unspecified.
+ *  - Batches: a context may hold nprob independent problems on the same
+ *    leaf grid, each with its own contrast and wavenumber (the
+ *    recursive-linearization solves are uncoupled, Section 3).  They are
+ *    factored and solved together: every leaf-stage, merge-level and top
+ *    kernel runs once for all problems.  Every per-problem array then has a
+ *    leading problem index: q_nodes [nprob][npde], ufar [nprob][ndir][ntheta],
+ *    u [nprob][ndir][npde], dq and grad [nprob][npde], r [nprob][ndir][ntheta].
+ *    All problems use the same number of directions per solve.  The sine
+ *    model and the Gauss-Newton step take nprob = 1.
  */
 #ifndef HPS_H_
 #define HPS_H_
@@ -78,12 +87,13 @@ typedef struct hps_opts {
   int precision;         /* hps_precision; only HPS_FP64 */
   int host_threads;      /* threads for the per-k boundary quadrature (<= 0: auto) */
   void* stream;          /* hipStream_t for all work (NULL = default stream) */
+  int nprob;             /* independent problems on this grid (1 .. 4096); see Batches */
 } hps_opts;
 
 typedef struct hps_ctx hps_ctx;
 
 /* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
- * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream. */
+ * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1. */
 void hps_default_opts(hps_opts* o);
 
 /* Creates a context for the geometry in *opts (host-side set-up only; device
@@ -97,7 +107,7 @@ void hps_destroy(hps_ctx* ctx);
 /* Message of the last failed call on this context ("" if none). */
 const char* hps_last_error(const hps_ctx* ctx);
 
-/* Number of PDE nodes npde = nleaf^2 (p-2)^2. */
+/* Number of PDE nodes npde = nleaf^2 (p-2)^2 (per problem). */
 int64_t hps_num_nodes(const hps_ctx* ctx);
 
 /* Number of outer-boundary nodes 4 nleaf (p-2). */
@@ -114,6 +124,10 @@ hps_status hps_node_coords(const hps_ctx* ctx, double* xy_host);
  * out of the factorisation. k > 0. */
 hps_status hps_set_wavenumber(hps_ctx* ctx, double k);
 
+/* As hps_set_wavenumber with one wavenumber per problem: k_host[nprob]
+ * (problems whose wavenumber is unchanged keep their operators). */
+hps_status hps_set_wavenumbers(hps_ctx* ctx, const double* k_host);
+
 /* Factorises the discrete interior + exterior problem for the real contrast
  * q_nodes (device, npde doubles, PDE-node order) at wavenumber k > 0: leaf
  * impedance maps, the merge tree, and the inverse of the top (boundary)
@@ -121,11 +135,20 @@ hps_status hps_set_wavenumber(hps_ctx* ctx, double k);
  * HPS_ESINGULAR if a zero pivot occurred.  Invalidates earlier solves. */
 hps_status hps_factor(hps_ctx* ctx, const double* q_nodes, double k);
 
+/* hps_factor for a batch: problem b has contrast q_nodes[b][.] and
+ * wavenumber k_host[b]. */
+hps_status hps_factor_batch(hps_ctx* ctx, const double* q_nodes, const double* k_host);
+
 /* Total-field solves for ndir plane waves exp(i k x.d_m),
  * d_m = (cos a_m, sin a_m), a_m = dir_angle_host[m]; keeps the fields u_0 at
  * the PDE nodes and the boundary data on the device for far-field, jvp and
  * vjp calls.  Requires hps_factor.  1 <= ndir <= 65535. */
 hps_status hps_solve(hps_ctx* ctx, int ndir, const double* dir_angle_host);
+
+/* hps_solve for a batch with directions per problem:
+ * dir_angle_host[b * ndir + m] is direction m of problem b.  (hps_solve
+ * uses the same ndir angles for every problem.) */
+hps_status hps_solve_batch(hps_ctx* ctx, int ndir, const double* dir_angle_host);
 
 /* Scattered field at x_p = R (cos theta_p, sin theta_p), p < ntheta, for every
  * solved direction: ufar (device, complex128 [ndir][ntheta]).  The

@@ -31,7 +31,7 @@ class Opts(ctypes.Structure):
                 ("y1", ctypes.c_double), ("nleaf", ctypes.c_int), ("p", ctypes.c_int),
                 ("eta_scale", ctypes.c_double), ("keep_derivs", ctypes.c_int),
                 ("precision", ctypes.c_int), ("host_threads", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("nprob", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -57,8 +57,11 @@ SIGNATURES = [
     ("hps_num_boundary_nodes", _L, [_P]),
     ("hps_node_coords", _I, [_P, _P]),
     ("hps_set_wavenumber", _I, [_P, _D]),
+    ("hps_set_wavenumbers", _I, [_P, _P]),
     ("hps_factor", _I, [_P, _P, _D]),
+    ("hps_factor_batch", _I, [_P, _P, _P]),
     ("hps_solve", _I, [_P, _I, _P]),
+    ("hps_solve_batch", _I, [_P, _I, _P]),
     ("hps_far_field", _I, [_P, _I, _P, _D, _P]),
     ("hps_total_field", _I, [_P, _P]),
     ("hps_jvp", _I, [_P, _P, _P]),
@@ -111,10 +114,12 @@ def _dev(t, dtype, numel=None, name="array"):
 
 class Solver:
     """One HPS context: geometry fixed at construction; factor/solve/... as in
-    the C ABI (include/hps.h)."""
+    the C ABI (include/hps.h).  With nprob > 1 the context holds a batch of
+    independent problems on the same grid: per-problem arrays get a leading
+    problem axis (q [nprob, npde], far field [nprob, ndir, ntheta], ...)."""
 
     def __init__(self, nleaf=4, p=16, box=(-1.0, 1.0, -1.0, 1.0), eta_scale=1.0,
-                 keep_derivs=True, host_threads=0, stream=None):
+                 keep_derivs=True, host_threads=0, stream=None, nprob=1):
         torch = _torch()
         L = lib()
         o = Opts()
@@ -124,6 +129,7 @@ class Solver:
         o.eta_scale = float(eta_scale)
         o.keep_derivs = 1 if keep_derivs else 0
         o.host_threads = int(host_threads)
+        o.nprob = int(nprob)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -134,6 +140,7 @@ class Solver:
             raise HpsError(rc, "hps_create failed (invalid options?)")
         self._h = h
         self.nleaf, self.p, self.box = o.nleaf, o.p, (o.x0, o.x1, o.y0, o.y1)
+        self.nprob = o.nprob
         self.npde = int(L.hps_num_nodes(h))
         self.nb = int(L.hps_num_boundary_nodes(h))
         self.ndir = 0
@@ -157,28 +164,52 @@ class Solver:
         self._check(lib().hps_node_coords(self._h, xy.ctypes.data_as(ctypes.c_void_p)), "node_coords")
         return xy
 
+    def _shape(self, *dims):
+        return tuple(dims) if self.nprob == 1 else (self.nprob,) + tuple(dims)
+
     def set_wavenumber(self, k):
-        self._check(lib().hps_set_wavenumber(self._h, float(k)), "set_wavenumber")
+        """k: one wavenumber for every problem, or one per problem."""
+        kv = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.float64), (self.nprob,)))
+        self._check(lib().hps_set_wavenumbers(self._h, kv.ctypes.data_as(ctypes.c_void_p)), "set_wavenumber")
 
     def factor(self, q, k):
+        """q: [npde] (or [nprob, npde]) float64 GPU tensor; k: scalar or one per problem."""
         torch = _torch()
         self._q = q
-        self._check(lib().hps_factor(self._h, _dev(q, torch.float64, self.npde, "q"), float(k)), "factor")
-        self.k = float(k)
+        qp = _dev(q, torch.float64, self.nprob * self.npde, "q")
+        if np.ndim(k) == 0:
+            self._check(lib().hps_factor(self._h, qp, float(k)), "factor")
+            self.k = float(k)
+        else:
+            kv = np.ascontiguousarray(np.asarray(k, dtype=np.float64).ravel())
+            if kv.size != self.nprob:
+                raise ValueError(f"need {self.nprob} wavenumbers, got {kv.size}")
+            self._check(lib().hps_factor_batch(self._h, qp, kv.ctypes.data_as(ctypes.c_void_p)), "factor")
+            self.k = kv.copy()
         self.generation += 1
 
     def solve(self, angles):
-        a = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).ravel())
-        self._check(lib().hps_solve(self._h, int(a.size), a.ctypes.data_as(ctypes.c_void_p)), "solve")
-        self.ndir = int(a.size)
+        """angles: [ndir] (the same for every problem) or [nprob, ndir]."""
+        a = np.asarray(angles, dtype=np.float64)
+        if a.ndim <= 1:
+            a = np.ascontiguousarray(a.ravel())
+            self._check(lib().hps_solve(self._h, int(a.size), a.ctypes.data_as(ctypes.c_void_p)), "solve")
+            self.ndir = int(a.size)
+        else:
+            if a.shape[0] != self.nprob:
+                raise ValueError(f"need directions for {self.nprob} problems, got {a.shape[0]}")
+            a = np.ascontiguousarray(a.reshape(self.nprob, -1))
+            self._check(lib().hps_solve_batch(self._h, int(a.shape[1]), a.ctypes.data_as(ctypes.c_void_p)),
+                        "solve")
+            self.ndir = int(a.shape[1])
         self.generation += 1
 
     def far_field(self, thetas, R, out=None):
         torch = _torch()
         th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).ravel())
         if out is None:
-            out = torch.empty((self.ndir, th.size), dtype=torch.complex128, device="cuda")
-        ptr = _dev(out, torch.complex128, self.ndir * th.size, "out")
+            out = torch.empty(self._shape(self.ndir, th.size), dtype=torch.complex128, device="cuda")
+        ptr = _dev(out, torch.complex128, self.nprob * self.ndir * th.size, "out")
         self._check(lib().hps_far_field(self._h, int(th.size), th.ctypes.data_as(ctypes.c_void_p),
                                         float(R), ptr), "far_field")
         self.ntheta = int(th.size)
@@ -187,25 +218,27 @@ class Solver:
     def total_field(self, out=None):
         torch = _torch()
         if out is None:
-            out = torch.empty((self.ndir, self.npde), dtype=torch.complex128, device="cuda")
-        self._check(lib().hps_total_field(self._h, _dev(out, torch.complex128, self.ndir * self.npde, "out")),
+            out = torch.empty(self._shape(self.ndir, self.npde), dtype=torch.complex128, device="cuda")
+        self._check(lib().hps_total_field(self._h, _dev(out, torch.complex128,
+                                                        self.nprob * self.ndir * self.npde, "out")),
                     "total_field")
         return out
 
     def jvp(self, dq, out=None):
         torch = _torch()
         if out is None:
-            out = torch.empty((self.ndir, self.ntheta), dtype=torch.complex128, device="cuda")
-        self._check(lib().hps_jvp(self._h, _dev(dq, torch.float64, self.npde, "dq"),
-                                  _dev(out, torch.complex128, self.ndir * self.ntheta, "out")), "jvp")
+            out = torch.empty(self._shape(self.ndir, self.ntheta), dtype=torch.complex128, device="cuda")
+        self._check(lib().hps_jvp(self._h, _dev(dq, torch.float64, self.nprob * self.npde, "dq"),
+                                  _dev(out, torch.complex128, self.nprob * self.ndir * self.ntheta, "out")),
+                    "jvp")
         return out
 
     def vjp(self, r, out=None):
         torch = _torch()
         if out is None:
-            out = torch.empty(self.npde, dtype=torch.float64, device="cuda")
-        self._check(lib().hps_vjp(self._h, _dev(r, torch.complex128, self.ndir * self.ntheta, "r"),
-                                  _dev(out, torch.float64, self.npde, "grad")), "vjp")
+            out = torch.empty(self._shape(self.npde), dtype=torch.float64, device="cuda")
+        self._check(lib().hps_vjp(self._h, _dev(r, torch.complex128, self.nprob * self.ndir * self.ntheta, "r"),
+                                  _dev(out, torch.float64, self.nprob * self.npde, "grad")), "vjp")
         return out
 
     def sine_eval(self, coef, out=None):

@@ -24,6 +24,17 @@ hipError_t zgemm_rowmask(hipStream_t st, int opA, int opB, int M, int N, int K, 
                          double2 beta, double2* C, ll ldc, ll sC, const int* rpos, ll srp,
                          int plo, int phi, int batch);
 
+// zgemm whose A / B operand for batch entry b is number b / adiv (b / bdiv):
+// one operand shared by consecutive groups of the batch.
+hipError_t zgemm_div(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
+                     const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB,
+                     int bdiv, double2 beta, double2* C, ll ldc, ll sC, int batch);
+// Both of the above.
+hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
+                      const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB,
+                      int bdiv, double2 beta, double2* C, ll ldc, ll sC, const int* rpos, ll srp,
+                      int plo, int phi, int batch);
+
 // Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
 size_t zinv_workspace(int n, int batch);
 

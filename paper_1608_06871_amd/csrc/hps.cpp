@@ -100,11 +100,13 @@ struct hps_ctx {
   std::string err;
   int nthreads = 1;
   int n = 0, nb = 0;
+  int P = 1;  // problems in the batch (same grid, own q and k)
 
-  // per wavenumber
+  // per wavenumber (one slot per problem)
   bool have_k = false;
-  double k = 0.0, eta = 0.0;
+  std::vector<double> kv, etav;
   DBuf dA0, dMout, dBop, dA1, dA2, dbnode;
+  DBuf dPk;  // device [k (P) | k^2 (P) | eta (P)]
   std::vector<DBuf> didx;  // 4 index arrays per level
 
   // factorisation
@@ -183,68 +185,141 @@ void upload(DBuf& b, const void* src, size_t bytes, hipStream_t st) {
   CK(hipStreamSynchronize(st));
 }
 
-void set_wavenumber(hps_ctx* c, double k) {
-  require(std::isfinite(k) && k > 0.0, HPS_EINVAL, "wavenumber must be positive and finite");
-  const auto t0 = std::chrono::steady_clock::now();
-  const Geometry& g = c->g;
-  const double eta = (c->o.eta_scale > 0.0 ? c->o.eta_scale : 1.0) * k;
-  const int n = c->n, ne = g.ne, nb = c->nb;
+// Host-side operators of one wavenumber: the leaf base matrix and outgoing
+// map (column-major), the boundary right-hand-side operator [S, -(K - I/2)]
+// and the top blocks A1, A2.
+struct WaveOps {
+  std::vector<cplx> A0, Mout, Bop, A1, A2;
+};
 
+void wave_ops(const hps_ctx* c, double k, double eta, WaveOps& w) {
+  const Geometry& g = c->g;
+  const int n = c->n, ne = g.ne, nb = c->nb;
   std::vector<cplx> A0, Mout;
   leaf_operators(g, k, eta, A0, Mout);
-  std::vector<cplx> A0c((size_t)n * n), Mc((size_t)ne * n);
+  w.A0.assign((size_t)n * n, cplx());
+  w.Mout.assign((size_t)ne * n, cplx());
   for (int r = 0; r < n; ++r)
-    for (int j = 0; j < n; ++j) A0c[r + (size_t)j * n] = A0[(size_t)r * n + j];
+    for (int j = 0; j < n; ++j) w.A0[r + (size_t)j * n] = A0[(size_t)r * n + j];
   for (int e = 0; e < ne; ++e)
-    for (int j = 0; j < n; ++j) Mc[e + (size_t)j * ne] = Mout[(size_t)e * n + j];
-
+    for (int j = 0; j < n; ++j) w.Mout[e + (size_t)j * ne] = Mout[(size_t)e * n + j];
   std::vector<double> tx(nb), ty(nb);
-  std::vector<double> bn(4 * (size_t)nb);
   for (int i = 0; i < nb; ++i) {
-    const BoundaryNode& b = g.root[i];
-    tx[i] = b.x;
-    ty[i] = b.y;
-    bn[4 * i] = b.x;
-    bn[4 * i + 1] = b.y;
-    bn[4 * i + 2] = b.nx;
-    bn[4 * i + 3] = b.ny;
+    tx[i] = g.root[i].x;
+    ty[i] = g.root[i].y;
   }
   std::vector<cplx> S, K;
   layer_moments(g, k, tx, ty, S, K, c->nthreads);
   const cplx cinv = cplx(0.0, -1.0 / (2.0 * eta));  // 1 / (2 i eta)
-  std::vector<cplx> Bop((size_t)nb * 2 * nb), A1((size_t)nb * nb), A2((size_t)nb * nb);
+  w.Bop.assign((size_t)nb * 2 * nb, cplx());
+  w.A1.assign((size_t)nb * nb, cplx());
+  w.A2.assign((size_t)nb * nb, cplx());
   for (int i = 0; i < nb; ++i)
     for (int j = 0; j < nb; ++j) {
-      const cplx s = S[(size_t)i * nb + j];
+      const cplx sv = S[(size_t)i * nb + j];
       const cplx kmi = K[(size_t)i * nb + j] - (i == j ? 0.5 : 0.0);
-      Bop[i + (size_t)j * nb] = s;
-      Bop[i + (size_t)(nb + j) * nb] = -kmi;
-      A1[i + (size_t)j * nb] = 0.5 * s - cinv * kmi;
-      A2[i + (size_t)j * nb] = 0.5 * s + cinv * kmi;
+      w.Bop[i + (size_t)j * nb] = sv;
+      w.Bop[i + (size_t)(nb + j) * nb] = -kmi;
+      w.A1[i + (size_t)j * nb] = 0.5 * sv - cinv * kmi;
+      w.A2[i + (size_t)j * nb] = 0.5 * sv + cinv * kmi;
     }
-  upload(c->dA0, A0c.data(), A0c.size() * sizeof(cplx), c->st);
-  upload(c->dMout, Mc.data(), Mc.size() * sizeof(cplx), c->st);
-  upload(c->dBop, Bop.data(), Bop.size() * sizeof(cplx), c->st);
-  upload(c->dA1, A1.data(), A1.size() * sizeof(cplx), c->st);
-  upload(c->dA2, A2.data(), A2.size() * sizeof(cplx), c->st);
-  upload(c->dbnode, bn.data(), bn.size() * sizeof(double), c->st);
-  c->k = k;
-  c->eta = eta;
+}
+
+void upload_at(DBuf& b, size_t off_bytes, const void* src, size_t bytes, hipStream_t st) {
+  CK(hipMemcpyAsync((char*)b.p + off_bytes, src, bytes, hipMemcpyHostToDevice, st));
+  CK(hipStreamSynchronize(st));
+}
+
+void set_wavenumbers(hps_ctx* c, const double* k) {
+  const int P = c->P;
+  for (int b = 0; b < P; ++b)
+    require(std::isfinite(k[b]) && k[b] > 0.0, HPS_EINVAL, "wavenumbers must be positive and finite");
+  const auto t0 = std::chrono::steady_clock::now();
+  const Geometry& g = c->g;
+  const int n = c->n, ne = g.ne, nb = c->nb;
+  const double es = c->o.eta_scale > 0.0 ? c->o.eta_scale : 1.0;
+  const size_t sA0 = (size_t)n * n, sMo = (size_t)ne * n, sBo = (size_t)nb * 2 * nb, sA = (size_t)nb * nb;
+  if (!c->have_k) {
+    c->dA0.ensure(zb(sA0 * P));
+    c->dMout.ensure(zb(sMo * P));
+    c->dBop.ensure(zb(sBo * P));
+    c->dA1.ensure(zb(sA * P));
+    c->dA2.ensure(zb(sA * P));
+    c->kv.assign(P, 0.0);
+    c->etav.assign(P, 0.0);
+    std::vector<double> bn(4 * (size_t)nb);
+    for (int i = 0; i < nb; ++i) {
+      const BoundaryNode& bd = g.root[i];
+      bn[4 * i] = bd.x;
+      bn[4 * i + 1] = bd.y;
+      bn[4 * i + 2] = bd.nx;
+      bn[4 * i + 3] = bd.ny;
+    }
+    upload(c->dbnode, bn.data(), bn.size() * sizeof(double), c->st);
+  }
+  bool changed = false;
+  for (int b = 0; b < P; ++b) {
+    if (c->have_k && k[b] == c->kv[b]) continue;
+    changed = true;
+    // reuse the operators of an earlier problem with the same wavenumber
+    int src = -1;
+    for (int a = 0; a < P && src < 0; ++a)
+      if (a != b && c->have_k && c->kv[a] == k[b]) src = a;
+    for (int a = 0; a < b && src < 0; ++a)
+      if (k[a] == k[b]) src = a;
+    if (src >= 0) {
+      CK(hipMemcpyAsync(c->dA0.z() + sA0 * b, c->dA0.z() + sA0 * src, zb(sA0), hipMemcpyDeviceToDevice, c->st));
+      CK(hipMemcpyAsync(c->dMout.z() + sMo * b, c->dMout.z() + sMo * src, zb(sMo), hipMemcpyDeviceToDevice,
+                        c->st));
+      CK(hipMemcpyAsync(c->dBop.z() + sBo * b, c->dBop.z() + sBo * src, zb(sBo), hipMemcpyDeviceToDevice,
+                        c->st));
+      CK(hipMemcpyAsync(c->dA1.z() + sA * b, c->dA1.z() + sA * src, zb(sA), hipMemcpyDeviceToDevice, c->st));
+      CK(hipMemcpyAsync(c->dA2.z() + sA * b, c->dA2.z() + sA * src, zb(sA), hipMemcpyDeviceToDevice, c->st));
+    } else {
+      WaveOps w;
+      wave_ops(c, k[b], es * k[b], w);
+      upload_at(c->dA0, zb(sA0 * b), w.A0.data(), zb(sA0), c->st);
+      upload_at(c->dMout, zb(sMo * b), w.Mout.data(), zb(sMo), c->st);
+      upload_at(c->dBop, zb(sBo * b), w.Bop.data(), zb(sBo), c->st);
+      upload_at(c->dA1, zb(sA * b), w.A1.data(), zb(sA), c->st);
+      upload_at(c->dA2, zb(sA * b), w.A2.data(), zb(sA), c->st);
+    }
+    c->kv[b] = k[b];
+    c->etav[b] = es * k[b];
+  }
+  std::vector<double> pk(3 * (size_t)P);
+  for (int b = 0; b < P; ++b) {
+    pk[b] = c->kv[b];
+    pk[P + b] = c->kv[b] * c->kv[b];
+    pk[2 * P + b] = c->etav[b];
+  }
+  upload(c->dPk, pk.data(), pk.size() * sizeof(double), c->st);
   c->have_k = true;
-  c->factored = false;
-  c->solved = false;
-  c->have_meas = false;
+  if (changed) {
+    c->factored = false;
+    c->solved = false;
+    c->have_meas = false;
+  }
   c->t_wave = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+void set_wavenumber(hps_ctx* c, double k) {
+  std::vector<double> kv(c->P, k);
+  set_wavenumbers(c, kv.data());
+}
+
+// All per-level counts below are for the whole batch: the P problems' trees
+// form a forest whose nodes are numbered problem-major, so at every level
+// node i has children 2 i and 2 i + 1 one level down, exactly as in one tree.
 void plan_factor_buffers(hps_ctx* c) {
   const Geometry& g = c->g;
-  const size_t nl = g.nleaf, n = c->n, ne = g.ne, mi = g.mi, nb = c->nb;
+  const size_t P = c->P;
+  const size_t nl = (size_t)g.nleaf * P, n = c->n, ne = g.ne, mi = g.mi, nb = c->nb;
   size_t zws = zinv_workspace((int)n, (int)nl);
   size_t rmax = nl * ne * ne, blk = 0, w = 0, q = 0, v = 0;
   for (int l = 1; l <= g.nlev; ++l) {
-    const LevelPattern& P = g.lev[l];
-    const size_t cnt = P.count, m = P.m, s = P.s, np = P.np;
+    const LevelPattern& L = g.lev[l];
+    const size_t cnt = L.count * P, m = L.m, s = L.s, np = L.np;
     zws = std::max(zws, zinv_workspace((int)s, (int)cnt));
     rmax = std::max(rmax, cnt * np * np);
     blk = std::max(blk, cnt * (2 * m * s + s * m + 2 * s * s));
@@ -252,8 +327,8 @@ void plan_factor_buffers(hps_ctx* c) {
     q = std::max(q, cnt * 2 * s * m);
     v = std::max(v, cnt * 2 * s * s);
   }
-  zws = std::max(zws, zinv_workspace((int)nb, 1));
-  c->sA.ensure(zb(std::max(nl * n * n, nb * nb)));
+  zws = std::max(zws, zinv_workspace((int)nb, (int)P));
+  c->sA.ensure(zb(std::max(nl * n * n, P * nb * nb)));
   c->sInv.ensure(zb(nl * n * n));
   c->sZws.ensure(zws);
   c->sR0.ensure(zb(rmax));
@@ -265,50 +340,55 @@ void plan_factor_buffers(hps_ctx* c) {
   c->sVin.ensure(zb(v));
   c->sV.ensure(zb(v));
   c->sTmp.ensure(zb(v));
-  c->sInfo.ensure(sizeof(int) * std::max<size_t>(nl, 1));
+  c->sInfo.ensure(sizeof(int) * std::max<size_t>(nl, P));
   c->dY.ensure(zb(nl * mi * ne));
   if (c->o.keep_derivs) c->dH.ensure(zb(nl * ne * mi));
-  c->dRroot.ensure(zb(nb * nb));
-  c->dZinv.ensure(zb(nb * nb));
+  c->dRroot.ensure(zb(P * nb * nb));
+  c->dZinv.ensure(zb(P * nb * nb));
   c->dD.resize(g.nlev + 1);
   c->dU.resize(g.nlev + 1);
   for (int l = 1; l <= g.nlev; ++l) {
-    const LevelPattern& P = g.lev[l];
-    c->dD[l].ensure(zb((size_t)P.count * 2 * P.s * 2 * P.m));
-    if (c->o.keep_derivs) c->dU[l].ensure(zb((size_t)P.count * 2 * P.m * 2 * P.s));
+    const LevelPattern& L = g.lev[l];
+    c->dD[l].ensure(zb(P * L.count * 2 * L.s * 2 * L.m));
+    if (c->o.keep_derivs) c->dU[l].ensure(zb(P * L.count * 2 * L.m * 2 * L.s));
   }
 }
 
-void factor(hps_ctx* c, const double* q, double k) {
+void factor(hps_ctx* c, const double* q, const double* kv) {
   require(q != nullptr, HPS_EINVAL, "q_nodes is NULL");
-  if (!c->have_k || k != c->k) set_wavenumber(c, k);
+  bool same = c->have_k;
+  for (int b = 0; b < c->P && same; ++b) same = (kv[b] == c->kv[b]);
+  if (!same) set_wavenumbers(c, kv);
   plan_factor_buffers(c);
   const Geometry& g = c->g;
   hipStream_t st = c->st;
-  const int n = c->n, ne = g.ne, mi = g.mi, nl = g.nleaf, nb = c->nb;
+  const int P = c->P;
+  const int n = c->n, ne = g.ne, mi = g.mi, lpp = g.nleaf, nl = g.nleaf * P, nb = c->nb;
   const ll nn = (ll)n * n;
+  const double* k2v = c->dPk.d() + P;
   c->factored = false;
   c->solved = false;
   mark(c, 0, 0);
-  CK(hipMemsetAsync(c->sInfo.p, 0, sizeof(int) * nl, st));
+  const int ninfo = std::max(nl, P);
+  CK(hipMemsetAsync(c->sInfo.p, 0, sizeof(int) * ninfo, st));
 
-  // leaf stage
-  CK(leaf_assemble(st, c->dA0.z(), q, k * k, n, mi, c->sA.z(), nl));
+  // leaf stage (all leaves of all problems)
+  CK(leaf_assemble(st, c->dA0.z(), nn, q, k2v, n, mi, c->sA.z(), nl, lpp));
   CK(zinv(st, n, c->sA.z(), n, nn, c->sInv.z(), n, nn, nl, c->sZws.p, c->sInfo.i()));
   const double2* inv_edge = c->sInv.z() + (ll)mi * n;  // columns for the edge unknowns
   CK(gather2d(st, mi, ne, inv_edge, n, nn, nullptr, nullptr, c->dY.z(), mi, (ll)mi * ne, 1.0, nl));
   double2* Rc = c->sR0.z();
-  CK(zgemm(st, OP_N, OP_N, ne, ne, n, ONE, c->dMout.z(), ne, 0, inv_edge, n, nn, ZERO, Rc, ne,
-           (ll)ne * ne, nl));
+  const ll smo = (ll)ne * n;  // one outgoing map per problem, shared by its leaves
+  CK(zgemm_div(st, OP_N, OP_N, ne, ne, n, ONE, c->dMout.z(), ne, smo, lpp, inv_edge, n, nn, 1, ZERO, Rc,
+               ne, (ll)ne * ne, nl));
   if (c->o.keep_derivs)
-    CK(zgemm(st, OP_N, OP_N, ne, mi, n, ONE, c->dMout.z(), ne, 0, c->sInv.z(), n, nn, ZERO,
-             c->dH.z(), ne, (ll)ne * mi, nl));
+    CK(zgemm_div(st, OP_N, OP_N, ne, mi, n, ONE, c->dMout.z(), ne, smo, lpp, c->sInv.z(), n, nn, 1, ZERO,
+                 c->dH.z(), ne, (ll)ne * mi, nl));
 
   // merge tree
   for (int l = 1; l <= g.nlev; ++l) {
-    const LevelPattern& P = g.lev[l];
-    const int cnt = P.count, m = P.m, s = P.s, nc = P.nc, np = P.np;
-    const int* i1a = c->didx[4 * l].i();
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;    const int* i1a = c->didx[4 * l].i();
     const int* i3a = c->didx[4 * l + 1].i();
     const int* i2b = c->didx[4 * l + 2].i();
     const int* i3b = c->didx[4 * l + 3].i();
@@ -372,16 +452,17 @@ void factor(hps_ctx* c, const double* q, double k) {
     Rc = Rn;
   }
 
-  // top: Z = A1 + A2 R_root, inverted
-  CK(hipMemcpyAsync(c->dRroot.p, Rc, zb((size_t)nb * nb), hipMemcpyDeviceToDevice, st));
+  // top: Z = A1 + A2 R_root per problem, inverted
+  const ll sbb = (ll)nb * nb;
+  CK(hipMemcpyAsync(c->dRroot.p, Rc, zb((size_t)P * sbb), hipMemcpyDeviceToDevice, st));
   double2* Z = c->sA.z();
-  CK(hipMemcpyAsync(Z, c->dA1.p, zb((size_t)nb * nb), hipMemcpyDeviceToDevice, st));
-  CK(zgemm(st, OP_N, OP_N, nb, nb, nb, ONE, c->dA2.z(), nb, 0, c->dRroot.z(), nb, 0, ONE, Z, nb, 0,
-           1));
-  CK(zinv(st, nb, Z, nb, 0, c->dZinv.z(), nb, 0, 1, c->sZws.p, c->sInfo.i()));
+  CK(hipMemcpyAsync(Z, c->dA1.p, zb((size_t)P * sbb), hipMemcpyDeviceToDevice, st));
+  CK(zgemm(st, OP_N, OP_N, nb, nb, nb, ONE, c->dA2.z(), nb, sbb, c->dRroot.z(), nb, sbb, ONE, Z, nb, sbb,
+           P));
+  CK(zinv(st, nb, Z, nb, sbb, c->dZinv.z(), nb, sbb, P, c->sZws.p, c->sInfo.i()));
   mark(c, 0, 1);
-  std::vector<int> info(nl);
-  CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * nl, hipMemcpyDeviceToHost, st));
+  std::vector<int> info(ninfo);
+  CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * ninfo, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   c->singular = 0;
   for (int v : info) c->singular |= (v != 0);
@@ -391,29 +472,30 @@ void factor(hps_ctx* c, const double* q, double k) {
 
 void plan_sweep_buffers(hps_ctx* c, int M) {
   const Geometry& g = c->g;
+  const size_t P = c->P;
   size_t fmax = (size_t)g.nleaf * g.ne, f3 = 0;
   for (int l = 1; l <= g.nlev; ++l) {
-    const LevelPattern& P = g.lev[l];
-    fmax = std::max(fmax, (size_t)P.count * P.np);
-    f3 = std::max(f3, (size_t)P.count * 2 * P.s);
+    const LevelPattern& L = g.lev[l];
+    fmax = std::max(fmax, (size_t)L.count * L.np);
+    f3 = std::max(f3, (size_t)L.count * 2 * L.s);
   }
   fmax = std::max(fmax, (size_t)c->nb);
-  c->dF0.ensure(zb(fmax * M));
-  c->dF1.ensure(zb(fmax * M));
-  c->dF3.ensure(zb(std::max<size_t>(f3, 1) * M));
-  c->dG.ensure(zb((size_t)2 * c->nb * M));
-  c->dRhs.ensure(zb((size_t)c->nb * M));
-  c->dg.ensure(zb((size_t)c->nb * M));
-  c->dST.ensure(zb((size_t)2 * c->nb * M));
-  c->du0.ensure(zb((size_t)g.nleaf * g.mi * M));
+  c->dF0.ensure(zb(P * fmax * M));
+  c->dF1.ensure(zb(P * fmax * M));
+  c->dF3.ensure(zb(P * std::max<size_t>(f3, 1) * M));
+  c->dG.ensure(zb(P * 2 * c->nb * M));
+  c->dRhs.ensure(zb(P * c->nb * M));
+  c->dg.ensure(zb(P * c->nb * M));
+  c->dST.ensure(zb(P * 2 * c->nb * M));
+  c->du0.ensure(zb(P * g.nleaf * g.mi * M));
 }
 
 // Scatter parent data [f1; f2] and shared-edge data [f3a; f3b] into the two
 // children's boundary orderings (one level of the down-sweep; also the
 // adjoint of the up-sweep's gathers).
 void scatter_children(hps_ctx* c, int l, const double2* Fp, const double2* F3, double2* Fch, int M) {
-  const LevelPattern& P = c->g.lev[l];
-  const int cnt = P.count, m = P.m, s = P.s, nc = P.nc, np = P.np;
+  const LevelPattern& L = c->g.lev[l];
+  const int cnt = L.count * c->P, m = L.m, s = L.s, nc = L.nc, np = L.np;
   const ll sp = (ll)np * M, s3 = 2LL * s * M, sc = 2LL * nc * M;
   hipStream_t st = c->st;
   CK(scatter_rows(st, m, M, Fp, np, sp, c->didx[4 * l].i(), Fch, nc, sc, cnt));
@@ -422,42 +504,47 @@ void scatter_children(hps_ctx* c, int l, const double2* Fp, const double2* F3, d
   CK(scatter_rows(st, s, M, F3 + s, 2 * s, s3, c->didx[4 * l + 3].i(), Fch + (ll)nc * M, nc, sc, cnt));
 }
 
+// ang: P x M direction angles (problem-major).
 void solve(hps_ctx* c, int M, const double* ang) {
   require(c->factored, HPS_ESTATE, "hps_solve before hps_factor");
   require(M >= 1 && M <= 65535 && ang != nullptr, HPS_EINVAL, "bad direction list");
-  for (int i = 0; i < M; ++i) require(std::isfinite(ang[i]), HPS_EINVAL, "non-finite angle");
+  const int P = c->P;
+  for (ll i = 0; i < (ll)M * P; ++i) require(std::isfinite(ang[i]), HPS_EINVAL, "non-finite angle");
   plan_sweep_buffers(c, M);
   const Geometry& g = c->g;
   hipStream_t st = c->st;
   const int nb = c->nb;
-  c->h_dirs.resize(2 * (size_t)M);
-  for (int i = 0; i < M; ++i) {
+  c->h_dirs.resize(2 * (size_t)M * P);
+  for (ll i = 0; i < (ll)M * P; ++i) {
     c->h_dirs[2 * i] = std::cos(ang[i]);
     c->h_dirs[2 * i + 1] = std::sin(ang[i]);
   }
   upload(c->d_dirs, c->h_dirs.data(), c->h_dirs.size() * sizeof(double), st);
   c->solved = false;
   mark(c, 1, 0);
-  CK(incident(st, (const double4*)c->dbnode.p, nb, c->d_dirs.z(), M, c->k, c->dG.z()));
-  CK(zgemm(st, OP_N, OP_N, nb, M, 2 * nb, ONE, c->dBop.z(), nb, 0, c->dG.z(), 2 * nb, 0, ZERO,
-           c->dRhs.z(), nb, 0, 1));
+  const double* kv = c->dPk.d();
+  const double* etav = c->dPk.d() + 2 * P;
+  const ll sG = 2LL * nb * M, sF = (ll)nb * M, sbb = (ll)nb * nb;
+  CK(incident(st, (const double4*)c->dbnode.p, nb, c->d_dirs.z(), M, kv, c->dG.z(), P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, 2 * nb, ONE, c->dBop.z(), nb, 2 * sbb, c->dG.z(), 2 * nb, sG, ZERO,
+           c->dRhs.z(), nb, sF, P));
   double2* Fc = c->dF0.z();
   double2* Fo = c->dF1.z();
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, 0, c->dRhs.z(), nb, 0, ZERO, Fc, nb, 0,
-           1));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, 0, Fc, nb, 0, ZERO, c->dg.z(), nb, 0,
-           1));
-  CK(boundary_st(st, Fc, c->dg.z(), c->dG.z(), nb, M, c->eta, c->dST.z()));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, sbb, c->dRhs.z(), nb, sF, ZERO, Fc, nb, sF,
+           P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, Fc, nb, sF, ZERO, c->dg.z(), nb, sF,
+           P));
+  CK(boundary_st(st, Fc, c->dg.z(), c->dG.z(), nb, M, etav, c->dST.z(), P));
   for (int l = g.nlev; l >= 1; --l) {
-    const LevelPattern& P = g.lev[l];
-    const int cnt = P.count, m = P.m, s = P.s, np = P.np;
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * P, m = L.m, s = L.s, np = L.np;
     CK(zgemm(st, OP_N, OP_N, 2 * s, M, 2 * m, ONE, c->dD[l].z(), 2 * s, 4LL * m * s, Fc, np,
              (ll)np * M, ZERO, c->dF3.z(), 2 * s, 2LL * s * M, cnt));
     scatter_children(c, l, Fc, c->dF3.z(), Fo, M);
     std::swap(Fc, Fo);
   }
   CK(zgemm(st, OP_N, OP_N, g.mi, M, g.ne, ONE, c->dY.z(), g.mi, (ll)g.mi * g.ne, Fc, g.ne,
-           (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf));
+           (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf * P));
   mark(c, 1, 1);
   c->ndir = M;
   c->solved = true;
@@ -479,16 +566,28 @@ void set_measurement(hps_ctx* c, int nt, const double* th, double R) {
     require(std::max(std::fabs(tx[i] - xc), std::fabs(ty[i] - yc)) > half * (1.0 + 1e-12),
             HPS_EINVAL, "measurement point inside Omega");
   }
-  std::vector<cplx> PS, PD;
-  layer_moments(g, c->k, tx, ty, PS, PD, c->nthreads);
-  const int nb = c->nb;
-  std::vector<cplx> Phi((size_t)nt * 2 * nb);
-  for (int p = 0; p < nt; ++p)
-    for (int j = 0; j < nb; ++j) {
-      Phi[p + (size_t)j * nt] = PD[(size_t)p * nb + j];
-      Phi[p + (size_t)(nb + j) * nt] = -PS[(size_t)p * nb + j];
+  const int nb = c->nb, P = c->P;
+  const size_t sphi = (size_t)nt * 2 * nb;
+  c->dPhi.ensure(zb(sphi * P));
+  for (int b = 0; b < P; ++b) {
+    int src = -1;
+    for (int a = 0; a < b && src < 0; ++a)
+      if (c->kv[a] == c->kv[b]) src = a;
+    if (src >= 0) {
+      CK(hipMemcpyAsync(c->dPhi.z() + sphi * b, c->dPhi.z() + sphi * src, zb(sphi), hipMemcpyDeviceToDevice,
+                        c->st));
+      continue;
     }
-  upload(c->dPhi, Phi.data(), Phi.size() * sizeof(cplx), c->st);
+    std::vector<cplx> PS, PD;
+    layer_moments(g, c->kv[b], tx, ty, PS, PD, c->nthreads);
+    std::vector<cplx> Phi(sphi);
+    for (int p = 0; p < nt; ++p)
+      for (int j = 0; j < nb; ++j) {
+        Phi[p + (size_t)j * nt] = PD[(size_t)p * nb + j];
+        Phi[p + (size_t)(nb + j) * nt] = -PS[(size_t)p * nb + j];
+      }
+    upload_at(c->dPhi, zb(sphi * b), Phi.data(), zb(sphi), c->st);
+  }
   c->theta.assign(th, th + nt);
   c->R = R;
   c->have_meas = true;
@@ -499,10 +598,10 @@ void far_field(hps_ctx* c, int nt, const double* th, double R, double* out) {
   require(nt >= 1 && th != nullptr && out != nullptr && std::isfinite(R) && R > 0.0, HPS_EINVAL,
           "bad measurement arguments");
   set_measurement(c, nt, th, R);
-  const int nb = c->nb, M = c->ndir;
+  const int nb = c->nb, M = c->ndir, P = c->P;
   mark(c, 2, 0);
-  CK(zgemm(c->st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, 0, c->dST.z(), 2 * nb, 0, ZERO,
-           (double2*)out, nt, 0, 1));
+  CK(zgemm(c->st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, (ll)nt * 2 * nb, c->dST.z(), 2 * nb,
+           2LL * nb * M, ZERO, (double2*)out, nt, (ll)nt * M, P));
   mark(c, 2, 1);
 }
 
@@ -512,19 +611,21 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
   require(dq != nullptr && out != nullptr, HPS_EINVAL, "NULL argument");
   const Geometry& g = c->g;
   hipStream_t st = c->st;
-  const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size();
-  c->sB.ensure(zb((size_t)g.nleaf * g.mi * M));
-  c->sST2.ensure(zb((size_t)2 * nb * M));
-  c->sW2.ensure(zb((size_t)nb * M));
+  const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size(), P = c->P;
+  const int nl = g.nleaf * P;
+  const ll sF = (ll)nb * M, sbb = (ll)nb * nb;
+  c->sB.ensure(zb((size_t)nl * g.mi * M));
+  c->sST2.ensure(zb((size_t)2 * P * nb * M));
+  c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 3, 0);
-  CK(body_load(st, dq, c->du0.z(), c->k * c->k, g.mi, M, g.nleaf, c->sB.z()));
+  CK(body_load(st, dq, c->du0.z(), c->dPk.d() + P, g.mi, M, nl, g.nleaf, c->sB.z()));
   double2* Hc = c->dF0.z();
   double2* Ho = c->dF1.z();
   CK(zgemm(st, OP_N, OP_N, g.ne, M, g.mi, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, c->sB.z(), g.mi,
-           (ll)g.mi * M, ZERO, Hc, g.ne, (ll)g.ne * M, g.nleaf));
+           (ll)g.mi * M, ZERO, Hc, g.ne, (ll)g.ne * M, nl));
   for (int l = 1; l <= g.nlev; ++l) {
-    const LevelPattern& P = g.lev[l];
-    const int cnt = P.count, m = P.m, s = P.s, nc = P.nc, np = P.np;
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;
     const ll sc = 2LL * nc * M, sp = (ll)np * M, s3 = 2LL * s * M;
     const double2* Ha = Hc;
     const double2* Hb = Hc + (ll)nc * M;
@@ -538,14 +639,15 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
     std::swap(Hc, Ho);
   }
   // root: Z f = -A2 h,  g = R f + h
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA2.z(), nb, 0, Hc, nb, 0, ZERO, c->sW2.z(), nb, 0, 1));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dZinv.z(), nb, 0, c->sW2.z(), nb, 0, ZERO, Ho, nb, 0,
-           1));
-  CK(hipMemcpyAsync(c->dg.p, Hc, zb((size_t)nb * M), hipMemcpyDeviceToDevice, st));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, 0, Ho, nb, 0, ONE, c->dg.z(), nb, 0, 1));
-  CK(boundary_st(st, Ho, c->dg.z(), nullptr, nb, M, c->eta, c->sST2.z()));
-  CK(zgemm(st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, 0, c->sST2.z(), 2 * nb, 0, ZERO,
-           (double2*)out, nt, 0, 1));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA2.z(), nb, sbb, Hc, nb, sF, ZERO, c->sW2.z(), nb, sF, P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dZinv.z(), nb, sbb, c->sW2.z(), nb, sF, ZERO, Ho, nb, sF,
+           P));
+  CK(hipMemcpyAsync(c->dg.p, Hc, zb((size_t)P * nb * M), hipMemcpyDeviceToDevice, st));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, Ho, nb, sF, ONE, c->dg.z(), nb, sF,
+           P));
+  CK(boundary_st(st, Ho, c->dg.z(), nullptr, nb, M, c->dPk.d() + 2 * P, c->sST2.z(), P));
+  CK(zgemm(st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, (ll)nt * 2 * nb, c->sST2.z(), 2 * nb,
+           2LL * nb * M, ZERO, (double2*)out, nt, (ll)nt * M, P));
   mark(c, 3, 1);
 }
 
@@ -555,37 +657,40 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
   require(r != nullptr && grad != nullptr, HPS_EINVAL, "NULL argument");
   const Geometry& g = c->g;
   hipStream_t st = c->st;
-  const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size();
-  c->sB.ensure(zb((size_t)g.nleaf * g.mi * M));
-  c->sST2.ensure(zb((size_t)2 * nb * M));
-  c->sW2.ensure(zb((size_t)nb * M));
+  const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size(), P = c->P;
+  const int nl = g.nleaf * P;
+  const ll sF = (ll)nb * M, sbb = (ll)nb * nb;
+  c->sB.ensure(zb((size_t)nl * g.mi * M));
+  c->sST2.ensure(zb((size_t)2 * P * nb * M));
+  c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 4, 0);
   // [sbar; tbar] = Phi^H r
-  CK(zgemm(st, OP_C, OP_N, 2 * nb, M, nt, ONE, c->dPhi.z(), nt, 0, (const double2*)r, nt, 0, ZERO,
-           c->sST2.z(), 2 * nb, 0, 1));
+  CK(zgemm(st, OP_C, OP_N, 2 * nb, M, nt, ONE, c->dPhi.z(), nt, (ll)nt * 2 * nb, (const double2*)r, nt,
+           (ll)nt * M, ZERO, c->sST2.z(), 2 * nb, 2LL * nb * M, P));
   double2* Hc = c->dF0.z();
   double2* Ho = c->dF1.z();
   double2* fb = Ho;
   double2* gb = Hc;
-  CK(boundary_st_adj(st, c->sST2.z(), nb, M, c->eta, fb, gb));
-  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, 0, gb, nb, 0, ONE, fb, nb, 0, 1));
-  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, 0, fb, nb, 0, ZERO, c->sW2.z(), nb, 0, 1));
-  CK(zgemm(st, OP_C, OP_N, nb, M, nb, MONE, c->dA2.z(), nb, 0, c->sW2.z(), nb, 0, ONE, gb, nb, 0, 1));
+  CK(boundary_st_adj(st, c->sST2.z(), nb, M, c->dPk.d() + 2 * P, fb, gb, P));
+  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, gb, nb, sF, ONE, fb, nb, sF, P));
+  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, sbb, fb, nb, sF, ZERO, c->sW2.z(), nb, sF, P));
+  CK(zgemm(st, OP_C, OP_N, nb, M, nb, MONE, c->dA2.z(), nb, sbb, c->sW2.z(), nb, sF, ONE, gb, nb, sF, P));
   for (int l = g.nlev; l >= 1; --l) {
-    const LevelPattern& P = g.lev[l];
-    const int cnt = P.count, m = P.m, s = P.s, np = P.np;
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * P, m = L.m, s = L.s, np = L.np;
     CK(zgemm(st, OP_C, OP_N, 2 * s, M, np, ONE, c->dU[l].z(), np, 4LL * m * s, Hc, np, (ll)np * M,
              ZERO, c->dF3.z(), 2 * s, 2LL * s * M, cnt));
     scatter_children(c, l, Hc, c->dF3.z(), Ho, M);
     std::swap(Hc, Ho);
   }
   CK(zgemm(st, OP_C, OP_N, g.mi, M, g.ne, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, Hc, g.ne,
-           (ll)g.ne * M, ZERO, c->sB.z(), g.mi, (ll)g.mi * M, g.nleaf));
-  CK(grad_reduce(st, c->du0.z(), c->sB.z(), c->k * c->k, g.mi, M, g.nleaf, grad));
+           (ll)g.ne * M, ZERO, c->sB.z(), g.mi, (ll)g.mi * M, nl));
+  CK(grad_reduce(st, c->du0.z(), c->sB.z(), c->dPk.d() + P, g.mi, M, nl, g.nleaf, grad));
   mark(c, 4, 1);
 }
 
 void sine_setup(hps_ctx* c, int S) {
+  require(c->P == 1, HPS_EINVAL, "the sine model takes a single-problem context");
   if (S == c->sine_S) return;
   const Geometry& g = c->g;
   const int m1 = g.p - 2, nX = g.L * m1;
@@ -672,6 +777,7 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
                  int S, const double* coef, const double* data, int max_iter, double tol,
                  double* coef_out) {
   require(c->o.keep_derivs != 0, HPS_ESTATE, "context created without keep_derivs");
+  require(c->P == 1, HPS_EINVAL, "the Gauss-Newton step takes a single-problem context");
   require(S >= 1 && coef && data && coef_out && max_iter >= 0 && tol >= 0.0, HPS_EINVAL,
           "bad Gauss-Newton arguments");
   const ll npde = (ll)c->g.nleaf * c->g.mi, ns = (ll)S * S, nd = (ll)M * nt;
@@ -697,7 +803,7 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
     return h;
   };
   sine_eval(c, S, coef, q);
-  factor(c, q, k);
+  factor(c, q, &k);
   solve(c, M, ang);
   far_field(c, nt, th, R, (double*)jv);
   CK(zsub(st, (const double2*)data, jv, res, nd));
@@ -744,7 +850,7 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
 
 int64_t device_bytes(const hps_ctx* c) {
   int64_t s = 0;
-  const DBuf* bufs[] = {&c->dA0, &c->dMout, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dY, &c->dH,
+  const DBuf* bufs[] = {&c->dA0, &c->dMout, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dPk, &c->dY, &c->dH,
                         &c->dRroot, &c->dZinv, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
                         &c->sBlk, &c->sW, &c->sWinv, &c->sQ, &c->sVin, &c->sV, &c->sTmp, &c->sInfo,
                         &c->d_dirs, &c->dG, &c->dRhs, &c->dF0, &c->dF1, &c->dF3, &c->du0, &c->dST,
@@ -775,6 +881,7 @@ void hps_default_opts(hps_opts* o) {
   o->precision = HPS_FP64;
   o->host_threads = 0;
   o->stream = nullptr;
+  o->nprob = 1;
 }
 
 hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
@@ -786,6 +893,7 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
   if (o.nleaf < 1 || o.nleaf > 256 || (o.nleaf & (o.nleaf - 1))) return HPS_EINVAL;
   if (o.p < 4 || o.p > 20) return HPS_EINVAL;
   if (o.precision != HPS_FP64) return HPS_EINVAL;
+  if (o.nprob < 1 || o.nprob > 4096) return HPS_EINVAL;
   hps_ctx* c = nullptr;
   try {
     c = new hps_ctx();
@@ -794,6 +902,7 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
   }
   hps_status s = guard(nullptr, [&] {
     c->o = o;
+    c->P = o.nprob;
     c->st = (hipStream_t)o.stream;
     CK(hipGetDevice(&c->device));
     unsigned hw = std::thread::hardware_concurrency();
@@ -844,12 +953,35 @@ hps_status hps_set_wavenumber(hps_ctx* c, double k) {
   return guard(c, [&] { set_wavenumber(c, k); });
 }
 
+hps_status hps_set_wavenumbers(hps_ctx* c, const double* k) {
+  if (!c || !k) return HPS_EINVAL;
+  return guard(c, [&] { set_wavenumbers(c, k); });
+}
+
 hps_status hps_factor(hps_ctx* c, const double* q, double k) {
   if (!c) return HPS_EINVAL;
+  return guard(c, [&] {
+    std::vector<double> kv(c->P, k);
+    factor(c, q, kv.data());
+  });
+}
+
+hps_status hps_factor_batch(hps_ctx* c, const double* q, const double* k) {
+  if (!c || !k) return HPS_EINVAL;
   return guard(c, [&] { factor(c, q, k); });
 }
 
 hps_status hps_solve(hps_ctx* c, int ndir, const double* ang) {
+  if (!c) return HPS_EINVAL;
+  return guard(c, [&] {
+    require(ndir >= 1 && ndir <= 65535 && ang != nullptr, HPS_EINVAL, "bad direction list");
+    std::vector<double> all((size_t)ndir * c->P);
+    for (int b = 0; b < c->P; ++b) std::memcpy(all.data() + (size_t)b * ndir, ang, sizeof(double) * ndir);
+    solve(c, ndir, all.data());
+  });
+}
+
+hps_status hps_solve_batch(hps_ctx* c, int ndir, const double* ang) {
   if (!c) return HPS_EINVAL;
   return guard(c, [&] { solve(c, ndir, ang); });
 }
@@ -864,7 +996,9 @@ hps_status hps_total_field(hps_ctx* c, double* u) {
   return guard(c, [&] {
     require(c->solved, HPS_ESTATE, "hps_total_field before hps_solve");
     require(u != nullptr, HPS_EINVAL, "NULL output");
-    CK(export_field(c->st, c->du0.z(), c->g.mi, c->ndir, c->g.nleaf, (double2*)u));
+    const ll per = (ll)c->g.nleaf * c->g.mi * c->ndir;
+    for (int b = 0; b < c->P; ++b)
+      CK(export_field(c->st, c->du0.z() + per * b, c->g.mi, c->ndir, c->g.nleaf, (double2*)u + per * b));
   });
 }
 

@@ -4,9 +4,13 @@
 
 namespace hps {
 
-// out[z] = A0 with -k2 q[z][r] added to the diagonal of the first mi rows.
-hipError_t leaf_assemble(hipStream_t st, const double2* A0, const double* q, double k2, int n,
-                         int mi, double2* out, ll nleaf);
+// Several problems share one leaf grid: leaf z belongs to problem z / lpp.
+// Per-problem scalars (k, k^2, eta) are device arrays indexed by problem.
+
+// out[z] = A0[problem] with -k^2 q[z][r] added to the diagonal of the first
+// mi rows.
+hipError_t leaf_assemble(hipStream_t st, const double2* A0, ll sA0, const double* q, const double* k2v,
+                         int n, int mi, double2* out, ll nleaf, ll lpp);
 // out(i, j) = sc * in(ridx[i], cidx[j]) (null index array = identity).
 hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
                     const int* ridx, const int* cidx, double2* out, ll ldo, ll so, double sc,
@@ -17,16 +21,17 @@ hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi,
 // out = off everywhere, diag on the diagonal.
 hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
                  double2 off, int batch);
+// ndir (ncol) columns per problem, nprob problems.
 hipError_t incident(hipStream_t st, const double4* bnode, int nb, const double2* dirs, int ndir,
-                    double k, double2* G);
+                    const double* kv, double2* G, int nprob);
 hipError_t boundary_st(hipStream_t st, const double2* f, const double2* g, const double2* G,
-                       int nb, int ncol, double eta, double2* ST);
-hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, double eta,
-                           double2* fb, double2* gb);
-hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, double k2, int mi,
-                     int ndir, ll nleaf, double2* b);
-hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, double k2, int mi,
-                       int ndir, ll nleaf, double* grad);
+                       int nb, int ncol, const double* etav, double2* ST, int nprob);
+hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, const double* etav,
+                           double2* fb, double2* gb, int nprob);
+hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, const double* k2v, int mi,
+                     int ndir, ll nleaf, ll lpp, double2* b);
+hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, const double* k2v, int mi,
+                       int ndir, ll nleaf, ll lpp, double* grad);
 hipError_t export_field(hipStream_t st, const double2* u0, int mi, int ndir, ll nleaf,
                         double2* out);
 hipError_t real_to_complex(hipStream_t st, const double* x, ll n, double2* y);

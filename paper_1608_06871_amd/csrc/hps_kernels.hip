@@ -16,16 +16,19 @@ inline unsigned blocks_for(ll n) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
-__global__ void k_leaf_assemble(const double2* A0, const double* q, double k2, int n, int mi,
-                                double2* out, ll nleaf) {
+// Leaf z belongs to problem z / lpp, whose base matrix is A0 + problem sA0 and
+// whose k^2 is k2v[problem].
+__global__ void k_leaf_assemble(const double2* A0, ll sA0, const double* q, const double* k2v, int n,
+                                int mi, double2* out, ll nleaf, ll lpp) {
   const ll per = (ll)n * n;
   const ll total = per * nleaf;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
     const ll z = idx / per;
+    const ll pb = z / lpp;
     const int e = (int)(idx % per);
-    double2 v = A0[e];
+    double2 v = A0[pb * sA0 + e];
     const int r = e % n, c = e / n;
-    if (r == c && r < mi) v.x -= k2 * q[z * mi + r];
+    if (r == c && r < mi) v.x -= k2v[pb] * q[z * mi + r];
     out[idx] = v;
   }
 }
@@ -69,12 +72,15 @@ __global__ void k_set2d(int M, int N, double2* out, ll ldo, ll so, double2 diag,
   }
 }
 
-// Rows [0, nb): d_nu u_inc; rows [nb, 2 nb): u_inc, one column per direction.
-__global__ void k_incident(const double4* bnode, int nb, const double2* dirs, int ndir, double k,
-                           double2* G) {
-  const ll total = (ll)nb * ndir;
+// Rows [0, nb): d_nu u_inc; rows [nb, 2 nb): u_inc, one column per direction;
+// column m belongs to problem m / ndir (wavenumber kv[m / ndir]).
+__global__ void k_incident(const double4* bnode, int nb, const double2* dirs, int ndir, const double* kv,
+                           double2* G, int nprob) {
+  const ll total = (ll)nb * ndir * nprob;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const int i = (int)(idx % nb), m = (int)(idx / nb);
+    const int i = (int)(idx % nb);
+    const ll m = idx / nb;
+    const double k = kv[m / ndir];
     const double4 b = bnode[i];
     const double2 d = dirs[m];
     double s, c;
@@ -87,12 +93,15 @@ __global__ void k_incident(const double4* bnode, int nb, const double2* dirs, in
 
 // From the incoming/outgoing impedance (f, g) on the outer boundary:
 //   s = (f - g) / (2 i eta) - u_inc,  t = (f + g) / 2 - d_nu u_inc
-// (the incident terms are skipped when G is null).  Output [s; t] per column.
+// (the incident terms are skipped when G is null).  Output [s; t] per column;
+// column m belongs to problem m / ncol (eta = etav[m / ncol]).
 __global__ void k_boundary_st(const double2* f, const double2* g, const double2* G, int nb,
-                              int ncol, double eta, double2* ST) {
-  const ll total = (ll)nb * ncol;
+                              int ncol, const double* etav, double2* ST, int nprob) {
+  const ll total = (ll)nb * ncol * nprob;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const int i = (int)(idx % nb), m = (int)(idx / nb);
+    const int i = (int)(idx % nb);
+    const ll m = idx / nb;
+    const double eta = etav[m / ncol];
     const double2 fv = f[(ll)m * nb + i], gv = g[(ll)m * nb + i];
     const double2 dmin = make_double2(fv.x - gv.x, fv.y - gv.y);
     // (a + ib) / (2 i eta) = (b - i a) / (2 eta)
@@ -112,11 +121,13 @@ __global__ void k_boundary_st(const double2* f, const double2* g, const double2*
 
 // Adjoint of k_boundary_st without incident terms: from (sbar, tbar)
 //   fbar = conj(1/(2 i eta)) sbar + tbar / 2,  gbar = -conj(1/(2 i eta)) sbar + tbar / 2.
-__global__ void k_boundary_st_adj(const double2* STb, int nb, int ncol, double eta, double2* fb,
-                                  double2* gb) {
-  const ll total = (ll)nb * ncol;
+__global__ void k_boundary_st_adj(const double2* STb, int nb, int ncol, const double* etav, double2* fb,
+                                  double2* gb, int nprob) {
+  const ll total = (ll)nb * ncol * nprob;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const int i = (int)(idx % nb), m = (int)(idx / nb);
+    const int i = (int)(idx % nb);
+    const ll m = idx / nb;
+    const double eta = etav[m / ncol];
     const double2 sb = STb[(ll)m * 2 * nb + i], tb = STb[(ll)m * 2 * nb + nb + i];
     // conj(1/(2 i eta)) = i / (2 eta):  i (a + ib) / (2 eta) = (-b + i a) / (2 eta)
     const double2 c = make_double2(-sb.y / (2.0 * eta), sb.x / (2.0 * eta));
@@ -125,23 +136,23 @@ __global__ void k_boundary_st_adj(const double2* STb, int nb, int ncol, double e
   }
 }
 
-// b[z][n + m mi] = k^2 dq[z mi + n] u0[z][n + m mi]
-__global__ void k_body_load(const double* dq, const double2* u0, double k2, int mi, int ndir,
-                            ll nleaf, double2* b) {
+// b[z][n + m mi] = k^2 dq[z mi + n] u0[z][n + m mi]  (k^2 of leaf z's problem)
+__global__ void k_body_load(const double* dq, const double2* u0, const double* k2v, int mi, int ndir,
+                            ll nleaf, ll lpp, double2* b) {
   const ll per = (ll)mi * ndir;
   const ll total = per * nleaf;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
     const ll z = idx / per;
     const int n = (int)(idx % per) % mi;
-    const double s = k2 * dq[z * mi + n];
+    const double s = k2v[z / lpp] * dq[z * mi + n];
     const double2 u = u0[idx];
     b[idx] = make_double2(s * u.x, s * u.y);
   }
 }
 
 // grad[z mi + n] = Re sum_m k^2 conj(u0) bbar   (fixed summation order)
-__global__ void k_grad_reduce(const double2* u0, const double2* bb, double k2, int mi, int ndir,
-                              ll nleaf, double* grad) {
+__global__ void k_grad_reduce(const double2* u0, const double2* bb, const double* k2v, int mi, int ndir,
+                              ll nleaf, ll lpp, double* grad) {
   const ll total = (ll)mi * nleaf;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
     const ll z = idx / mi;
@@ -152,7 +163,7 @@ __global__ void k_grad_reduce(const double2* u0, const double2* bb, double k2, i
       const double2 u = u0[base + (ll)m * mi], v = bb[base + (ll)m * mi];
       acc += u.x * v.x + u.y * v.y;
     }
-    grad[idx] = k2 * acc;
+    grad[idx] = k2v[z / lpp] * acc;
   }
 }
 
@@ -243,11 +254,11 @@ hipError_t zsub(hipStream_t st, const double2* x, const double2* y, double2* z, 
   return hipGetLastError();
 }
 
-hipError_t leaf_assemble(hipStream_t st, const double2* A0, const double* q, double k2, int n,
-                         int mi, double2* out, ll nleaf) {
+hipError_t leaf_assemble(hipStream_t st, const double2* A0, ll sA0, const double* q, const double* k2v,
+                         int n, int mi, double2* out, ll nleaf, ll lpp) {
   KernelTimer kt(st, K_LEAF, 0.0, 16.0 * (double)n * n * nleaf + 8.0 * mi * (double)nleaf);
-  hipLaunchKernelGGL(k_leaf_assemble, dim3(blocks_for((ll)n * n * nleaf)), dim3(NT), 0, st, A0, q,
-                     k2, n, mi, out, nleaf);
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(blocks_for((ll)n * n * nleaf)), dim3(NT), 0, st, A0, sA0, q,
+                     k2v, n, mi, out, nleaf, lpp);
   return hipGetLastError();
 }
 
@@ -280,42 +291,42 @@ hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, doub
 }
 
 hipError_t incident(hipStream_t st, const double4* bnode, int nb, const double2* dirs, int ndir,
-                    double k, double2* G) {
-  KernelTimer kt(st, K_POINT, 0.0, (32.0 + 32.0 * ndir) * (double)nb);
-  hipLaunchKernelGGL(k_incident, dim3(blocks_for((ll)nb * ndir)), dim3(NT), 0, st, bnode, nb, dirs,
-                     ndir, k, G);
+                    const double* kv, double2* G, int nprob) {
+  KernelTimer kt(st, K_POINT, 0.0, (32.0 + 32.0 * ndir) * (double)nb * nprob);
+  hipLaunchKernelGGL(k_incident, dim3(blocks_for((ll)nb * ndir * nprob)), dim3(NT), 0, st, bnode, nb,
+                     dirs, ndir, kv, G, nprob);
   return hipGetLastError();
 }
 
 hipError_t boundary_st(hipStream_t st, const double2* f, const double2* g, const double2* G,
-                       int nb, int ncol, double eta, double2* ST) {
-  KernelTimer kt(st, K_POINT, 0.0, 16.0 * 5.0 * nb * (double)ncol);
-  hipLaunchKernelGGL(k_boundary_st, dim3(blocks_for((ll)nb * ncol)), dim3(NT), 0, st, f, g, G, nb,
-                     ncol, eta, ST);
+                       int nb, int ncol, const double* etav, double2* ST, int nprob) {
+  KernelTimer kt(st, K_POINT, 0.0, 16.0 * 5.0 * nb * (double)ncol * nprob);
+  hipLaunchKernelGGL(k_boundary_st, dim3(blocks_for((ll)nb * ncol * nprob)), dim3(NT), 0, st, f, g, G,
+                     nb, ncol, etav, ST, nprob);
   return hipGetLastError();
 }
 
-hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, double eta,
-                           double2* fb, double2* gb) {
-  KernelTimer kt(st, K_POINT, 0.0, 16.0 * 4.0 * nb * (double)ncol);
-  hipLaunchKernelGGL(k_boundary_st_adj, dim3(blocks_for((ll)nb * ncol)), dim3(NT), 0, st, STb, nb,
-                     ncol, eta, fb, gb);
+hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, const double* etav,
+                           double2* fb, double2* gb, int nprob) {
+  KernelTimer kt(st, K_POINT, 0.0, 16.0 * 4.0 * nb * (double)ncol * nprob);
+  hipLaunchKernelGGL(k_boundary_st_adj, dim3(blocks_for((ll)nb * ncol * nprob)), dim3(NT), 0, st, STb,
+                     nb, ncol, etav, fb, gb, nprob);
   return hipGetLastError();
 }
 
-hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, double k2, int mi,
-                     int ndir, ll nleaf, double2* b) {
+hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, const double* k2v, int mi,
+                     int ndir, ll nleaf, ll lpp, double2* b) {
   KernelTimer kt(st, K_POINT, 6.0 * mi * (double)ndir * nleaf, (8.0 + 32.0 * ndir) * mi * (double)nleaf);
   hipLaunchKernelGGL(k_body_load, dim3(blocks_for((ll)mi * ndir * nleaf)), dim3(NT), 0, st, dq, u0,
-                     k2, mi, ndir, nleaf, b);
+                     k2v, mi, ndir, nleaf, lpp, b);
   return hipGetLastError();
 }
 
-hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, double k2, int mi,
-                       int ndir, ll nleaf, double* grad) {
+hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, const double* k2v, int mi,
+                       int ndir, ll nleaf, ll lpp, double* grad) {
   KernelTimer kt(st, K_POINT, 4.0 * mi * (double)ndir * nleaf, (8.0 + 32.0 * ndir) * mi * (double)nleaf);
-  hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for((ll)mi * nleaf)), dim3(NT), 0, st, u0, bb, k2,
-                     mi, ndir, nleaf, grad);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for((ll)mi * nleaf)), dim3(NT), 0, st, u0, bb, k2v,
+                     mi, ndir, nleaf, lpp, grad);
   return hipGetLastError();
 }
 

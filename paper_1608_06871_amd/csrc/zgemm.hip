@@ -12,6 +12,7 @@
 // prefetched into registers while the current one is multiplied.  Operands
 // may be used as stored (N), transposed (T) or conjugate-transposed (C); all
 // shapes are bounds-checked (zero fill).  The tile shape is chosen per call.
+#include <cstdio>
 #include <cstdlib>
 
 #include "common.h"
@@ -36,6 +37,7 @@ struct Args {
   const int* rpos;  // optional: rows r with plo <= rpos[r] < phi take beta = 0
   ll srp;
   int plo, phi;
+  int adiv, bdiv;  // batch index divisors of A and B (operand of batch b: b / div)
 };
 
 __device__ inline double2 ld_op(const double2* p, bool conj) {
@@ -91,8 +93,8 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   const int m0 = (blockIdx.x % tilesM) * TM;
   const int n0 = (blockIdx.x / tilesM) * TN;
   const ll b = blockIdx.y;
-  const double2* A = a.A + b * a.sA;
-  const double2* B = a.B + b * a.sB;
+  const double2* A = a.A + (b / a.adiv) * a.sA;
+  const double2* B = a.B + (b / a.bdiv) * a.sB;
   double2* C = a.C + b * a.sC;
 
   const int t = threadIdx.x;
@@ -222,6 +224,23 @@ const LaunchFn VARIANTS[] = {
 };
 constexpr int NVARIANT = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
+// HPS_ZGEMM_TRACE=<file> appends one line per call (M N K batch opA opB
+// beta!=0 rowmask) for offline analysis of the call shapes.
+void trace_call(const Args& a, int batch) {
+  static FILE* f = nullptr;
+  static int state = 0;
+  if (state == 0) {
+    const char* e = std::getenv("HPS_ZGEMM_TRACE");
+    f = (e && *e) ? std::fopen(e, "a") : nullptr;
+    state = 1;
+  }
+  if (!f) return;
+  const bool rb = (a.beta.x != 0.0 || a.beta.y != 0.0);
+  std::fprintf(f, "%d %d %d %d %d %d %d %d\n", a.M, a.N, a.K, batch, a.opA, a.opB, rb ? 1 : 0,
+               a.rpos ? 1 : 0);
+  std::fflush(f);
+}
+
 int forced_variant() {
   static int v = -2;
   if (v == -2) {
@@ -247,12 +266,29 @@ hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 
 hipError_t zgemm_rowmask(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
                          const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB, double2 beta,
                          double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi, int batch) {
+  return zgemm_full(st, opA, opB, M, N, K, alpha, A, lda, sA, 1, B, ldb, sB, 1, beta, C, ldc, sC, rpos, srp,
+                    plo, phi, batch);
+}
+
+hipError_t zgemm_div(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
+                     const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB, int bdiv,
+                     double2 beta, double2* C, ll ldc, ll sC, int batch) {
+  return zgemm_full(st, opA, opB, M, N, K, alpha, A, lda, sA, adiv, B, ldb, sB, bdiv, beta, C, ldc, sC,
+                    nullptr, 0, 0, 0, batch);
+}
+
+hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
+                      const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB, int bdiv,
+                      double2 beta, double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi,
+                      int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  if (batch > 65535) return hipErrorInvalidValue;
-  Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, rpos, srp, plo, phi};
+  if (batch > 65535 || adiv < 1 || bdiv < 1) return hipErrorInvalidValue;
+  Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, rpos, srp, plo, phi,
+         adiv, bdiv};
   const bool rb = (beta.x != 0.0 || beta.y != 0.0);
   KernelTimer kt(st, K_ZGEMM, 8.0 * M * N * (double)a.K * batch,
                  16.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);
+  trace_call(a, batch);
   const int fv = forced_variant();
   if (fv >= 0) return VARIANTS[fv](st, a, batch);
   // Tuned on MI355X over the solver's shapes (rank-32 updates of the

@@ -1,0 +1,98 @@
+"""Batched contexts (several independent (q, k) problems on one leaf grid):
+every per-problem result must equal the single-problem solve of the same
+problem.  The batch runs the same kernels with a larger batch count, so the
+results are expected to be identical, not merely close; one problem is also
+checked against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _problems(xy, ks, seed0):
+    qs = [synth.gaussian_bumps(xy, 5, seed0 + i, amp=(0.1, 0.3), width=0.15) for i in range(len(ks))]
+    dqs = [synth.gaussian_bumps(xy, 2, seed0 + 50 + i, amp=(0.01, 0.02), width=0.3) for i in range(len(ks))]
+    return qs, dqs
+
+
+def _single(hps, L, k, q, dq, dirs, th, R, r):
+    s = hps.Solver(nleaf=L, p=16)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    s.solve(dirs)
+    ff = s.far_field(th, R).cpu().numpy()
+    jv = s.jvp(torch.from_numpy(dq).cuda()).cpu().numpy()
+    g = s.vjp(torch.from_numpy(r).cuda()).cpu().numpy()
+    return ff, jv, g
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_batch_equals_single(L):
+    import paper_1608_06871_amd as hps
+    ks = [5.0, 11.5, 7.25]
+    P = len(ks)
+    M, nt, R = 6, 16, 2.0
+    b = hps.Solver(nleaf=L, p=16, nprob=P)
+    xy = b.node_coords()
+    qs, dqs = _problems(xy, ks, 10 * L)
+    rng = np.random.default_rng(L)
+    dirs = rng.uniform(0, 2 * np.pi, size=(P, M))
+    th = synth.equispaced_angles(nt)
+    rs = [rng.standard_normal((M, nt)) + 1j * rng.standard_normal((M, nt)) for _ in range(P)]
+    print(f"batch L={L} P={P} M={M}", flush=True)
+    b.factor(torch.from_numpy(np.stack(qs)).cuda(), ks)
+    b.solve(dirs)
+    ff = b.far_field(th, R).cpu().numpy()
+    jv = b.jvp(torch.from_numpy(np.stack(dqs)).cuda()).cpu().numpy()
+    g = b.vjp(torch.from_numpy(np.stack(rs)).cuda()).cpu().numpy()
+    assert ff.shape == (P, M, nt) and g.shape == (P, b.npde)
+    for i in range(P):
+        ff1, jv1, g1 = _single(hps, L, ks[i], qs[i], dqs[i], dirs[i], th, R, rs[i])
+        assert np.array_equal(ff[i], ff1), f"problem {i}: far field differs"
+        assert np.array_equal(jv[i], jv1), f"problem {i}: jvp differs"
+        assert np.array_equal(g[i], g1), f"problem {i}: vjp differs"
+
+
+def test_batch_shared_directions_and_oracle():
+    """hps_solve with one direction list for all problems; problem 1 against
+    the oracle's far field (<= 1e-9 relative)."""
+    import paper_1608_06871_amd as hps
+    from oracle.bie import circle_points
+    from oracle.forward import Problem
+
+    ks = [6.0, 9.0]
+    L, M, nt, R = 2, 4, 12, 2.0
+    b = hps.Solver(nleaf=L, p=16, nprob=2)
+    xy = b.node_coords()
+    qs, _ = _problems(xy, ks, 77)
+    dirs = synth.equispaced_angles(M)
+    _, th = circle_points(R, nt)
+    b.factor(torch.from_numpy(np.stack(qs)).cuda(), ks)
+    b.solve(dirs)
+    ff = b.far_field(th, R).cpu().numpy()
+    prob = Problem(L, ks[1])
+    prob.set_measurement(th, R)
+    prob.factor(qs[1])
+    prob.solve(dirs)
+    ref = np.asarray(prob.far_field())
+    err = np.linalg.norm(ff[1] - ref) / np.linalg.norm(ref)
+    print(f"batch oracle rel err {err:.2e}", flush=True)
+    assert err <= 1e-9
+
+
+def test_batch_argument_errors():
+    import paper_1608_06871_amd as hps
+    b = hps.Solver(nleaf=2, p=16, nprob=2)
+    q = torch.zeros(2 * b.npde, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        b.factor(q, [5.0, 6.0, 7.0])
+    with pytest.raises(hps.HpsError):
+        b.factor(q, [5.0, -1.0])
+    b.factor(q, [5.0, 6.0])
+    with pytest.raises(ValueError):
+        b.solve(np.zeros((3, 4)))
+    with pytest.raises(hps.HpsError):
+        b.sine_eval(torch.zeros(4, dtype=torch.float64, device="cuda"))
