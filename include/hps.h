@@ -73,10 +73,20 @@ typedef enum {
   HPS_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
   HPS_ESTATE = -4,     /* call order violated (solve before factor, ...) */
   HPS_ESINGULAR = -5,  /* a zero pivot was met in a factorisation */
-  HPS_ENOCONV = -6     /* reserved: iterative refinement did not converge */
+  HPS_ENOCONV = -6     /* HPS_MIXED: refinement stopped above refine_tol (results kept) */
 } hps_status;
 
-typedef enum { HPS_FP64 = 0 } hps_precision;
+/* HPS_FP64: everything in complex128.
+ * HPS_MIXED: the factorisation is complex128; the forward solves run their
+ * level sweeps in complex64 on FP32 matrix cores (copies of the merge
+ * operators) and are then refined on the interface (skeleton) system of
+ * leaf-edge impedance data: the residual is formed in complex128 with the
+ * leaf impedance-to-impedance maps (interface mismatches at every merge and
+ * the outer-boundary relation) and corrected with complex64 sweeps, until
+ * its norm is at most refine_tol times that of the boundary data or
+ * max_refine corrections were made.  hps_jvp / hps_vjp use the complex128
+ * operators. */
+typedef enum { HPS_FP64 = 0, HPS_MIXED = 1 } hps_precision;
 
 typedef struct hps_opts {
   double x0, x1, y0, y1; /* square domain Omega; x1 - x0 must equal y1 - y0 */
@@ -84,16 +94,19 @@ typedef struct hps_opts {
   int p;                 /* Chebyshev-Lobatto points per leaf side (4 .. 20) */
   double eta_scale;      /* impedance parameter eta = eta_scale * k (<= 0: 1) */
   int keep_derivs;       /* non-zero: keep the operators hps_jvp / hps_vjp need */
-  int precision;         /* hps_precision; only HPS_FP64 */
+  int precision;         /* hps_precision */
   int host_threads;      /* threads for the per-k boundary quadrature (<= 0: auto) */
   void* stream;          /* hipStream_t for all work (NULL = default stream) */
   int nprob;             /* independent problems on this grid (1 .. 4096); see Batches */
+  int max_refine;        /* HPS_MIXED: most refinement corrections per solve (0 .. 100) */
+  double refine_tol;     /* HPS_MIXED: relative residual target (> 0) */
 } hps_opts;
 
 typedef struct hps_ctx hps_ctx;
 
 /* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
- * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1. */
+ * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1,
+ * max_refine = 8, refine_tol = 1e-13. */
 void hps_default_opts(hps_opts* o);
 
 /* Creates a context for the geometry in *opts (host-side set-up only; device
@@ -211,6 +224,8 @@ typedef struct hps_stats {
   int64_t device_bytes;   /* device memory held by the context */
   int ndir;               /* directions of the last solve */
   int singular;           /* 1 if the last factorisation met a zero pivot */
+  int refine_iters;       /* HPS_MIXED: corrections made by the last solve */
+  double refine_residual; /* HPS_MIXED: its final relative interface residual */
 } hps_stats;
 
 /* Timings of the last calls (synchronises the stream) and memory use. */

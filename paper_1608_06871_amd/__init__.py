@@ -31,14 +31,16 @@ class Opts(ctypes.Structure):
                 ("y1", ctypes.c_double), ("nleaf", ctypes.c_int), ("p", ctypes.c_int),
                 ("eta_scale", ctypes.c_double), ("keep_derivs", ctypes.c_int),
                 ("precision", ctypes.c_int), ("host_threads", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("nprob", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("nprob", ctypes.c_int), ("max_refine", ctypes.c_int),
+                ("refine_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("t_wavenumber_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_far_field_ms", ctypes.c_double),
                 ("t_jvp_ms", ctypes.c_double), ("t_vjp_ms", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int)]
+                ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int),
+                ("refine_iters", ctypes.c_int), ("refine_residual", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -119,7 +121,8 @@ class Solver:
     problem axis (q [nprob, npde], far field [nprob, ndir, ntheta], ...)."""
 
     def __init__(self, nleaf=4, p=16, box=(-1.0, 1.0, -1.0, 1.0), eta_scale=1.0,
-                 keep_derivs=True, host_threads=0, stream=None, nprob=1):
+                 keep_derivs=True, host_threads=0, stream=None, nprob=1, precision="fp64",
+                 max_refine=None, refine_tol=None):
         torch = _torch()
         L = lib()
         o = Opts()
@@ -130,6 +133,14 @@ class Solver:
         o.keep_derivs = 1 if keep_derivs else 0
         o.host_threads = int(host_threads)
         o.nprob = int(nprob)
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        o.precision = 0 if precision == "fp64" else 1
+        if max_refine is not None:
+            o.max_refine = int(max_refine)
+        if refine_tol is not None:
+            o.refine_tol = float(refine_tol)
+        self.precision = precision
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -35,6 +35,11 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
                       int bdiv, double2 beta, double2* C, ll ldc, ll sC, const int* rpos, ll srp,
                       int plo, int phi, int batch);
 
+// FP32 complex GEMM (same conventions as zgemm; FP32 MFMA, FP32 accumulation).
+hipError_t cgemm(hipStream_t st, int opA, int opB, int M, int N, int K, float2 alpha,
+                 const float2* A, ll lda, ll sA, const float2* B, ll ldb, ll sB, float2 beta,
+                 float2* C, ll ldc, ll sC, int batch);
+
 // Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
 size_t zinv_workspace(int n, int batch);
 
@@ -49,6 +54,7 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
 // Kernel classes of the optional launch profiler.
 enum KernelKind {
   K_ZGEMM = 0,
+  K_CGEMM,      // FP32 complex GEMM (mixed precision)
   K_GJ_PANEL,   // Gauss-Jordan panel elimination (register / LDS / global panel)
   K_TP_SELECT,  // tournament pivot selection (leaves and reductions)
   K_TP_BLOCK,   // pivot-block inverse of the tournament path

@@ -109,6 +109,18 @@ struct hps_ctx {
   DBuf dPk;  // device [k (P) | k^2 (P) | eta (P)]
   std::vector<DBuf> didx;  // 4 index arrays per level
 
+  // mixed precision
+  bool mixed = false;
+  int refine_iters = 0;
+  double refine_res = 0.0;
+  DBuf dRleaf;                              // leaf ItI maps (complex128)
+  std::vector<DBuf> dD32, dU32, dE32;       // complex64 sweep operators per level
+  DBuf sE;                                  // h-to-f3 maps before conversion
+  DBuf mF0, mF1, mF3, mTmp;                 // complex64 sweep vectors
+  std::vector<DBuf> mH3;                    // complex64 shared-edge sources per level
+  std::vector<DBuf> dRho;                   // interface residuals per level (complex128)
+  DBuf dFl, dGl, rF0, rF1, rG0, rG1, rT0, rT1, dRb, sNorm;
+
   // factorisation
   bool factored = false;
   int singular = 0;
@@ -347,10 +359,27 @@ void plan_factor_buffers(hps_ctx* c) {
   c->dZinv.ensure(zb(P * nb * nb));
   c->dD.resize(g.nlev + 1);
   c->dU.resize(g.nlev + 1);
+  const bool needU = c->o.keep_derivs || c->mixed;
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
     c->dD[l].ensure(zb(P * L.count * 2 * L.s * 2 * L.m));
-    if (c->o.keep_derivs) c->dU[l].ensure(zb(P * L.count * 2 * L.m * 2 * L.s));
+    if (needU) c->dU[l].ensure(zb(P * L.count * 2 * L.m * 2 * L.s));
+  }
+  if (c->mixed) {
+    c->dRleaf.ensure(zb(nl * ne * ne));
+    c->dD32.resize(g.nlev + 1);
+    c->dU32.resize(g.nlev + 1);
+    c->dE32.resize(g.nlev + 1);
+    size_t emax = 1;
+    for (int l = 1; l <= g.nlev; ++l) {
+      const LevelPattern& L = g.lev[l];
+      const size_t cnt = P * L.count;
+      c->dD32[l].ensure(cnt * 2 * L.s * 2 * L.m * sizeof(float2));
+      c->dU32[l].ensure(cnt * 2 * L.m * 2 * L.s * sizeof(float2));
+      c->dE32[l].ensure(cnt * 2 * L.s * 2 * L.s * sizeof(float2));
+      emax = std::max(emax, cnt * 2 * L.s * 2 * L.s);
+    }
+    c->sE.ensure(zb(emax));
   }
 }
 
@@ -384,6 +413,7 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   if (c->o.keep_derivs)
     CK(zgemm_div(st, OP_N, OP_N, ne, mi, n, ONE, c->dMout.z(), ne, smo, lpp, c->sInv.z(), n, nn, 1, ZERO,
                  c->dH.z(), ne, (ll)ne * mi, nl));
+  if (c->mixed) CK(hipMemcpyAsync(c->dRleaf.p, Rc, zb((size_t)nl * ne * ne), hipMemcpyDeviceToDevice, st));
 
   // merge tree
   for (int l = 1; l <= g.nlev; ++l) {
@@ -434,7 +464,7 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
     CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, A13, m, ms, D, 2 * s, sd, ONE, Rn, np, sp, cnt));
     CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, B23, m, ms, D + s, 2 * s, sd, ONE, Rn + m, np, sp,
              cnt));
-    if (c->o.keep_derivs) {
+    if (c->o.keep_derivs || c->mixed) {
       double2* Vin = c->sVin.z();
       double2* V = c->sV.z();
       double2* Tm = c->sTmp.z();
@@ -448,6 +478,16 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
       CK(zgemm(st, OP_N, OP_N, s, 2 * s, s, ONE, A33, s, ss, V, s, sv, ONE, Tm, s, sv, cnt));
       CK(zgemm(st, OP_N, OP_N, m, 2 * s, s, MONE, B23, m, ms, Tm, s, sv, ZERO, U + m, 2 * m, sd,
                cnt));
+      if (c->mixed) {
+        // E = [V; -Tm]: shared-edge sources h3 to f3 (the down-sweep's h term)
+        double2* E = c->sE.z();
+        const ll se = 4 * ss;
+        CK(gather2d(st, s, 2 * s, V, s, sv, nullptr, nullptr, E, 2 * s, se, 1.0, cnt));
+        CK(gather2d(st, s, 2 * s, Tm, s, sv, nullptr, nullptr, E + s, 2 * s, se, -1.0, cnt));
+        CK(to_f32(st, E, (ll)cnt * se, (float2*)c->dE32[l].p));
+        CK(to_f32(st, D, (ll)cnt * sd, (float2*)c->dD32[l].p));
+        CK(to_f32(st, U, (ll)cnt * sd, (float2*)c->dU32[l].p));
+      }
     }
     Rc = Rn;
   }
@@ -504,6 +544,221 @@ void scatter_children(hps_ctx* c, int l, const double2* Fp, const double2* F3, d
   CK(scatter_rows(st, s, M, F3 + s, 2 * s, s3, c->didx[4 * l + 3].i(), Fch + (ll)nc * M, nc, sc, cnt));
 }
 
+// ---- mixed precision: complex64 sweeps refined on the skeleton system ----
+//
+// Skeleton unknowns: the incoming impedance data f on every leaf edge.  The
+// leaf maps give g = R_leaf f; the equations are the matching f3a = -g3b,
+// f3b = -g3a at the shared edge of every merge, and A1 f + A2 g = rhs on
+// the outer boundary.  The residual is formed in complex128; a correction
+// solves the same system with the residuals as sources: an interface
+// residual enters a merge exactly like the h data of a body load, with
+// h3a += rho_b and h3b += rho_a, so the correction is an up-sweep of sources
+// (U), the top solve and a down-sweep that adds E h3 at every level.
+
+void plan_mixed_buffers(hps_ctx* c, int M) {
+  const Geometry& g = c->g;
+  const size_t P = c->P, Ms = M;
+  const size_t leaf = P * g.nleaf * g.ne * Ms;
+  size_t up = 1, sh = 1;
+  c->dRho.resize(g.nlev + 1);
+  c->mH3.resize(g.nlev + 1);
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& L = g.lev[l];
+    const size_t cnt = P * L.count;
+    up = std::max(up, cnt * L.np * Ms);
+    sh = std::max(sh, cnt * 2 * L.s * Ms);
+    c->dRho[l].ensure(zb(cnt * 2 * L.s * Ms));
+    c->mH3[l].ensure(cnt * 2 * L.s * Ms * sizeof(float2));
+  }
+  const size_t top = P * c->nb * Ms;
+  c->dFl.ensure(zb(leaf));
+  c->dGl.ensure(zb(leaf));
+  c->rF0.ensure(zb(up));
+  c->rF1.ensure(zb(up));
+  c->rG0.ensure(zb(up));
+  c->rG1.ensure(zb(up));
+  c->rT0.ensure(zb(std::max(sh, top)));
+  c->rT1.ensure(zb(std::max(sh, top)));
+  c->dRb.ensure(zb(top));
+  c->mF0.ensure(std::max(leaf, up) * sizeof(float2));
+  c->mF1.ensure(std::max(leaf, up) * sizeof(float2));
+  c->mF3.ensure(sh * sizeof(float2));
+  c->sNorm.ensure(sizeof(double) * (256 + g.nlev + 8));
+}
+
+// complex64 down-sweep from root data Fr (complex64 [P][nb][M]) to leaf-edge
+// data (returned buffer, complex64 [nl][ne][M]); with_h adds E h3 per level.
+float2* mixed_down(hps_ctx* c, int M, float2* Fr, bool with_h) {
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const float2 one = make_float2(1.0f, 0.0f), zero = make_float2(0.0f, 0.0f);
+  float2* Fc = Fr;
+  float2* Fo = (Fr == (float2*)c->mF0.p) ? (float2*)c->mF1.p : (float2*)c->mF0.p;
+  float2* F3 = (float2*)c->mF3.p;
+  for (int l = g.nlev; l >= 1; --l) {
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * c->P, m = L.m, s = L.s, nc = L.nc, np = L.np;
+    const ll s3 = 2LL * s * M;
+    CK(cgemm(st, OP_N, OP_N, 2 * s, M, 2 * m, one, (const float2*)c->dD32[l].p, 2 * s, 4LL * m * s, Fc, np,
+             (ll)np * M, zero, F3, 2 * s, s3, cnt));
+    if (with_h)
+      CK(cgemm(st, OP_N, OP_N, 2 * s, M, 2 * s, one, (const float2*)c->dE32[l].p, 2 * s, 4LL * s * s,
+               (const float2*)c->mH3[l].p, 2 * s, s3, one, F3, 2 * s, s3, cnt));
+    const ll sp = (ll)np * M, sc = 2LL * nc * M;
+    CK(scatter_rows(st, m, M, Fc, np, sp, c->didx[4 * l].i(), Fo, nc, sc, cnt));
+    CK(scatter_rows(st, s, M, F3, 2 * s, s3, c->didx[4 * l + 1].i(), Fo, nc, sc, cnt));
+    CK(scatter_rows(st, m, M, Fc + m, np, sp, c->didx[4 * l + 2].i(), Fo + (ll)nc * M, nc, sc, cnt));
+    CK(scatter_rows(st, s, M, F3 + s, 2 * s, s3, c->didx[4 * l + 3].i(), Fo + (ll)nc * M, nc, sc, cnt));
+    std::swap(Fc, Fo);
+  }
+  return Fc;
+}
+
+// Residual of the skeleton system at the leaf data dFl (complex128):
+// dRho[l] = [f3b + g3a; f3a + g3b] per level, dRb = A1 f + A2 g - rhs on
+// the outer boundary.  Returns the relative residual
+// max(||rho|| / ||f||, ||r_b|| / ||rhs||); froot / groot receive the outer
+// boundary data.
+double mixed_residual(hps_ctx* c, int M, const double2*& froot, const double2*& groot) {
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int P = c->P, ne = g.ne, nb = c->nb, nl = g.nleaf * P;
+  CK(zgemm(st, OP_N, OP_N, ne, M, ne, ONE, c->dRleaf.z(), ne, (ll)ne * ne, c->dFl.z(), ne, (ll)ne * M, ZERO,
+           c->dGl.z(), ne, (ll)ne * M, nl));
+  const double2* fc = c->dFl.z();
+  const double2* gc = c->dGl.z();
+  double2* fo[2] = {c->rF0.z(), c->rF1.z()};
+  double2* go[2] = {c->rG0.z(), c->rG1.z()};
+  double* partial = c->sNorm.d();
+  double* nrm = partial + 256;  // [0] f, [1] rhs, [2] r_b, [3 ..] rho per level
+  int pp = 0;
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;
+    const ll sc = 2LL * nc * M, sp = (ll)np * M, s3 = 2LL * s * M;
+    const double2* fa = fc;
+    const double2* fb = fc + (ll)nc * M;
+    const double2* ga = gc;
+    const double2* gb = gc + (ll)nc * M;
+    const int* i1a = c->didx[4 * l].i();
+    const int* i3a = c->didx[4 * l + 1].i();
+    const int* i2b = c->didx[4 * l + 2].i();
+    const int* i3b = c->didx[4 * l + 3].i();
+    double2* fp = fo[pp];
+    double2* gp = go[pp];
+    CK(gather2d(st, m, M, fa, nc, sc, i1a, nullptr, fp, np, sp, 1.0, cnt));
+    CK(gather2d(st, m, M, fb, nc, sc, i2b, nullptr, fp + m, np, sp, 1.0, cnt));
+    CK(gather2d(st, m, M, ga, nc, sc, i1a, nullptr, gp, np, sp, 1.0, cnt));
+    CK(gather2d(st, m, M, gb, nc, sc, i2b, nullptr, gp + m, np, sp, 1.0, cnt));
+    double2* t0 = c->rT0.z();
+    double2* t1 = c->rT1.z();
+    CK(gather2d(st, s, M, fb, nc, sc, i3b, nullptr, t0, 2 * s, s3, 1.0, cnt));
+    CK(gather2d(st, s, M, fa, nc, sc, i3a, nullptr, t0 + s, 2 * s, s3, 1.0, cnt));
+    CK(gather2d(st, s, M, ga, nc, sc, i3a, nullptr, t1, 2 * s, s3, 1.0, cnt));
+    CK(gather2d(st, s, M, gb, nc, sc, i3b, nullptr, t1 + s, 2 * s, s3, 1.0, cnt));
+    const ll nr = (ll)cnt * s3;
+    CK(zadd(st, t0, t1, c->dRho[l].z(), nr));
+    CK(dot(st, (const double*)c->dRho[l].p, (const double*)c->dRho[l].p, 2 * nr, partial, nrm + 2 + l));
+    fc = fp;
+    gc = gp;
+    pp ^= 1;
+  }
+  froot = fc;
+  groot = gc;
+  const ll sF = (ll)nb * M, sbb = (ll)nb * nb, ntop = (ll)P * sF;
+  CK(hipMemcpyAsync(c->dRb.p, c->dRhs.p, zb((size_t)ntop), hipMemcpyDeviceToDevice, st));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA1.z(), nb, sbb, froot, nb, sF, MONE, c->dRb.z(), nb, sF, P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA2.z(), nb, sbb, groot, nb, sF, ONE, c->dRb.z(), nb, sF, P));
+  const ll nleaf = (ll)nl * ne * M;
+  CK(dot(st, (const double*)c->dFl.p, (const double*)c->dFl.p, 2 * nleaf, partial, nrm));
+  CK(dot(st, (const double*)c->dRhs.p, (const double*)c->dRhs.p, 2 * ntop, partial, nrm + 1));
+  CK(dot(st, (const double*)c->dRb.p, (const double*)c->dRb.p, 2 * ntop, partial, nrm + 2));
+  std::vector<double> h(g.nlev + 3);
+  CK(hipMemcpyAsync(h.data(), nrm, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  double rho = 0.0;
+  for (int l = 1; l <= g.nlev; ++l) rho += h[2 + l];
+  const double rf = h[0] > 0.0 ? std::sqrt(rho / h[0]) : std::sqrt(rho);
+  const double rb = h[1] > 0.0 ? std::sqrt(h[2] / h[1]) : std::sqrt(h[2]);
+  return std::max(rf, rb);
+}
+
+// One correction of the leaf data dFl from the residuals dRho, dRb.
+void mixed_correct(hps_ctx* c, int M) {
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int P = c->P, nb = c->nb;
+  const float2 one = make_float2(1.0f, 0.0f), zero = make_float2(0.0f, 0.0f);
+  // up-sweep of sources (complex64); the leaves carry none
+  const float2* hc = nullptr;
+  float2* ho[2] = {(float2*)c->mF0.p, (float2*)c->mF1.p};
+  int pp = 0;
+  for (int l = 1; l <= g.nlev; ++l) {
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;
+    const ll sc = 2LL * nc * M, sp = (ll)np * M, s3 = 2LL * s * M, nr = (ll)cnt * s3;
+    float2* H3 = (float2*)c->mH3[l].p;
+    float2* hp = ho[pp];
+    if (hc == nullptr) {
+      CK(to_f32(st, c->dRho[l].z(), nr, H3));
+      CK(cgemm(st, OP_N, OP_N, np, M, 2 * s, one, (const float2*)c->dU32[l].p, np, 4LL * m * s, H3, 2 * s, s3,
+               zero, hp, np, sp, cnt));
+    } else {
+      const float2* ha = hc;
+      const float2* hb = hc + (ll)nc * M;
+      CK(gather2d(st, m, M, ha, nc, sc, c->didx[4 * l].i(), nullptr, hp, np, sp, 1.0f, cnt));
+      CK(gather2d(st, m, M, hb, nc, sc, c->didx[4 * l + 2].i(), nullptr, hp + m, np, sp, 1.0f, cnt));
+      CK(gather2d(st, s, M, ha, nc, sc, c->didx[4 * l + 1].i(), nullptr, H3, 2 * s, s3, 1.0f, cnt));
+      CK(gather2d(st, s, M, hb, nc, sc, c->didx[4 * l + 3].i(), nullptr, H3 + s, 2 * s, s3, 1.0f, cnt));
+      CK(add_to_f32(st, c->dRho[l].z(), nr, H3));
+      CK(cgemm(st, OP_N, OP_N, np, M, 2 * s, one, (const float2*)c->dU32[l].p, np, 4LL * m * s, H3, 2 * s, s3,
+               one, hp, np, sp, cnt));
+    }
+    hc = hp;
+    pp ^= 1;
+  }
+  // top: delta f = Z^-1 (-r_b - A2 h)
+  const ll sF = (ll)nb * M, sbb = (ll)nb * nb, ntop = (ll)P * sF;
+  double2* hr = c->rT0.z();
+  double2* w = c->rT1.z();
+  CK(to_f64(st, hc, ntop, hr));
+  CK(gather2d(st, (int)ntop, 1, c->dRb.z(), ntop, 0, nullptr, nullptr, w, ntop, 0, -1.0, 1));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dA2.z(), nb, sbb, hr, nb, sF, ONE, w, nb, sF, P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, sbb, w, nb, sF, ZERO, hr, nb, sF, P));
+  float2* dr = (hc == (float2*)c->mF0.p) ? (float2*)c->mF1.p : (float2*)c->mF0.p;
+  CK(to_f32(st, hr, ntop, dr));
+  float2* dfl = mixed_down(c, M, dr, true);
+  CK(add_f32(st, dfl, (ll)P * g.nleaf * g.ne * M, c->dFl.z()));
+}
+
+// Mixed-precision forward solve from the root data Fc = Z^-1 rhs
+// (complex128).  Leaves dST and du0 as the complex128 path does.
+void solve_mixed(hps_ctx* c, int M, const double2* Fc) {
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int P = c->P, nb = c->nb;
+  plan_mixed_buffers(c, M);
+  const ll ntop = (ll)P * nb * M;
+  float2* fr = (float2*)c->mF0.p;
+  CK(to_f32(st, Fc, ntop, fr));
+  float2* fl = mixed_down(c, M, fr, false);
+  CK(to_f64(st, fl, (ll)P * g.nleaf * g.ne * M, c->dFl.z()));
+  const double2* froot = nullptr;
+  const double2* groot = nullptr;
+  int it = 0;
+  double res = mixed_residual(c, M, froot, groot);
+  while (res > c->o.refine_tol && it < c->o.max_refine) {
+    mixed_correct(c, M);
+    ++it;
+    res = mixed_residual(c, M, froot, groot);
+  }
+  c->refine_iters = it;
+  c->refine_res = res;
+  CK(boundary_st(st, froot, groot, c->dG.z(), nb, M, c->dPk.d() + 2 * P, c->dST.z(), P));
+  CK(zgemm(st, OP_N, OP_N, g.mi, M, g.ne, ONE, c->dY.z(), g.mi, (ll)g.mi * g.ne, c->dFl.z(), g.ne,
+           (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf * P));
+}
+
 // ang: P x M direction angles (problem-major).
 void solve(hps_ctx* c, int M, const double* ang) {
   require(c->factored, HPS_ESTATE, "hps_solve before hps_factor");
@@ -532,6 +787,15 @@ void solve(hps_ctx* c, int M, const double* ang) {
   double2* Fo = c->dF1.z();
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, sbb, c->dRhs.z(), nb, sF, ZERO, Fc, nb, sF,
            P));
+  if (c->mixed) {
+    solve_mixed(c, M, Fc);
+    mark(c, 1, 1);
+    c->ndir = M;
+    c->solved = true;
+    if (!(c->refine_res <= c->o.refine_tol))
+      throw HpsError{HPS_ENOCONV, "refinement stopped at relative residual " + std::to_string(c->refine_res)};
+    return;
+  }
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, Fc, nb, sF, ZERO, c->dg.z(), nb, sF,
            P));
   CK(boundary_st(st, Fc, c->dg.z(), c->dG.z(), nb, M, etav, c->dST.z(), P));
@@ -860,6 +1124,11 @@ int64_t device_bytes(const hps_ctx* c) {
   for (const auto& b : c->didx) s += (int64_t)b.bytes;
   for (const auto& b : c->dD) s += (int64_t)b.bytes;
   for (const auto& b : c->dU) s += (int64_t)b.bytes;
+  const DBuf* mb[] = {&c->dRleaf, &c->sE, &c->mF0, &c->mF1, &c->mF3, &c->mTmp, &c->dFl, &c->dGl, &c->rF0,
+                      &c->rF1, &c->rG0, &c->rG1, &c->rT0, &c->rT1, &c->dRb, &c->sNorm};
+  for (const DBuf* b : mb) s += (int64_t)b->bytes;
+  for (const auto* v : {&c->dD32, &c->dU32, &c->dE32, &c->mH3, &c->dRho})
+    for (const auto& b : *v) s += (int64_t)b.bytes;
   return s;
 }
 
@@ -882,6 +1151,8 @@ void hps_default_opts(hps_opts* o) {
   o->host_threads = 0;
   o->stream = nullptr;
   o->nprob = 1;
+  o->max_refine = 8;
+  o->refine_tol = 1e-13;
 }
 
 hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
@@ -892,8 +1163,10 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
   if (!(lx > 0.0) || std::fabs(lx - ly) > 1e-14 * lx) return HPS_EINVAL;
   if (o.nleaf < 1 || o.nleaf > 256 || (o.nleaf & (o.nleaf - 1))) return HPS_EINVAL;
   if (o.p < 4 || o.p > 20) return HPS_EINVAL;
-  if (o.precision != HPS_FP64) return HPS_EINVAL;
+  if (o.precision != HPS_FP64 && o.precision != HPS_MIXED) return HPS_EINVAL;
   if (o.nprob < 1 || o.nprob > 4096) return HPS_EINVAL;
+  if (o.precision == HPS_MIXED && (o.max_refine < 0 || o.max_refine > 100 || !(o.refine_tol > 0.0)))
+    return HPS_EINVAL;
   hps_ctx* c = nullptr;
   try {
     c = new hps_ctx();
@@ -903,6 +1176,7 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
   hps_status s = guard(nullptr, [&] {
     c->o = o;
     c->P = o.nprob;
+    c->mixed = (o.precision == HPS_MIXED);
     c->st = (hipStream_t)o.stream;
     CK(hipGetDevice(&c->device));
     unsigned hw = std::thread::hardware_concurrency();
@@ -1050,6 +1324,8 @@ hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
     out->device_bytes = device_bytes(c);
     out->ndir = c->ndir;
     out->singular = c->singular;
+    out->refine_iters = c->refine_iters;
+    out->refine_residual = c->refine_res;
   });
 }
 

@@ -18,6 +18,17 @@ hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll 
 // out(ridx[i], j) = in(i, j).
 hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
                         const int* ridx, double2* out, ll ldo, ll so, int batch);
+// FP32 versions (mixed-precision sweeps).
+hipError_t gather2d(hipStream_t st, int M, int N, const float2* in, ll ldi, ll si, const int* ridx,
+                    const int* cidx, float2* out, ll ldo, ll so, float sc, int batch);
+hipError_t scatter_rows(hipStream_t st, int M, int N, const float2* in, ll ldi, ll si, const int* ridx,
+                        float2* out, ll ldo, ll so, int batch);
+// y = (float) x;  y += (double) x;  y = (double) x;  y += (float) x;  z = x + y
+hipError_t to_f32(hipStream_t st, const double2* x, ll n, float2* y);
+hipError_t add_f32(hipStream_t st, const float2* x, ll n, double2* y);
+hipError_t to_f64(hipStream_t st, const float2* x, ll n, double2* y);
+hipError_t add_to_f32(hipStream_t st, const double2* x, ll n, float2* y);
+hipError_t zadd(hipStream_t st, const double2* x, const double2* y, double2* z, ll n);
 // out = off everywhere, diag on the diagonal.
 hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
                  double2 off, int batch);

@@ -33,8 +33,9 @@ __global__ void k_leaf_assemble(const double2* A0, ll sA0, const double* q, cons
   }
 }
 
-__global__ void k_gather2d(int M, int N, const double2* in, ll ldi, ll si, const int* ridx,
-                           const int* cidx, double2* out, ll ldo, ll so, double sc, int batch) {
+template <typename T2, typename T>
+__global__ void k_gather2d(int M, int N, const T2* in, ll ldi, ll si, const int* ridx, const int* cidx,
+                           T2* out, ll ldo, ll so, T sc, int batch) {
   const ll per = (ll)M * N;
   const ll total = per * batch;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
@@ -43,13 +44,17 @@ __global__ void k_gather2d(int M, int N, const double2* in, ll ldi, ll si, const
     const int i = e % M, j = e / M;
     const int ri = ridx ? ridx[i] : i;
     const int cj = cidx ? cidx[j] : j;
-    const double2 v = in[b * si + (ll)ri + (ll)cj * ldi];
-    out[b * so + (ll)i + (ll)j * ldo] = make_double2(sc * v.x, sc * v.y);
+    const T2 v = in[b * si + (ll)ri + (ll)cj * ldi];
+    T2 o;
+    o.x = sc * v.x;
+    o.y = sc * v.y;
+    out[b * so + (ll)i + (ll)j * ldo] = o;
   }
 }
 
-__global__ void k_scatter_rows(int M, int N, const double2* in, ll ldi, ll si, const int* ridx,
-                               double2* out, ll ldo, ll so, int batch) {
+template <typename T2>
+__global__ void k_scatter_rows(int M, int N, const T2* in, ll ldi, ll si, const int* ridx, T2* out, ll ldo,
+                               ll so, int batch) {
   const ll per = (ll)M * N;
   const ll total = per * batch;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
@@ -216,6 +221,31 @@ __global__ void k_sum_partials(const double* partial, int nb, double* out) {
   if (threadIdx.x == 0) *out = sh[0];
 }
 
+__global__ void k_to_f32(const double2* x, ll n, float2* y) {
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT)
+    y[i] = make_float2((float)x[i].x, (float)x[i].y);
+}
+
+__global__ void k_add_f32(const float2* x, ll n, double2* y) {
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT)
+    y[i] = make_double2(y[i].x + (double)x[i].x, y[i].y + (double)x[i].y);
+}
+
+__global__ void k_to_f64(const float2* x, ll n, double2* y) {
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT)
+    y[i] = make_double2((double)x[i].x, (double)x[i].y);
+}
+
+__global__ void k_add_to_f32(const double2* x, ll n, float2* y) {
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT)
+    y[i] = make_float2(y[i].x + (float)x[i].x, y[i].y + (float)x[i].y);
+}
+
+__global__ void k_zadd(const double2* x, const double2* y, double2* z, ll n) {
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT)
+    z[i] = make_double2(x[i].x + y[i].x, x[i].y + y[i].y);
+}
+
 // y = a x + b y
 __global__ void k_axpby(double a, const double* x, double b, double* y, ll n) {
   for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT) y[i] = a * x[i] + b * y[i];
@@ -267,8 +297,17 @@ hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll 
                     int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
-  hipLaunchKernelGGL(k_gather2d, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, in,
-                     ldi, si, ridx, cidx, out, ldo, so, sc, batch);
+  hipLaunchKernelGGL((k_gather2d<double2, double>), dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M,
+                     N, in, ldi, si, ridx, cidx, out, ldo, so, sc, batch);
+  return hipGetLastError();
+}
+
+hipError_t gather2d(hipStream_t st, int M, int N, const float2* in, ll ldi, ll si, const int* ridx,
+                    const int* cidx, float2* out, ll ldo, ll so, float sc, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 0.0, 16.0 * (double)M * N * batch);
+  hipLaunchKernelGGL((k_gather2d<float2, float>), dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
+                     in, ldi, si, ridx, cidx, out, ldo, so, sc, batch);
   return hipGetLastError();
 }
 
@@ -276,8 +315,47 @@ hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi,
                         const int* ridx, double2* out, ll ldo, ll so, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
-  hipLaunchKernelGGL(k_scatter_rows, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
+  hipLaunchKernelGGL(k_scatter_rows<double2>, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
                      in, ldi, si, ridx, out, ldo, so, batch);
+  return hipGetLastError();
+}
+
+hipError_t scatter_rows(hipStream_t st, int M, int N, const float2* in, ll ldi, ll si, const int* ridx,
+                        float2* out, ll ldo, ll so, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 0.0, 16.0 * (double)M * N * batch);
+  hipLaunchKernelGGL(k_scatter_rows<float2>, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, in,
+                     ldi, si, ridx, out, ldo, so, batch);
+  return hipGetLastError();
+}
+
+hipError_t to_f32(hipStream_t st, const double2* x, ll n, float2* y) {
+  KernelTimer kt(st, K_POINT, 0.0, 24.0 * (double)n);
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t add_f32(hipStream_t st, const float2* x, ll n, double2* y) {
+  KernelTimer kt(st, K_POINT, 2.0 * (double)n, 40.0 * (double)n);
+  hipLaunchKernelGGL(k_add_f32, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t to_f64(hipStream_t st, const float2* x, ll n, double2* y) {
+  KernelTimer kt(st, K_POINT, 0.0, 24.0 * (double)n);
+  hipLaunchKernelGGL(k_to_f64, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t add_to_f32(hipStream_t st, const double2* x, ll n, float2* y) {
+  KernelTimer kt(st, K_POINT, 2.0 * (double)n, 32.0 * (double)n);
+  hipLaunchKernelGGL(k_add_to_f32, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t zadd(hipStream_t st, const double2* x, const double2* y, double2* z, ll n) {
+  KernelTimer kt(st, K_POINT, 2.0 * (double)n, 48.0 * (double)n);
+  hipLaunchKernelGGL(k_zadd, dim3(blocks_for(n)), dim3(NT), 0, st, x, y, z, n);
   return hipGetLastError();
 }
 

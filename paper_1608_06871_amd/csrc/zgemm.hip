@@ -1,14 +1,16 @@
-// Batched complex FP64 GEMM on CDNA4 matrix cores.
+// Batched complex GEMM on CDNA4 matrix cores, in FP64 (zgemm) and FP32
+// (cgemm).
 //
-// Complex products run on the FP64 MFMA (v_mfma_f64_16x16x4f64) as real
-// products on split real/imaginary planes, with the 3M method
-// (Re = ArBr - AiBi, Im = (Ar + Ai)(Br + Bi) - ArBr - AiBi: three matrix-core
-// operations per complex multiply-add, the sums formed in registers from the
-// LDS planes; Higham analyses its accuracy) or the four direct products.
+// Complex products run on the 16x16x4 MFMA of the precision
+// (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32) as real products on split
+// real/imaginary planes, with the 3M method (Re = ArBr - AiBi,
+// Im = (Ar + Ai)(Br + Bi) - ArBr - AiBi: three matrix-core operations per
+// complex multiply-add, the sums formed in registers from the LDS planes;
+// Higham analyses its accuracy) or the four direct products.
 // A 256-thread workgroup (4 wave64s, 2 x 2) owns a (32 WM) x (32 WN) tile of
 // C; each wave owns (16 WM) x (16 WN) as WM x WN MFMA blocks of 16 x 16.  The
-// K loop steps by 16: the A and B tiles are loaded from HBM with coalesced
-// 16-byte accesses into real/imaginary planes in LDS, and the next tile is
+// K loop steps by TK: the A and B tiles are loaded from HBM with coalesced
+// accesses into real/imaginary planes in LDS, and the next tile is
 // prefetched into registers while the current one is multiplied.  Operands
 // may be used as stored (N), transposed (T) or conjugate-transposed (C); all
 // shapes are bounds-checked (zero fill).  The tile shape is chosen per call.
@@ -21,27 +23,59 @@ namespace hps {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Cx;
+template <>
+struct Cx<double> {
+  typedef double2 T2;
+  typedef v4d V4;
+};
+template <>
+struct Cx<float> {
+  typedef float2 T2;
+  typedef v4f V4;
+};
+
+// 16x16x4 MFMA.  Inputs (both precisions): lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16].  Output item r of lane l: FP64 row l / 16 + 4 r,
+// FP32 row 4 (l / 16) + r; column l % 16 (probed on the hardware).
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T>
+__device__ inline int mfma_row(int lk, int r) {
+  return sizeof(T) == 8 ? lk + 4 * r : 4 * lk + r;
+}
 
 constexpr int PAD = 1;
 constexpr int NT = 256;
 
-struct Args {
+template <typename T>
+struct ArgsT {
+  typedef typename Cx<T>::T2 T2;
   int M, N, K, opA, opB;
-  const double2* A;
+  const T2* A;
   ll lda, sA;
-  const double2* B;
+  const T2* B;
   ll ldb, sB;
-  double2* C;
+  T2* C;
   ll ldc, sC;
-  double2 alpha, beta;
+  T2 alpha, beta;
   const int* rpos;  // optional: rows r with plo <= rpos[r] < phi take beta = 0
   ll srp;
   int plo, phi;
   int adiv, bdiv;  // batch index divisors of A and B (operand of batch b: b / div)
 };
+typedef ArgsT<double> Args;
 
-__device__ inline double2 ld_op(const double2* p, bool conj) {
-  double2 v = *p;
+template <typename T2>
+__device__ inline T2 ld_op(const T2* p, bool conj) {
+  T2 v = *p;
   if (conj) v.y = -v.y;
   return v;
 }
@@ -49,29 +83,32 @@ __device__ inline double2 ld_op(const double2* p, bool conj) {
 // Loads / stores of a TR x TK tile of a matrix X viewed as rows x K: A as
 // op(A) (M x K), B through the transpose of op(B) (N x K).  `contig` means
 // consecutive rows are adjacent in memory, so threads run along the rows.
-template <int TR, int TK>
+template <int TR, int TK, typename T>
 struct TileIO {
+  typedef typename Cx<T>::T2 T2;
   static constexpr int PER = TR * TK / NT;
-  __device__ static void load(const double2* X, ll ld, int nrow, int ncol, int r0, int k0, bool contig,
-                              bool conj, int t, double2* reg) {
+  __device__ static void load(const T2* X, ll ld, int nrow, int ncol, int r0, int k0, bool contig, bool conj,
+                              int t, T2* reg) {
+    T2 z;
+    z.x = 0;
+    z.y = 0;
     if (contig) {
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int idx = t + j * NT;
         const int r = r0 + idx % TR, k = k0 + idx / TR;
-        reg[j] = (r < nrow && k < ncol) ? ld_op(X + (ll)r + (ll)k * ld, conj) : make_double2(0.0, 0.0);
+        reg[j] = (r < nrow && k < ncol) ? ld_op(X + (ll)r + (ll)k * ld, conj) : z;
       }
     } else {
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int idx = t + j * NT;
         const int k = k0 + idx % TK, r = r0 + idx / TK;
-        reg[j] = (r < nrow && k < ncol) ? ld_op(X + (ll)k + (ll)r * ld, conj) : make_double2(0.0, 0.0);
+        reg[j] = (r < nrow && k < ncol) ? ld_op(X + (ll)k + (ll)r * ld, conj) : z;
       }
     }
   }
-  __device__ static void store(double (*re)[TR + PAD], double (*im)[TR + PAD], bool contig, int t,
-                               const double2* reg) {
+  __device__ static void store(T (*re)[TR + PAD], T (*im)[TR + PAD], bool contig, int t, const T2* reg) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const int idx = t + j * NT;
@@ -83,19 +120,21 @@ struct TileIO {
   }
 };
 
-template <int WM, int WN, bool M3, int TK, int WAVES>
-__global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
+template <typename T, int WM, int WN, bool M3, int TK, int WAVES>
+__global__ __launch_bounds__(NT, WAVES) void gemm_kernel(ArgsT<T> a) {
+  typedef typename Cx<T>::T2 T2;
+  typedef typename Cx<T>::V4 V4;
   constexpr int TM = 32 * WM, TN = 32 * WN;
-  __shared__ double Are[TK][TM + PAD], Aim[TK][TM + PAD];
-  __shared__ double Bre[TK][TN + PAD], Bim[TK][TN + PAD];
+  __shared__ T Are[TK][TM + PAD], Aim[TK][TM + PAD];
+  __shared__ T Bre[TK][TN + PAD], Bim[TK][TN + PAD];
 
   const int tilesM = (a.M + TM - 1) / TM;
   const int m0 = (blockIdx.x % tilesM) * TM;
   const int n0 = (blockIdx.x / tilesM) * TN;
   const ll b = blockIdx.y;
-  const double2* A = a.A + (b / a.adiv) * a.sA;
-  const double2* B = a.B + (b / a.bdiv) * a.sB;
-  double2* C = a.C + b * a.sC;
+  const T2* A = a.A + (b / a.adiv) * a.sA;
+  const T2* B = a.B + (b / a.bdiv) * a.sB;
+  T2* C = a.C + b * a.sC;
 
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
@@ -105,33 +144,35 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   const bool b_rows = a.opB != OP_N, b_conj = a.opB == OP_C;
 
   // M3: p1 = ArBr, p2 = AiBi, p3 = (Ar+Ai)(Br+Bi); otherwise p1 = Re, p3 = Im
-  v4d p1[WM][WN], p2[WM][WN], p3[WM][WN];
+  V4 p1[WM][WN], p2[WM][WN], p3[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
-      p1[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-      p2[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-      p3[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      p1[i][j] = V4{0, 0, 0, 0};
+      p2[i][j] = V4{0, 0, 0, 0};
+      p3[i][j] = V4{0, 0, 0, 0};
     }
 
-  double2 ra[TileIO<TM, TK>::PER], rb[TileIO<TN, TK>::PER];
-  TileIO<TM, TK>::load(A, a.lda, a.M, a.K, m0, 0, a_rows, a_conj, t, ra);
-  TileIO<TN, TK>::load(B, a.ldb, a.N, a.K, n0, 0, b_rows, b_conj, t, rb);
+  typedef TileIO<TM, TK, T> IOA;
+  typedef TileIO<TN, TK, T> IOB;
+  T2 ra[IOA::PER], rb[IOB::PER];
+  IOA::load(A, a.lda, a.M, a.K, m0, 0, a_rows, a_conj, t, ra);
+  IOB::load(B, a.ldb, a.N, a.K, n0, 0, b_rows, b_conj, t, rb);
   const int nk = (a.K + TK - 1) / TK;
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
-    TileIO<TM, TK>::store(Are, Aim, a_rows, t, ra);
-    TileIO<TN, TK>::store(Bre, Bim, b_rows, t, rb);
+    IOA::store(Are, Aim, a_rows, t, ra);
+    IOB::store(Bre, Bim, b_rows, t, rb);
     __syncthreads();
     if (kt + 1 < nk) {
-      TileIO<TM, TK>::load(A, a.lda, a.M, a.K, m0, (kt + 1) * TK, a_rows, a_conj, t, ra);
-      TileIO<TN, TK>::load(B, a.ldb, a.N, a.K, n0, (kt + 1) * TK, b_rows, b_conj, t, rb);
+      IOA::load(A, a.lda, a.M, a.K, m0, (kt + 1) * TK, a_rows, a_conj, t, ra);
+      IOB::load(B, a.ldb, a.N, a.K, n0, (kt + 1) * TK, b_rows, b_conj, t, rb);
     }
 #pragma unroll
     for (int ks = 0; ks < TK / 4; ++ks) {
       const int kk = ks * 4 + lk;
-      double ar[WM], ai[WM], br[WN], bi[WN];
+      T ar[WM], ai[WM], br[WN], bi[WN];
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
         ar[i] = Are[kk][wm + 16 * i + lr];
@@ -147,27 +188,25 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
         for (int i = 0; i < WM; ++i)
 #pragma unroll
           for (int j = 0; j < WN; ++j) {
-            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
-            p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], p2[i][j], 0, 0, 0);
-            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i] + ai[i], br[j] + bi[j], p3[i][j], 0,
-                                                            0, 0);
+            p1[i][j] = mfma16(ar[i], br[j], p1[i][j]);
+            p2[i][j] = mfma16(ai[i], bi[j], p2[i][j]);
+            p3[i][j] = mfma16(ar[i] + ai[i], br[j] + bi[j], p3[i][j]);
           }
       } else {
 #pragma unroll
         for (int i = 0; i < WM; ++i)
 #pragma unroll
           for (int j = 0; j < WN; ++j) {
-            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
-            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], p1[i][j], 0, 0, 0);
-            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], p3[i][j], 0, 0, 0);
-            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], p3[i][j], 0, 0, 0);
+            p1[i][j] = mfma16(ar[i], br[j], p1[i][j]);
+            p1[i][j] = mfma16(-ai[i], bi[j], p1[i][j]);
+            p3[i][j] = mfma16(ar[i], bi[j], p3[i][j]);
+            p3[i][j] = mfma16(ai[i], br[j], p3[i][j]);
           }
       }
     }
   }
 
-  // D layout of the 16x16x4 f64 MFMA: item r of a lane is row lane/16 + 4 r,
-  // column lane % 16.
+  // output layout: see mfma16
   const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
   const int* rp = a.rpos ? a.rpos + (ll)blockIdx.y * a.srp : nullptr;
 #pragma unroll
@@ -178,14 +217,16 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
       if (col >= a.N) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + 16 * i + lk + 4 * r;
+        const int row = m0 + wm + 16 * i + mfma_row<T>(lk, r);
         if (row >= a.M) continue;
-        const double xr = M3 ? p1[i][j][r] - p2[i][j][r] : p1[i][j][r];
-        const double xi = M3 ? p3[i][j][r] - p1[i][j][r] - p2[i][j][r] : p3[i][j][r];
-        double2 v = make_double2(a.alpha.x * xr - a.alpha.y * xi, a.alpha.x * xi + a.alpha.y * xr);
-        double2* pc = C + (ll)row + (ll)col * a.ldc;
+        const T xr = M3 ? p1[i][j][r] - p2[i][j][r] : p1[i][j][r];
+        const T xi = M3 ? p3[i][j][r] - p1[i][j][r] - p2[i][j][r] : p3[i][j][r];
+        T2 v;
+        v.x = a.alpha.x * xr - a.alpha.y * xi;
+        v.y = a.alpha.x * xi + a.alpha.y * xr;
+        T2* pc = C + (ll)row + (ll)col * a.ldc;
         if (use_beta && !(rp && rp[row] >= a.plo && rp[row] < a.phi)) {
-          const double2 c = *pc;
+          const T2 c = *pc;
           v.x += a.beta.x * c.x - a.beta.y * c.y;
           v.y += a.beta.x * c.y + a.beta.y * c.x;
         }
@@ -194,14 +235,18 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
     }
 }
 
-template <int WM, int WN, bool M3, int TK, int WAVES>
-hipError_t launch(hipStream_t st, const Args& a, int batch) {
+template <typename T, int WM, int WN, bool M3, int TK, int WAVES>
+hipError_t launch_t(hipStream_t st, const ArgsT<T>& a, int batch) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   const ll tiles = (ll)((a.M + TM - 1) / TM) * ((a.N + TN - 1) / TN);
   if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((zgemm_kernel<WM, WN, M3, TK, WAVES>), dim3((unsigned)tiles, (unsigned)batch), dim3(NT),
+  hipLaunchKernelGGL((gemm_kernel<T, WM, WN, M3, TK, WAVES>), dim3((unsigned)tiles, (unsigned)batch), dim3(NT),
                      0, st, a);
   return hipGetLastError();
+}
+template <int WM, int WN, bool M3, int TK, int WAVES>
+hipError_t launch(hipStream_t st, const Args& a, int batch) {
+  return launch_t<double, WM, WN, M3, TK, WAVES>(st, a, batch);
 }
 
 // Kernel variants (tile WM x WN, 3M or four products, K step, waves per
@@ -296,6 +341,20 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
   if (a.K <= 64) return launch<2, 1, true, 8, 3>(st, a, batch);
   if (M >= 1024 && N >= 1024 && a.K >= 512) return launch<2, 2, true, 16, 2>(st, a, batch);
   return launch<2, 1, true, 16, 2>(st, a, batch);
+}
+
+hipError_t cgemm(hipStream_t st, int opA, int opB, int M, int N, int K, float2 alpha, const float2* A, ll lda,
+                 ll sA, const float2* B, ll ldb, ll sB, float2 beta, float2* C, ll ldc, ll sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (batch > 65535) return hipErrorInvalidValue;
+  ArgsT<float> a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, nullptr, 0,
+                 0, 0, 1, 1};
+  const bool rb = (beta.x != 0.0f || beta.y != 0.0f);
+  KernelTimer kt(st, K_CGEMM, 8.0 * M * N * (double)a.K * batch,
+                 8.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);
+  if (a.K <= 64) return launch_t<float, 2, 1, true, 8, 3>(st, a, batch);
+  if (M >= 1024 && N >= 1024 && a.K >= 512) return launch_t<float, 2, 2, true, 16, 2>(st, a, batch);
+  return launch_t<float, 2, 1, true, 16, 2>(st, a, batch);
 }
 
 }  // namespace hps

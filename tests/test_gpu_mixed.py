@@ -1,0 +1,123 @@
+"""Mixed precision (complex64 sweeps refined on the skeleton system) against
+the complex128 path and the oracle: the far field, the total field and the
+derivatives must agree to <= 1e-8 relative (the refinement target is 1e-13
+on the interface residual, so in practice they agree to ~1e-12)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _run(hps, prec, L, k, q, dirs, th, R, nprob=1, **kw):
+    s = hps.Solver(nleaf=L, p=16, precision=prec, nprob=nprob, **kw)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    s.solve(dirs)
+    return s, s.far_field(th, R).cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("L,k,M", [(2, 5.0, 4), (4, 10.0, 16), (8, 37.5, 32)])
+def test_mixed_far_field_matches_fp64(L, k, M):
+    import paper_1608_06871_amd as hps
+    th = synth.equispaced_angles(64)
+    xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+    q = synth.gaussian_bumps(xy, 5, 1, amp=(0.1, 0.3), width=0.15)
+    dirs = synth.equispaced_angles(M)
+    print(f"mixed L={L} k={k} M={M}", flush=True)
+    _, ref = _run(hps, "fp64", L, k, q, dirs, th, 2.0, keep_derivs=False)
+    s, ff = _run(hps, "mixed", L, k, q, dirs, th, 2.0, keep_derivs=False)
+    st = s.stats()
+    err = _rel(ff, ref)
+    print(f"  rel err {err:.2e}, {st['refine_iters']} corrections, residual {st['refine_residual']:.2e}",
+          flush=True)
+    assert 1 <= st["refine_iters"] <= 4
+    assert st["refine_residual"] <= 1e-13
+    assert err <= 1e-8
+
+
+def test_mixed_against_oracle():
+    import paper_1608_06871_amd as hps
+    from oracle.bie import circle_points
+    from oracle.forward import Problem, directions
+    L, k, M, P, R = 4, 10.0, 16, 64, 2.0
+    xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+    q = synth.gaussian_bumps(xy, 5, 1, amp=(0.1, 0.3), width=0.15)
+    _, th = circle_points(R, P)
+    _, ff = _run(hps, "mixed", L, k, q, directions(M), th, R, keep_derivs=False)
+    prob = Problem(L, k)
+    prob.set_measurement(th, R)
+    prob.factor(q)
+    prob.solve(directions(M))
+    ref = np.asarray(prob.far_field())
+    err = _rel(ff, ref)
+    print(f"mixed vs oracle {err:.2e}", flush=True)
+    assert err <= 1e-8
+
+
+def test_mixed_total_field_derivatives_and_batch():
+    """Total field, jvp and vjp of a mixed context (derivatives use the
+    complex128 operators on the refined fields), batched, against complex128."""
+    import paper_1608_06871_amd as hps
+    L, M, nt, R = 4, 8, 32, 2.0
+    ks = [7.0, 12.0]
+    xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+    qs = np.stack([synth.gaussian_bumps(xy, 5, 20 + i, amp=(0.1, 0.3), width=0.15) for i in range(2)])
+    dq = np.stack([synth.gaussian_bumps(xy, 2, 40 + i, amp=(0.01, 0.02), width=0.3) for i in range(2)])
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal((2, M, nt)) + 1j * rng.standard_normal((2, M, nt))
+    th = synth.equispaced_angles(nt)
+    dirs = synth.equispaced_angles(M)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        s, ff = _run(hps, prec, L, ks, qs, dirs, th, R, nprob=2)
+        u = s.total_field().cpu().numpy()
+        jv = s.jvp(torch.from_numpy(dq).cuda()).cpu().numpy()
+        g = s.vjp(torch.from_numpy(r).cuda()).cpu().numpy()
+        out[prec] = (ff, u, jv, g)
+    for name, a, b in zip(("far field", "total field", "jvp", "vjp"), out["mixed"], out["fp64"]):
+        e = _rel(a, b)
+        print(f"  {name}: {e:.2e}", flush=True)
+        assert e <= 1e-8, name
+
+
+def test_mixed_not_converged_reports():
+    """With no corrections allowed the complex64 solve alone stays above the
+    target: hps_solve reports HPS_ENOCONV and the statistics say why."""
+    import paper_1608_06871_amd as hps
+    L, k = 4, 10.0
+    xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+    q = synth.gaussian_bumps(xy, 5, 1, amp=(0.1, 0.3), width=0.15)
+    s = hps.Solver(nleaf=L, p=16, precision="mixed", keep_derivs=False, max_refine=0)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    with pytest.raises(hps.HpsError) as e:
+        s.solve(synth.equispaced_angles(8))
+    assert e.value.code == hps.HPS_ENOCONV
+    st = s.stats()
+    assert st["refine_iters"] == 0 and 1e-10 < st["refine_residual"] < 1e-3
+
+
+def test_mixed_fullsize_k80():
+    """k = 80 on 64 x 64 leaves with 256 directions (the benchmark workload):
+    mixed against complex128 at <= 1e-8 relative far-field error."""
+    import paper_1608_06871_amd as hps
+    L, k, M = 64, 80.0, 256
+    xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+    q = synth.gaussian_bumps(xy, 40, 3, amp=(0.0, 0.5), width=0.15, rescale_max=0.5)
+    dirs = synth.equispaced_angles(M)
+    th = synth.equispaced_angles(256)
+    print("mixed full size", flush=True)
+    _, ref = _run(hps, "fp64", L, k, q, dirs, th, 2.0, keep_derivs=False)
+    torch.cuda.empty_cache()
+    s, ff = _run(hps, "mixed", L, k, q, dirs, th, 2.0, keep_derivs=False)
+    st = s.stats()
+    err = _rel(ff, ref)
+    print(f"  rel err {err:.2e}, {st['refine_iters']} corrections, residual {st['refine_residual']:.2e}",
+          flush=True)
+    assert err <= 1e-8
