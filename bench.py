@@ -175,6 +175,7 @@ def main():
     ap.add_argument("--config", default="k80_L64_M256", choices=sorted(CONFIGS) + ["batch32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (--gpus {args.gpus} "
@@ -262,6 +263,41 @@ def main():
                         "bytes_per_launch": kd["bytes"] / kd["launches"]}
         log("kernel classes: " + ", ".join(f"{n} {v['total_ms']:.1f} ms/{v['launches']}" for n, v in kernels.items()))
 
+    mixed = None
+    if not args.no_mixed:
+        # the same workload in mixed precision (complex64 sweeps + refinement),
+        # timed the same way, with its far-field error against complex128
+        del s
+        torch.cuda.empty_cache()
+        sm = hps.Solver(nleaf=L, p=16, keep_derivs=False, precision="mixed")
+        sm.set_wavenumber(k)
+        um = torch.empty((M, P), dtype=torch.complex128, device="cuda")
+
+        def mstep():
+            sm.factor(q, k)
+            sm.solve(dirs)
+            sm.far_field(th, R, out=um)
+        mstep()
+        torch.cuda.synchronize()
+        mf, ms = [], []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            mstep()
+            st = sm.stats()
+            mf.append(st["t_factor_ms"])
+            ms.append(st["t_solve_ms"])
+        torch.cuda.synchronize()
+        dtm = (time.perf_counter() - t0) / args.steps
+        err = float((um - ufar).abs().pow(2).sum().sqrt() / ufar.abs().pow(2).sum().sqrt())
+        mixed = {"ms_per_factor_solve_farfield": dtm * 1e3, "factor_ms": float(np.median(mf)),
+                 "solve_ms": float(np.median(ms)), "rhs_per_s_incl_factor": M / dtm,
+                 "solve_only_rhs_per_s": M / (float(np.median(ms)) * 1e-3),
+                 "refine_iters": int(st["refine_iters"]), "refine_residual": float(st["refine_residual"]),
+                 "far_field_rel_err_vs_fp64": err}
+        log(f"mixed: factor {mixed['factor_ms']:.1f} ms, solve {mixed['solve_ms']:.1f} ms, "
+            f"{mixed['refine_iters']} corrections, far-field error vs fp64 {err:.2e}")
+        del sm
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
@@ -269,6 +305,8 @@ def main():
         log(f"cpu baseline: {cpu['value']:.2f} RHS solves/s")
 
     med = {ph: float(np.median(v)) for ph, v in phases.items()}
+    if mixed is not None:
+        mixed["fp64_factor_solve_farfield_ms"] = med["factor"] + med["solve"] + med["far_field"]
     out = {
         "metric": "RHS solves/sec + factor time at k=80, mixed vs FP64 at <=1e-8 rel far-field err",
         "value": value,
@@ -296,6 +334,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "mixed": mixed,
     }
     print(json.dumps(out), flush=True)
 

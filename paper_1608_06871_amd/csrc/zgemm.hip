@@ -16,6 +16,8 @@
 // shapes are bounds-checked (zero fill).  The tile shape is chosen per call.
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
+#include <vector>
 
 #include "common.h"
 
@@ -70,6 +72,8 @@ struct ArgsT {
   ll srp;
   int plo, phi;
   int adiv, bdiv;  // batch index divisors of A and B (operand of batch b: b / div)
+  int kchunk;      // split K: slice z of the grid covers [z kchunk, (z + 1) kchunk)
+  ll sCz;          // split K: C offset of slice z
 };
 typedef ArgsT<double> Args;
 
@@ -120,7 +124,7 @@ struct TileIO {
   }
 };
 
-template <typename T, int WM, int WN, bool M3, int TK, int WAVES>
+template <typename T, int WM, int WN, bool M3, int TK, int WAVES, bool SK, bool DIV>
 __global__ __launch_bounds__(NT, WAVES) void gemm_kernel(ArgsT<T> a) {
   typedef typename Cx<T>::T2 T2;
   typedef typename Cx<T>::V4 V4;
@@ -132,9 +136,14 @@ __global__ __launch_bounds__(NT, WAVES) void gemm_kernel(ArgsT<T> a) {
   const int m0 = (blockIdx.x % tilesM) * TM;
   const int n0 = (blockIdx.x / tilesM) * TN;
   const ll b = blockIdx.y;
-  const T2* A = a.A + (b / a.adiv) * a.sA;
-  const T2* B = a.B + (b / a.bdiv) * a.sB;
-  T2* C = a.C + b * a.sC;
+  // DIV: operands shared by groups of the batch (a separate instantiation:
+  // the division changes the register allocation of the whole kernel)
+  const T2* A = a.A + (DIV ? (ll)((int)blockIdx.y / a.adiv) : b) * a.sA;
+  const T2* B = a.B + (DIV ? (ll)((int)blockIdx.y / a.bdiv) : b) * a.sB;
+  // SK (split K): this workgroup covers K range [kb, ke) and writes slice z
+  const int kb = SK ? (int)blockIdx.z * a.kchunk : 0;
+  const int ke = SK ? ((kb + a.kchunk < a.K) ? kb + a.kchunk : a.K) : a.K;
+  T2* C = a.C + b * a.sC + (SK ? (ll)blockIdx.z * a.sCz : 0);
 
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
@@ -157,17 +166,17 @@ __global__ __launch_bounds__(NT, WAVES) void gemm_kernel(ArgsT<T> a) {
   typedef TileIO<TM, TK, T> IOA;
   typedef TileIO<TN, TK, T> IOB;
   T2 ra[IOA::PER], rb[IOB::PER];
-  IOA::load(A, a.lda, a.M, a.K, m0, 0, a_rows, a_conj, t, ra);
-  IOB::load(B, a.ldb, a.N, a.K, n0, 0, b_rows, b_conj, t, rb);
-  const int nk = (a.K + TK - 1) / TK;
+  IOA::load(A, a.lda, a.M, ke, m0, kb, a_rows, a_conj, t, ra);
+  IOB::load(B, a.ldb, a.N, ke, n0, kb, b_rows, b_conj, t, rb);
+  const int nk = (ke - kb + TK - 1) / TK;
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
     IOA::store(Are, Aim, a_rows, t, ra);
     IOB::store(Bre, Bim, b_rows, t, rb);
     __syncthreads();
     if (kt + 1 < nk) {
-      IOA::load(A, a.lda, a.M, a.K, m0, (kt + 1) * TK, a_rows, a_conj, t, ra);
-      IOB::load(B, a.ldb, a.N, a.K, n0, (kt + 1) * TK, b_rows, b_conj, t, rb);
+      IOA::load(A, a.lda, a.M, ke, m0, kb + (kt + 1) * TK, a_rows, a_conj, t, ra);
+      IOB::load(B, a.ldb, a.N, ke, n0, kb + (kt + 1) * TK, b_rows, b_conj, t, rb);
     }
 #pragma unroll
     for (int ks = 0; ks < TK / 4; ++ks) {
@@ -235,18 +244,253 @@ __global__ __launch_bounds__(NT, WAVES) void gemm_kernel(ArgsT<T> a) {
     }
 }
 
-template <typename T, int WM, int WN, bool M3, int TK, int WAVES>
-hipError_t launch_t(hipStream_t st, const ArgsT<T>& a, int batch) {
+// The FP64 kernel used by default.  It is kept as its own (non-template)
+// source: the same loop written through the precision template above
+// compiles to code that runs about 10% slower on MI355X (measured), so the
+// template serves FP32, split-K and shared-operand calls only.
+__device__ inline double2 ld_op64(const double2* p, bool conj) {
+  double2 v = *p;
+  if (conj) v.y = -v.y;
+  return v;
+}
+
+// Loads / stores of a TR x TK tile of a matrix X viewed as rows x K: A as
+// op(A) (M x K), B through the transpose of op(B) (N x K).  `contig` means
+// consecutive rows are adjacent in memory, so threads run along the rows.
+template <int TR, int TK>
+struct TileIO64 {
+  static constexpr int PER = TR * TK / NT;
+  __device__ static void load(const double2* X, ll ld, int nrow, int ncol, int r0, int k0, bool contig,
+                              bool conj, int t, double2* reg) {
+    if (contig) {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = t + j * NT;
+        const int r = r0 + idx % TR, k = k0 + idx / TR;
+        reg[j] = (r < nrow && k < ncol) ? ld_op64(X + (ll)r + (ll)k * ld, conj) : make_double2(0.0, 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = t + j * NT;
+        const int k = k0 + idx % TK, r = r0 + idx / TK;
+        reg[j] = (r < nrow && k < ncol) ? ld_op64(X + (ll)k + (ll)r * ld, conj) : make_double2(0.0, 0.0);
+      }
+    }
+  }
+  __device__ static void store(double (*re)[TR + PAD], double (*im)[TR + PAD], bool contig, int t,
+                               const double2* reg) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = t + j * NT;
+      const int r = contig ? idx % TR : idx / TK;
+      const int k = contig ? idx / TR : idx % TK;
+      re[k][r] = reg[j].x;
+      im[k][r] = reg[j].y;
+    }
+  }
+};
+
+template <int WM, int WN, bool M3, int TK, int WAVES>
+__global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  __shared__ double Are[TK][TM + PAD], Aim[TK][TM + PAD];
+  __shared__ double Bre[TK][TN + PAD], Bim[TK][TN + PAD];
+
+  const int tilesM = (a.M + TM - 1) / TM;
+  const int m0 = (blockIdx.x % tilesM) * TM;
+  const int n0 = (blockIdx.x / tilesM) * TN;
+  const ll b = blockIdx.y;
+  const double2* A = a.A + b * a.sA;
+  const double2* B = a.B + b * a.sB;
+  double2* C = a.C + b * a.sC;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wm = (w & 1) * 16 * WM, wn = (w >> 1) * 16 * WN;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool a_rows = a.opA == OP_N, a_conj = a.opA == OP_C;
+  const bool b_rows = a.opB != OP_N, b_conj = a.opB == OP_C;
+
+  // M3: p1 = ArBr, p2 = AiBi, p3 = (Ar+Ai)(Br+Bi); otherwise p1 = Re, p3 = Im
+  v4d p1[WM][WN], p2[WM][WN], p3[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      p1[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      p2[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      p3[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+
+  double2 ra[TileIO64<TM, TK>::PER], rb[TileIO64<TN, TK>::PER];
+  TileIO64<TM, TK>::load(A, a.lda, a.M, a.K, m0, 0, a_rows, a_conj, t, ra);
+  TileIO64<TN, TK>::load(B, a.ldb, a.N, a.K, n0, 0, b_rows, b_conj, t, rb);
+  const int nk = (a.K + TK - 1) / TK;
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    TileIO64<TM, TK>::store(Are, Aim, a_rows, t, ra);
+    TileIO64<TN, TK>::store(Bre, Bim, b_rows, t, rb);
+    __syncthreads();
+    if (kt + 1 < nk) {
+      TileIO64<TM, TK>::load(A, a.lda, a.M, a.K, m0, (kt + 1) * TK, a_rows, a_conj, t, ra);
+      TileIO64<TN, TK>::load(B, a.ldb, a.N, a.K, n0, (kt + 1) * TK, b_rows, b_conj, t, rb);
+    }
+#pragma unroll
+    for (int ks = 0; ks < TK / 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      double ar[WM], ai[WM], br[WN], bi[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        ar[i] = Are[kk][wm + 16 * i + lr];
+        ai[i] = Aim[kk][wm + 16 * i + lr];
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        br[j] = Bre[kk][wn + 16 * j + lr];
+        bi[j] = Bim[kk][wn + 16 * j + lr];
+      }
+      if constexpr (M3) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
+            p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], p2[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i] + ai[i], br[j] + bi[j], p3[i][j], 0,
+                                                            0, 0);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
+            p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], p1[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], p3[i][j], 0, 0, 0);
+            p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], p3[i][j], 0, 0, 0);
+          }
+      }
+    }
+  }
+
+  // D layout of the 16x16x4 f64 MFMA: item r of a lane is row lane/16 + 4 r,
+  // column lane % 16.
+  const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
+  const int* rp = a.rpos ? a.rpos + (ll)blockIdx.y * a.srp : nullptr;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int col = n0 + wn + 16 * j + lr;
+      if (col >= a.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * i + lk + 4 * r;
+        if (row >= a.M) continue;
+        const double xr = M3 ? p1[i][j][r] - p2[i][j][r] : p1[i][j][r];
+        const double xi = M3 ? p3[i][j][r] - p1[i][j][r] - p2[i][j][r] : p3[i][j][r];
+        double2 v = make_double2(a.alpha.x * xr - a.alpha.y * xi, a.alpha.x * xi + a.alpha.y * xr);
+        double2* pc = C + (ll)row + (ll)col * a.ldc;
+        if (use_beta && !(rp && rp[row] >= a.plo && rp[row] < a.phi)) {
+          const double2 c = *pc;
+          v.x += a.beta.x * c.x - a.beta.y * c.y;
+          v.y += a.beta.x * c.y + a.beta.y * c.x;
+        }
+        *pc = v;
+      }
+    }
+}
+
+template <typename T, int WM, int WN, bool M3, int TK, int WAVES, bool SK = false, bool DIV = false>
+hipError_t launch_t(hipStream_t st, const ArgsT<T>& a, int batch, int splits = 1) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   const ll tiles = (ll)((a.M + TM - 1) / TM) * ((a.N + TN - 1) / TN);
   if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_kernel<T, WM, WN, M3, TK, WAVES>), dim3((unsigned)tiles, (unsigned)batch), dim3(NT),
-                     0, st, a);
+  hipLaunchKernelGGL((gemm_kernel<T, WM, WN, M3, TK, WAVES, SK, DIV>),
+                     dim3((unsigned)tiles, (unsigned)batch, splits), dim3(NT), 0, st, a);
   return hipGetLastError();
+}
+
+// C = alpha sum_z W[z] + beta C (rows in the overwrite range take beta = 0);
+// W[z] holds batch consecutive M x N blocks.
+__global__ void k_splitk_reduce(const double2* W, int splits, ll sz, int M, int N, double2 alpha, double2 beta,
+                                double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi, int batch) {
+  const ll per = (ll)M * N, total = per * batch;
+  const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll b = idx / per;
+    const int e = (int)(idx % per);
+    const int i = e % M, j = e / M;
+    double2 acc = W[idx];
+    for (int z = 1; z < splits; ++z) {
+      const double2 w = W[idx + z * sz];
+      acc.x += w.x;
+      acc.y += w.y;
+    }
+    double2 v = make_double2(alpha.x * acc.x - alpha.y * acc.y, alpha.x * acc.y + alpha.y * acc.x);
+    double2* pc = C + b * sC + (ll)i + (ll)j * ldc;
+    const int* rp = rpos ? rpos + b * srp : nullptr;
+    if (use_beta && !(rp && rp[i] >= plo && rp[i] < phi)) {
+      const double2 c = *pc;
+      v.x += beta.x * c.x - beta.y * c.y;
+      v.y += beta.x * c.y + beta.y * c.x;
+    }
+    *pc = v;
+  }
+}
+
+// Split-K workspace, one per stream (calls on one stream are ordered).
+struct SplitWs {
+  hipStream_t st;
+  void* p;
+  size_t bytes;
+};
+std::mutex g_ws_mu;
+std::vector<SplitWs> g_ws;
+
+hipError_t splitk_workspace(hipStream_t st, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto& w : g_ws)
+    if (w.st == st) {
+      if (w.bytes < bytes) {
+        HPS_HIP_TRY(hipStreamSynchronize(st));
+        HPS_HIP_TRY(hipFree(w.p));
+        w.p = nullptr;
+        w.bytes = 0;
+        HPS_HIP_TRY(hipMalloc(&w.p, bytes));
+        w.bytes = bytes;
+      }
+      *out = w.p;
+      return hipSuccess;
+    }
+  void* p = nullptr;
+  HPS_HIP_TRY(hipMalloc(&p, bytes));
+  g_ws.push_back({st, p, bytes});
+  *out = p;
+  return hipSuccess;
+}
+
+// Number of K slices for a call with fewer output tiles than compute units
+// and a long K: about two workgroups per compute unit, slices of at least
+// 512 (a split costs a reduction pass, so shapes that already fill the chip
+// are left alone).
+int choose_splits(int M, int N, int K, int batch) {
+  const ll tiles = (ll)((M + 63) / 64) * ((N + 31) / 32) * batch;
+  if (tiles >= 256 || K < 1024) return 1;
+  ll s = (512 + tiles - 1) / tiles;
+  if (s > K / 512) s = K / 512;
+  if (s > 16) s = 16;
+  return s < 2 ? 1 : (int)s;
 }
 template <int WM, int WN, bool M3, int TK, int WAVES>
 hipError_t launch(hipStream_t st, const Args& a, int batch) {
-  return launch_t<double, WM, WN, M3, TK, WAVES>(st, a, batch);
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  const ll tiles = (ll)((a.M + TM - 1) / TM) * ((a.N + TN - 1) / TN);
+  if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((zgemm_kernel<WM, WN, M3, TK, WAVES>), dim3((unsigned)tiles, (unsigned)batch), dim3(NT), 0,
+                     st, a);
+  return hipGetLastError();
 }
 
 // Kernel variants (tile WM x WN, 3M or four products, K step, waves per
@@ -329,13 +573,40 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535 || adiv < 1 || bdiv < 1) return hipErrorInvalidValue;
   Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, rpos, srp, plo, phi,
-         adiv, bdiv};
+         adiv, bdiv, K < 0 ? 0 : K, 0};
   const bool rb = (beta.x != 0.0 || beta.y != 0.0);
   KernelTimer kt(st, K_ZGEMM, 8.0 * M * N * (double)a.K * batch,
                  16.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);
   trace_call(a, batch);
+  if (adiv != 1 || bdiv != 1) {
+    if (a.K <= 64) return launch_t<double, 2, 1, true, 8, 3, false, true>(st, a, batch);
+    return launch_t<double, 2, 1, true, 16, 2, false, true>(st, a, batch);
+  }
   const int fv = forced_variant();
   if (fv >= 0) return VARIANTS[fv](st, a, batch);
+  const int splits = choose_splits(M, N, a.K, batch);
+  if (splits > 1) {
+    // partial products of K slices into the workspace, then one reduction
+    const ll per = (ll)M * N * batch;
+    void* ws = nullptr;
+    HPS_HIP_TRY(splitk_workspace(st, (size_t)per * splits * sizeof(double2), &ws));
+    Args p = a;
+    p.C = (double2*)ws;
+    p.ldc = M;
+    p.sC = (ll)M * N;
+    p.alpha = make_double2(1.0, 0.0);
+    p.beta = make_double2(0.0, 0.0);
+    p.rpos = nullptr;
+    p.kchunk = ((a.K + splits - 1) / splits + 15) / 16 * 16;
+    p.sCz = per;
+    const int used = (a.K + p.kchunk - 1) / p.kchunk;
+    HPS_HIP_TRY((launch_t<double, 2, 1, true, 16, 2, true>(st, p, batch, used)));
+    ll blocks = (per + NT - 1) / NT;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(NT), 0, st, (const double2*)ws, used, per, M,
+                       N, alpha, beta, C, ldc, sC, rpos, srp, plo, phi, batch);
+    return hipGetLastError();
+  }
   // Tuned on MI355X over the solver's shapes (rank-32 updates of the
   // inverses, leaf sweeps, merge products, top solve): all 3M.
   if (a.K <= 64) return launch<2, 1, true, 8, 3>(st, a, batch);
@@ -348,7 +619,7 @@ hipError_t cgemm(hipStream_t st, int opA, int opB, int M, int N, int K, float2 a
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
   ArgsT<float> a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, nullptr, 0,
-                 0, 0, 1, 1};
+                 0, 0, 1, 1, K < 0 ? 0 : K, 0};
   const bool rb = (beta.x != 0.0f || beta.y != 0.0f);
   KernelTimer kt(st, K_CGEMM, 8.0 * M * N * (double)a.K * batch,
                  8.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);

@@ -50,6 +50,32 @@ def test_zgemm_matches_cpu(M, N, K, batch, opA, opB):
     assert np.max(np.abs(got - ref) / scale) < 1e-14
 
 
+@pytest.mark.parametrize("M,N,K,batch,opA", [(256, 256, 7168, 1, 0), (100, 40, 3000, 3, 0), (200, 64, 1030, 2, 2),
+                                             (33, 17, 5000, 1, 1)])
+def test_zgemm_split_k(M, N, K, batch, opA):
+    """Few output tiles and a long K: the K range is split over workgroups
+    and reduced in a fixed order (same result on every call)."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    print(f"zgemm split-K M={M} N={N} K={K} batch={batch} opA={opA}", flush=True)
+    rng = np.random.default_rng(K + M)
+    A = _rand(rng, (batch, M, K) if opA == 0 else (batch, K, M))
+    B = _rand(rng, (batch, K, N))
+    C0 = _rand(rng, (batch, M, N))
+    f = {0: lambda x: x, 1: lambda x: np.swapaxes(x, 1, 2), 2: lambda x: np.conj(np.swapaxes(x, 1, 2))}
+    alpha, beta = 0.7 - 0.3j, -0.5 + 0.25j
+    ref = alpha * (f[opA](A) @ B) + beta * C0
+    outs = []
+    for rep in range(2):
+        C = _colmajor(torch, C0)
+        hps.zgemm(_colmajor(torch, A), _colmajor(torch, B), C, opA=opA, alpha=alpha, beta=beta)
+        torch.cuda.synchronize()
+        outs.append(_back(C))
+    scale = np.abs(f[opA](A)) @ np.abs(B) + np.abs(C0)
+    assert np.max(np.abs(outs[0] - ref) / scale) < 1e-14
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_zgemm_beta_zero_ignores_nan():
     torch = _torch()
     import paper_1608_06871_amd as hps
