@@ -30,6 +30,8 @@
 //     partial pivoting, candidate sets are reduced the same way until the
 //     panel's pivot rows remain, whose block is inverted (tp_block); the
 //     panel columns are then exchanged with one GEMM.
+#include <cfloat>
+
 #include "common.h"
 
 namespace hps {
@@ -41,12 +43,6 @@ constexpr int NS_MAX_N = 512;  // largest order handled by the register panel
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// Pivot magnitude |re| + |im|; NaN ranks as +inf so that the arg-max always
-// lands on an eligible row.
-__device__ inline double pivmag(double2 a) {
-  const double m = fabs(a.x) + fabs(a.y);
-  return m == m ? m : INFINITY;
 }
 __device__ inline double2 crecip(double2 a) {
   const double d = a.x * a.x + a.y * a.y;
@@ -90,65 +86,59 @@ __device__ __forceinline__ double2 cfms(double2 x, double2 g, double2 p) {
       ROW[(B0) + k_] = cfms(ROW[(B0) + k_], G, PR[(B0) + k_]); \
   } while (0)
 
-// Wave-wide arg-max of (v, i) by DPP moves inside each 16-lane row (quad
-// exchanges, then rotations by 4 and 8) and lane reads across the four
-// rows.  Every lane returns the winner; ties go to the lower index.
+// Pivot key of a candidate row: the magnitude |re| + |im| in the high bits
+// (its IEEE pattern orders like the value for non-negative numbers; NaN and
+// infinity rank as the largest finite value, so a pivot always lands on a
+// valid row) and 2047 - idx in the low 11 bits, so that the largest key is
+// the largest magnitude and ties (also magnitudes that agree to 41 bits) go
+// to the lowest idx (< 1024).  Key 0: no candidate.
+typedef unsigned long long u64;
+__device__ inline u64 pivkey(double2 a, int idx) {
+  double m = fabs(a.x) + fabs(a.y);
+  m = (m <= DBL_MAX) ? m : DBL_MAX;
+  return ((u64)__double_as_longlong(m) & ~(u64)0x7FF) | (u64)(2047 - idx);
+}
+__device__ inline int key_index(u64 k) { return 2047 - (int)(k & 0x7FF); }
+// no candidate, or a zero pivot
+__device__ inline bool key_zero(u64 k) { return (k >> 11) == 0; }
+
 template <int CTRL>
-__device__ __forceinline__ void amax_dpp(double& v, int& i) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
-  const double ov = __hiloint2double(hi, lo);
-  if (ov > v || (ov == v && oi < i)) {
-    v = ov;
-    i = oi;
-  }
+__device__ __forceinline__ u64 kmax_dpp(u64 k) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)k, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(k >> 32), CTRL, 0xF, 0xF, false);
+  const u64 o = ((u64)hi << 32) | lo;
+  return o > k ? o : k;
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
+__device__ __forceinline__ u64 readlane_u64(u64 v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((u64)hi << 32) | lo;
 }
 
-__device__ __forceinline__ int wave_argmax(double v, int i, double* best) {
-  amax_dpp<0xB1>(v, i);   // quad_perm [1, 0, 3, 2]
-  amax_dpp<0x4E>(v, i);   // quad_perm [2, 3, 0, 1]
-  amax_dpp<0x124>(v, i);  // row_ror:4
-  amax_dpp<0x128>(v, i);  // row_ror:8
-  double bv = readlane_f64(v, 0);
-  int bi = __builtin_amdgcn_readlane(i, 0);
-#pragma unroll
-  for (int r = 16; r < 64; r += 16) {
-    const double rv = readlane_f64(v, r);
-    const int ri = __builtin_amdgcn_readlane(i, r);
-    if (rv > bv || (rv == bv && ri < bi)) {
-      bv = rv;
-      bi = ri;
-    }
-  }
-  *best = bv;
-  return bi;
+// Wave-wide maximum key: DPP moves inside each 16-lane row (quad exchanges,
+// then rotations by 4 and 8), then lane reads of the four rows.  Uniform.
+__device__ __forceinline__ u64 wave_max_key(u64 k) {
+  k = kmax_dpp<0xB1>(k);   // quad_perm [1, 0, 3, 2]
+  k = kmax_dpp<0x4E>(k);   // quad_perm [2, 3, 0, 1]
+  k = kmax_dpp<0x124>(k);  // row_ror:4
+  k = kmax_dpp<0x128>(k);  // row_ror:8
+  const u64 a = readlane_u64(k, 0), b = readlane_u64(k, 16);
+  const u64 c = readlane_u64(k, 32), d = readlane_u64(k, 48);
+  const u64 ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
 }
 
-// Overall winner among the per-wave winners posted in LDS.
+// Largest of the per-wave keys posted in LDS (all read at once).
 template <int W>
-__device__ __forceinline__ int pick_winner(const double* cval, const int* cidx, double* best, int* wave) {
-  double bv = cval[0];
-  int p = cidx[0], pw = 0;
+__device__ __forceinline__ u64 pick_key(const u64* ck) {
+  u64 b = ck[0];
 #pragma unroll
   for (int q = 1; q < W; ++q) {
-    const double v = cval[q];
-    const int i = cidx[q];
-    if (v > bv || (v == bv && i < p)) {
-      bv = v;
-      p = i;
-      pw = q;
-    }
+    const u64 v = ck[q];
+    b = v > b ? v : b;
   }
-  *best = bv;
-  *wave = pw;
-  return p;
+  return b;
 }
 
 __global__ void gj_init(int* pos_all, int n) {
@@ -169,8 +159,8 @@ template <int W>
 __global__ __launch_bounds__(64 * W) void gj_panel(double2* Aall, ll lda, ll sA, int n, int c0, int b,
                                                    int* sig_all, int* pos_all, int* info) {
   __shared__ double2 cand[2][W][BMAX];
-  __shared__ double cval[2][W];
-  __shared__ int cidx[2][W];
+  __shared__ u64 ckey[2][W];
+  __shared__ double2 cinv[2][W];
   const ll bi = blockIdx.x;
   const int t = threadIdx.x;
   const int w = t >> 6;
@@ -193,20 +183,20 @@ __global__ __launch_bounds__(64 * W) void gj_panel(double2* Aall, ll lda, ll sA,
     const unsigned hot = 1u << c;                                              \
     double2 rc;                                                                \
     HPS_GET8(row, hot, B0, rc);                                                \
-    double wbest;                                                              \
-    const int wi = wave_argmax(isused ? -1.0 : pivmag(rc), t, &wbest);         \
-    if (t == wi) {                                                             \
+    const u64 wk = wave_max_key(isused ? 0ull : pivkey(rc, t));                \
+    /* every wave posts its key (0: no candidate left); the winner lane     \
+       posts its row and the reciprocal of its pivot */                        \
+    if ((t & 63) == 0) ckey[par][w] = wk;                                      \
+    if (t == key_index(wk)) {                                                  \
       _Pragma("unroll") for (int j = 0; j < BMAX; ++j) cand[par][w][j] = row[j]; \
-      cval[par][w] = wbest;                                                    \
-      cidx[par][w] = wi;                                                       \
+      cinv[par][w] = crecip(rc);                                               \
     }                                                                          \
     __syncthreads();                                                           \
-    double bv;                                                                 \
-    int pw;                                                                    \
-    const int p = pick_winner<W>(cval[par], cidx[par], &bv, &pw);              \
-    const bool zero = !(bv > 0.0);                                             \
+    const u64 bk = pick_key<W>(ckey[par]);                                     \
+    const int p = key_index(bk), pw = p >> 6;                                  \
+    const bool zero = key_zero(bk);                                            \
     const double2* pr = cand[par][pw];                                         \
-    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(pr[c]);         \
+    const double2 inv = zero ? make_double2(0.0, 0.0) : cinv[par][pw];         \
     if (t == 0) {                                                              \
       sig[c0 + c] = p;                                                         \
       if (zero) info[bi] = 1;                                                  \
@@ -284,69 +274,112 @@ constexpr int TF = 8;          // candidate sets merged per reduction workgroup
 constexpr int TRW = TF * BMAX / 64;  // waves of a reduction workgroup
 
 // Partial-pivoting elimination of up to 64 SW candidate rows of the panel
-// [c0, c0 + b): thread t holds row `id` (id < 0: no row) in registers.  Rows
-// never move; the pivot of each column is the largest remaining entry, its
-// row is posted to LDS (double-buffered, one barrier per column) and the
-// other remaining rows are eliminated against it (only the blocks of 8
-// columns that still matter).  selid[c] receives the id of the c-th pivot
-// row, -1 once the candidates are exhausted.
+// [c0, c0 + b).  Rows never move; the pivot of each column is the largest
+// remaining entry, its row is posted to LDS (double-buffered, one barrier per
+// column) and the remaining rows are eliminated against it.  selid[c]
+// receives the id of the c-th pivot row, -1 once the candidates are
+// exhausted.
+//
+// Register layout: lane l of wave w holds the set rows 64 w + (l & 15) + 16 i
+// (i = 0..3; ids in id[i], -1: no row) in the panel columns (l >> 4) + 4 k
+// (k = 0..7).  Every pivot-row value read from LDS thus serves four rows, and
+// the eliminated columns are spread evenly over the lanes, so that the
+// update skips whole k blocks.  The multipliers of column c live in the
+// lanes holding c and reach the other three lanes of each row by a lane
+// permutation (ds_bpermute).  The outer loop over k is unrolled (static
+// register indices); the inner loop over the four columns of a k block is not.
+__device__ __forceinline__ double bperm_f64(int addr, double x) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
 template <int SW>
-__device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, int id, int b,
-                                            double2 (*cand)[SW][BMAX], double (*cval)[SW],
-                                            int (*cidx)[SW], int* selid) {
-  const int t = threadIdx.x, w = t >> 6;
-  double2 row[BMAX];
+__device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, const int (&id)[4], int b,
+                                            double2 (*cand)[SW][BMAX], u64 (*ckey)[SW],
+                                            double2 (*cinv)[SW], int* selid) {
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, rg = lane & 15, cb = lane >> 4;
+  double2 v[4][8];
 #pragma unroll
-  for (int j = 0; j < BMAX; ++j)
-    row[j] = (id >= 0 && j < b) ? A[(ll)id + (ll)(c0 + j) * lda] : make_double2(0.0, 0.0);
-  bool done = id < 0;
-  bool out = false;  // candidates exhausted
-  // four rolled loops, one per block of 8 columns (see gj_panel); blocks left
-  // of the current one are dead and not updated
-#define HPS_SEL_STEP(B0)                                                       \
-  do {                                                                         \
-    const int par = c & 1;                                                     \
-    const unsigned hot = 1u << c;                                              \
-    double2 rc;                                                                \
-    HPS_GET8(row, hot, B0, rc);                                                \
-    double wbest;                                                              \
-    const int wi = wave_argmax(done ? -1.0 : pivmag(rc), t, &wbest);           \
-    if (t == wi) {                                                             \
-      _Pragma("unroll") for (int j = 0; j < BMAX; ++j) cand[par][w][j] = row[j]; \
-      cval[par][w] = wbest;                                                    \
-      cidx[par][w] = wi;                                                       \
-    }                                                                          \
-    __syncthreads();                                                           \
-    double bv;                                                                 \
-    int pw;                                                                    \
-    const int p = pick_winner<SW>(cval[par], cidx[par], &bv, &pw);             \
-    out = bv < 0.0; /* no candidate rows left (uniform) */                     \
-    const double2* pr = cand[par][pw];                                         \
-    const bool upd = (t != p) && !done && bv > 0.0;                            \
-    if (t == p && !out) {                                                      \
-      selid[c] = id;                                                           \
-      done = true;                                                             \
-    }                                                                          \
-    /* l = 0 leaves the row unchanged */                                       \
-    const double2 l = upd ? cmul(rc, crecip(pr[c])) : make_double2(0.0, 0.0);  \
-    if ((B0) <= 0) HPS_UPD8(row, l, pr, 0);                                    \
-    if ((B0) <= 8) HPS_UPD8(row, l, pr, 8);                                    \
-    if ((B0) <= 16) HPS_UPD8(row, l, pr, 16);                                  \
-    HPS_UPD8(row, l, pr, 24);                                                  \
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int col = cb + 4 * k;
+      v[i][k] = (id[i] >= 0 && col < b) ? A[(ll)id[i] + (ll)(c0 + col) * lda] : make_double2(0.0, 0.0);
+    }
+  bool done[4];
+  int lr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    done[i] = id[i] < 0;
+    lr[i] = 64 * w + rg + 16 * i;
+  }
+  bool out = false;
+  int cend = b;  // first column without a pivot row
+#define HPS_SEL_POST(I, K)                                                            \
+  do {                                                                               \
+    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) cand[par][w][cb + 4 * k_] = v[I][k_]; \
+    if (mine) cinv[par][w] = crecip(v[I][K]);                                        \
   } while (0)
-  int c = 0;
-#pragma unroll 1
-  for (; c < (b < 8 ? b : 8) && !out; ++c) HPS_SEL_STEP(0);
-#pragma unroll 1
-  for (; c < (b < 16 ? b : 16) && !out; ++c) HPS_SEL_STEP(8);
-#pragma unroll 1
-  for (; c < (b < 24 ? b : 24) && !out; ++c) HPS_SEL_STEP(16);
-#pragma unroll 1
-  for (; c < b && !out; ++c) HPS_SEL_STEP(24);
+#define HPS_SEL_STEP(K)                                                              \
+  _Pragma("unroll 1") for (int cbc = 0; cbc < 4 && !out; ++cbc) {                    \
+    const int c = 4 * (K) + cbc;                                                     \
+    if (c >= b) break;                                                               \
+    const int par = c & 1;                                                           \
+    const bool mine = (cb == cbc);                                                   \
+    u64 key = 0;                                                                     \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                  \
+      const u64 ki = (mine && !done[i]) ? pivkey(v[i][K], lr[i]) : 0ull;             \
+      key = ki > key ? ki : key;                                                     \
+    }                                                                                \
+    const u64 wk = wave_max_key(key);                                                \
+    if (lane == 0) ckey[par][w] = wk;                                                \
+    const int wl = key_index(wk);                                                    \
+    if (wk != 0ull && rg == (wl & 15)) {                                             \
+      const int iw = (wl >> 4) & 3; /* uniform */                                    \
+      if (iw == 0) HPS_SEL_POST(0, K);                                                  \
+      else if (iw == 1) HPS_SEL_POST(1, K);                                             \
+      else if (iw == 2) HPS_SEL_POST(2, K);                                             \
+      else HPS_SEL_POST(3, K);                                                          \
+    }                                                                                \
+    __syncthreads();                                                                 \
+    const u64 bk = pick_key<SW>(ckey[par]);                                          \
+    if (bk == 0ull) { /* no candidate rows left (uniform) */                         \
+      out = true;                                                                    \
+      cend = c;                                                                      \
+      break;                                                                         \
+    }                                                                                \
+    const int p = key_index(bk), pw = p >> 6, pi = (p >> 4) & 3;                     \
+    if (w == pw && rg == (p & 15)) {                                                 \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) done[i] = done[i] || (i == pi);  \
+      if (cb == 0) selid[c] = pi == 0 ? id[0] : pi == 1 ? id[1] : pi == 2 ? id[2] : id[3]; \
+    }                                                                                \
+    const double2 inv = key_zero(bk) ? make_double2(0.0, 0.0) : cinv[par][pw];      \
+    const int src = (rg + 16 * cbc) << 2;                                            \
+    double2 l[4];                                                                    \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                  \
+      const double2 m = cmul(v[i][K], inv);                                          \
+      l[i].x = bperm_f64(src, m.x);                                                  \
+      l[i].y = bperm_f64(src, m.y);                                                  \
+    }                                                                                \
+    const double2* pr = cand[par][pw];                                               \
+    _Pragma("unroll") for (int k = (K); k < 8; ++k) {                                \
+      const double2 pv = pr[cb + 4 * k];                                             \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) v[i][k] = cfms(v[i][k], l[i], pv); \
+    }                                                                                \
+  }
+  HPS_SEL_STEP(0)
+  HPS_SEL_STEP(1)
+  HPS_SEL_STEP(2)
+  HPS_SEL_STEP(3)
+  HPS_SEL_STEP(4)
+  HPS_SEL_STEP(5)
+  HPS_SEL_STEP(6)
+  HPS_SEL_STEP(7)
 #undef HPS_SEL_STEP
-  // the column at which the candidates ran out (if any) and the rest: none
+#undef HPS_SEL_POST
   if (out)
-    for (int k = c - 1 + t; k < b; k += 64 * SW) selid[k] = -1;
+    for (int k = cend + t; k < b; k += 64 * SW) selid[k] = -1;
   __syncthreads();
 }
 
@@ -355,41 +388,42 @@ __device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, in
 __global__ __launch_bounds__(TR) void tp_leaf(const double2* Aall, ll lda, ll sA, int n, int c0, int b,
                                               int G, const int* pos_all, int* cand_all) {
   __shared__ double2 cand[2][TLW][BMAX];
-  __shared__ double cval[2][TLW];
-  __shared__ int cidx[2][TLW];
+  __shared__ u64 ckey[2][TLW];
+  __shared__ double2 cinv[2][TLW];
   __shared__ int selid[BMAX];
   const ll bi = blockIdx.y;
   const int g = blockIdx.x, t = threadIdx.x;
-  const int r = g * TR + t;
-  const int id = (r < n && pos_all[bi * n + r] < 0) ? r : -1;
-  select_rows<TLW>(Aall + bi * sA, lda, c0, id, b, cand, cval, cidx, selid);
+  const int base = g * TR + 64 * (t >> 6) + (t & 15);
+  int id[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = base + 16 * i;
+    id[i] = (r < n && pos_all[bi * n + r] < 0) ? r : -1;
+  }
+  select_rows<TLW>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid);
   int* out = cand_all + (bi * G + g) * (ll)b;
   if (t < b) out[t] = selid[t];
 }
 
 // Reduction: workgroup g merges candidate sets [TF g, TF g + TF) of Gin
-// (entries -1 mark missing candidates).
+// (entries -1 mark missing candidates); the sets are taken in order, so ties
+// go to the earlier set.
 __global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll lda, ll sA, int c0, int b,
                                                       int Gin, const int* cin_all, int Gout, int* cout_all) {
   __shared__ double2 cand[2][TRW][BMAX];
-  __shared__ double cval[2][TRW];
-  __shared__ int cidx[2][TRW];
+  __shared__ u64 ckey[2][TRW];
+  __shared__ double2 cinv[2][TRW];
   __shared__ int selid[BMAX];
-  __shared__ int ids[TF * BMAX];
-  __shared__ int nsel;
   const ll bi = blockIdx.y;
   const int g = blockIdx.x, t = threadIdx.x;
-  const int* cin = cin_all + bi * (ll)Gin * b;
-  if (t == 0) {
-    int k = 0;
-    for (int s = TF * g; s < TF * g + TF && s < Gin; ++s)
-      for (int i = 0; i < b; ++i)
-        if (cin[(ll)s * b + i] >= 0) ids[k++] = cin[(ll)s * b + i];
-    nsel = k;
-  }
-  __syncthreads();
-  const int id = (t < nsel) ? ids[t] : -1;
-  select_rows<TRW>(Aall + bi * sA, lda, c0, id, b, cand, cval, cidx, selid);
+  // slot j of the group: entry j % b of candidate set TF g + j / b (-1: none)
+  const int nslot = (Gin - TF * g < TF ? Gin - TF * g : TF) * b;
+  const int* cin = cin_all + (bi * Gin + TF * g) * (ll)b;
+  const int base = 64 * (t >> 6) + (t & 15);
+  int id[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) id[i] = (base + 16 * i < nslot) ? cin[base + 16 * i] : -1;
+  select_rows<TRW>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid);
   int* out = cout_all + (bi * Gout + g) * (ll)b;
   if (t < b) out[t] = selid[t];
 }

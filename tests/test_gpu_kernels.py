@@ -115,6 +115,34 @@ def test_zinv_reports_singular():
     assert e.value.code == hps.HPS_ESINGULAR
 
 
+@pytest.mark.parametrize("n", [64, 600])
+def test_zinv_equal_magnitudes(n):
+    """Every entry of a Fourier matrix has the same magnitude, so every pivot
+    search is a tie (broken towards the lowest row); the inverse is exact up
+    to rounding (the matrix is unitary up to scale)."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    j = np.arange(n)
+    F = np.exp(-2j * np.pi * np.outer(j, j) / n)[None]
+    inv = _back(hps.zinv(_colmajor(torch, F)))[0]
+    ref = np.conj(F[0]).T / n
+    assert np.max(np.abs(inv - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [40, 700])
+def test_zinv_nan_entry_propagates(n):
+    """A NaN entry ranks as the largest pivot candidate: the call completes and
+    the NaN reaches the inverse instead of being hidden."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    rng = np.random.default_rng(n)
+    A = _rand(rng, (1, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    A[0, n // 3, 0] = np.nan
+    inv = _back(hps.zinv(_colmajor(torch, A)))
+    torch.cuda.synchronize()
+    assert np.isnan(inv).any()
+
+
 @pytest.mark.parametrize("n", [252, 700])
 def test_zinv_row_scaled_keeps_accuracy(n):
     """Rows scaled by 1e6 (like the PDE rows of a small leaf next to its
