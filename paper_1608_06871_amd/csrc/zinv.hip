@@ -22,9 +22,9 @@
 // have inner dimensions up to n / 2.
 //
 // Leaves of the recursion are panels of at most 32 columns:
-//   - n <= 512: one workgroup per matrix, thread r holding row r of the panel
-//     in registers; per column a wave arg-max (DPP), one LDS exchange of the
-//     wave winners (one barrier) and the register update;
+//   - n <= 512: one workgroup per matrix, the panel in registers (four rows
+//     by eight columns per lane); per column a wave arg-max (DPP), one LDS
+//     exchange of the wave winners (one barrier) and the register update;
 //   - n > 512: tournament pivoting (communication-avoiding LU, Grigori,
 //     Demmel and Xiang 2011): chunks of rows pick candidate pivot rows by
 //     partial pivoting, candidate sets are reduced the same way until the
@@ -58,33 +58,6 @@ __device__ __forceinline__ double2 cfms(double2 x, double2 g, double2 p) {
   r.y = fma(-g.y, p.x, r.y);
   return r;
 }
-
-// Register-row access with a run-time column c inside a block of 8 columns
-// known at compile time (B0): one-hot selects, so every register index stays
-// static.  These are macros, not functions: a helper taking the row by
-// reference is optimised on its own first, and there the selects of loads
-// become loads from selected addresses, which then pin the caller's row array
-// in scratch memory.
-#define HPS_GET8(ROW, HOT, B0, OUT)                  \
-  do {                                               \
-    OUT = ROW[B0];                                   \
-    _Pragma("unroll") for (int k_ = 1; k_ < 8; ++k_) \
-      if (((HOT) >> ((B0) + k_)) & 1u) OUT = ROW[(B0) + k_]; \
-  } while (0)
-#define HPS_SET8(ROW, HOT, B0, V)                             \
-  do {                                                        \
-    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_)          \
-      if (((HOT) >> ((B0) + k_)) & 1u) ROW[(B0) + k_] = (V);  \
-  } while (0)
-// ROW[j] -= G PR[j] for the columns of block B0 (PR in LDS; the scheduling
-// barrier keeps the reads of later blocks from being hoisted, which would
-// double the register footprint)
-#define HPS_UPD8(ROW, G, PR, B0)                     \
-  do {                                               \
-    __builtin_amdgcn_sched_barrier(0);               \
-    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) \
-      ROW[(B0) + k_] = cfms(ROW[(B0) + k_], G, PR[(B0) + k_]); \
-  } while (0)
 
 // Pivot key of a candidate row: the magnitude |re| + |im| in the high bits
 // (its IEEE pattern orders like the value for non-negative numbers; NaN and
@@ -147,14 +120,25 @@ __global__ void gj_init(int* pos_all, int n) {
   if (r < n) pos_all[bi * n + r] = -1;
 }
 
-// Panel [c0, c0 + b) for n <= 64 W.  Thread r owns row r of the panel in
-// registers.  Per column: a wave arg-max over the unused rows; each wave's
-// winner posts its row to LDS (double-buffered by column parity, so one
-// barrier per column suffices); every thread picks the overall winner p and
-// applies the Jordan exchange at (p, c).  The column loop is not unrolled
-// (one copy of the step stays in the instruction cache); the current column
-// is picked from the register row by one-hot selects, so every register index
-// stays static.
+__device__ __forceinline__ double bperm_f64(int addr, double x) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// Panel [c0, c0 + b) of an order-n matrix, n <= 64 W, one workgroup per
+// matrix.  Register layout: lane l of wave w holds the rows
+// 64 w + (l & 15) + 16 i (i = 0..3) in the panel columns (l >> 4) + 4 k
+// (k = 0..7), so every pivot-row value read from LDS serves four rows.
+// Per column c: the lanes holding c form pivot keys of their unused rows, a
+// wave maximum is taken, each wave's winner row is posted to LDS with the
+// reciprocal of its pivot (double-buffered by column parity, one barrier per
+// column); every lane then picks the overall winner p, fetches the
+// multipliers g = M[r][c] / M[p][c] of its rows from the lanes holding c
+// (ds_bpermute) and applies the Jordan exchange at (p, c): rows r != p take
+// M[r][j] - g M[p][j] and -g in column c, row p takes M[p][j] / M[p][c] and
+// the reciprocal in column c.  The loop over k is unrolled (static register
+// indices); the loop over the four columns of a k block is not.
 template <int W>
 __global__ __launch_bounds__(64 * W) void gj_panel(double2* Aall, ll lda, ll sA, int n, int c0, int b,
                                                    int* sig_all, int* pos_all, int* info) {
@@ -162,77 +146,108 @@ __global__ __launch_bounds__(64 * W) void gj_panel(double2* Aall, ll lda, ll sA,
   __shared__ u64 ckey[2][W];
   __shared__ double2 cinv[2][W];
   const ll bi = blockIdx.x;
-  const int t = threadIdx.x;
-  const int w = t >> 6;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, rg = lane & 15, cb = lane >> 4;
   double2* A = Aall + bi * sA;
   int* sig = sig_all + bi * n;
   int* pos = pos_all + bi * n;
-  const bool own = t < n;
-  bool isused = own ? (pos[t] >= 0) : true;
-  int mycol = -1;
-  double2 row[BMAX];
+  int lr[4];
+  bool used[4];
+  int mycol[4];
+  double2 v[4][8];
 #pragma unroll
-  for (int j = 0; j < BMAX; ++j)
-    row[j] = (own && j < b) ? A[(ll)t + (ll)(c0 + j) * lda] : make_double2(0.0, 0.0);
-  // The column loop is split into four rolled loops, one per block of 8
-  // columns, so that the block of the current column is a compile-time
-  // constant (B0) while one copy of each step stays in the instruction cache.
-#define HPS_GJ_STEP(B0)                                                        \
-  do {                                                                         \
-    const int par = c & 1;                                                     \
-    const unsigned hot = 1u << c;                                              \
-    double2 rc;                                                                \
-    HPS_GET8(row, hot, B0, rc);                                                \
-    const u64 wk = wave_max_key(isused ? 0ull : pivkey(rc, t));                \
-    /* every wave posts its key (0: no candidate left); the winner lane     \
-       posts its row and the reciprocal of its pivot */                        \
-    if ((t & 63) == 0) ckey[par][w] = wk;                                      \
-    if (t == key_index(wk)) {                                                  \
-      _Pragma("unroll") for (int j = 0; j < BMAX; ++j) cand[par][w][j] = row[j]; \
-      cinv[par][w] = crecip(rc);                                               \
-    }                                                                          \
-    __syncthreads();                                                           \
-    const u64 bk = pick_key<W>(ckey[par]);                                     \
-    const int p = key_index(bk), pw = p >> 6;                                  \
-    const bool zero = key_zero(bk);                                            \
-    const double2* pr = cand[par][pw];                                         \
-    const double2 inv = zero ? make_double2(0.0, 0.0) : cinv[par][pw];         \
-    if (t == 0) {                                                              \
-      sig[c0 + c] = p;                                                         \
-      if (zero) info[bi] = 1;                                                  \
-    }                                                                          \
-    /* other rows: row - g pr with -g in column c (g = row[c] inv); the       \
-       pivot row: pr inv with inv in column c (one wave takes that branch) */ \
-    const bool piv = (t == p);                                                 \
-    const double2 g = (own && !piv) ? cmul(rc, inv) : make_double2(0.0, 0.0);  \
-    HPS_UPD8(row, g, pr, 0);                                                   \
-    HPS_UPD8(row, g, pr, 8);                                                   \
-    HPS_UPD8(row, g, pr, 16);                                                  \
-    HPS_UPD8(row, g, pr, 24);                                                  \
-    if ((p >> 6) == w) {                                                       \
-      if (piv) {                                                               \
-        isused = true;                                                         \
-        mycol = c0 + c;                                                        \
-        _Pragma("unroll") for (int j = 0; j < BMAX; ++j) row[j] = cmul(pr[j], inv); \
-      }                                                                        \
-    }                                                                          \
-    const double2 nv = piv ? inv : make_double2(-g.x, -g.y);                   \
-    HPS_SET8(row, hot, B0, nv);                                                \
+  for (int i = 0; i < 4; ++i) {
+    lr[i] = 64 * w + rg + 16 * i;
+    used[i] = lr[i] < n ? (pos[lr[i]] >= 0) : true;
+    mycol[i] = -1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int col = cb + 4 * k;
+      v[i][k] = (lr[i] < n && col < b) ? A[(ll)lr[i] + (ll)(c0 + col) * lda] : make_double2(0.0, 0.0);
+    }
+  }
+#define HPS_GJ_POST(I, K)                                                            \
+  do {                                                                               \
+    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) cand[par][w][cb + 4 * k_] = v[I][k_]; \
+    if (mine) cinv[par][w] = crecip(v[I][K]);                                        \
   } while (0)
-#pragma unroll 1
-  for (int c = 0; c < (b < 8 ? b : 8); ++c) HPS_GJ_STEP(0);
-#pragma unroll 1
-  for (int c = 8; c < (b < 16 ? b : 16); ++c) HPS_GJ_STEP(8);
-#pragma unroll 1
-  for (int c = 16; c < (b < 24 ? b : 24); ++c) HPS_GJ_STEP(16);
-#pragma unroll 1
-  for (int c = 24; c < b; ++c) HPS_GJ_STEP(24);
+#define HPS_GJ_STEP(K)                                                               \
+  _Pragma("unroll 1") for (int cbc = 0; cbc < 4; ++cbc) {                            \
+    const int c = 4 * (K) + cbc;                                                     \
+    if (c >= b) break;                                                               \
+    const int par = c & 1;                                                           \
+    const bool mine = (cb == cbc);                                                   \
+    u64 key = 0;                                                                     \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                  \
+      const u64 ki = (mine && !used[i]) ? pivkey(v[i][K], lr[i]) : 0ull;             \
+      key = ki > key ? ki : key;                                                     \
+    }                                                                                \
+    const u64 wk = wave_max_key(key);                                                \
+    if (lane == 0) ckey[par][w] = wk;                                                \
+    const int wl = key_index(wk);                                                    \
+    if (wk != 0ull && rg == (wl & 15)) {                                             \
+      const int iw = (wl >> 4) & 3; /* uniform */                                    \
+      if (iw == 0) HPS_GJ_POST(0, K);                                                \
+      else if (iw == 1) HPS_GJ_POST(1, K);                                           \
+      else if (iw == 2) HPS_GJ_POST(2, K);                                           \
+      else HPS_GJ_POST(3, K);                                                        \
+    }                                                                                \
+    __syncthreads();                                                                 \
+    const u64 bk = pick_key<W>(ckey[par]);                                           \
+    const int p = key_index(bk), pw = p >> 6, pi = (p >> 4) & 3;                     \
+    const bool zero = key_zero(bk);                                                  \
+    if (t == 0) {                                                                    \
+      sig[c0 + c] = p;                                                               \
+      if (zero) info[bi] = 1;                                                        \
+    }                                                                                \
+    const double2 inv = zero ? make_double2(0.0, 0.0) : cinv[par][pw];              \
+    const bool prow = (w == pw && rg == (p & 15)); /* lanes of row p */              \
+    const int src = (rg + 16 * cbc) << 2;                                            \
+    double2 g[4];                                                                    \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                  \
+      const bool ip = prow && i == pi;                                               \
+      const double2 m = cmul(v[i][K], inv);                                          \
+      g[i].x = bperm_f64(src, m.x);                                                  \
+      g[i].y = bperm_f64(src, m.y);                                                  \
+      if (ip) g[i] = make_double2(0.0, 0.0);                                         \
+    }                                                                                \
+    const double2* pr = cand[par][pw];                                               \
+    _Pragma("unroll") for (int k = 0; k < 8; ++k) {                                  \
+      const double2 pv = pr[cb + 4 * k];                                             \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) v[i][k] = cfms(v[i][k], g[i], pv); \
+    }                                                                                \
+    if (prow) {                                                                      \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i)                                  \
+        if (i == pi) {                                                               \
+          used[i] = true;                                                            \
+          mycol[i] = c0 + c;                                                         \
+          _Pragma("unroll") for (int k = 0; k < 8; ++k) v[i][k] = cmul(v[i][k], inv); \
+        }                                                                            \
+    }                                                                                \
+    if (mine) {                                                                      \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i)                                  \
+        v[i][K] = (prow && i == pi) ? inv : make_double2(-g[i].x, -g[i].y);          \
+    }                                                                                \
+  }
+  HPS_GJ_STEP(0)
+  HPS_GJ_STEP(1)
+  HPS_GJ_STEP(2)
+  HPS_GJ_STEP(3)
+  HPS_GJ_STEP(4)
+  HPS_GJ_STEP(5)
+  HPS_GJ_STEP(6)
+  HPS_GJ_STEP(7)
 #undef HPS_GJ_STEP
-  if (own) {
+#undef HPS_GJ_POST
 #pragma unroll
-    for (int j = 0; j < BMAX; ++j)
-      if (j < b) A[(ll)t + (ll)(c0 + j) * lda] = row[j];
-    if (mycol >= 0) pos[t] = mycol;
+  for (int i = 0; i < 4; ++i) {
+    if (lr[i] < n) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int col = cb + 4 * k;
+        if (col < b) A[(ll)lr[i] + (ll)(c0 + col) * lda] = v[i][k];
+      }
+      if (mycol[i] >= 0 && cb == 0) pos[lr[i]] = mycol[i];
+    }
   }
 }
 
@@ -288,12 +303,6 @@ constexpr int TRW = TF * BMAX / 64;  // waves of a reduction workgroup
 // lanes holding c and reach the other three lanes of each row by a lane
 // permutation (ds_bpermute).  The outer loop over k is unrolled (static
 // register indices); the inner loop over the four columns of a k block is not.
-__device__ __forceinline__ double bperm_f64(int addr, double x) {
-  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
-  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
-  return __hiloint2double(hi, lo);
-}
-
 template <int SW>
 __device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, const int (&id)[4], int b,
                                             double2 (*cand)[SW][BMAX], u64 (*ckey)[SW],
