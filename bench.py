@@ -81,6 +81,51 @@ def cpu_baseline(cfg, L_sample=8):
                       f"{P} angles: {dt:.1f} s; SuperLU on 1 thread, dense parts on {blas} BLAS threads"}
 
 
+def sine_truth(S, seed=4):
+    """Sine coefficients of a smooth contrast: c_mn = 0.3 g_mn exp(-(m^2 + n^2)
+    / 800), g ~ N(0, 1), later rescaled so that max q = 0.5 at the nodes."""
+    rng = np.random.default_rng(seed)
+    m = np.arange(1, S + 1)
+    env = np.exp(-(m[:, None] ** 2 + m[None, :] ** 2) / 800.0)
+    return 0.3 * rng.standard_normal((S, S)) * env
+
+
+def gn_timing(s, k, dirs, th, R, steps, S=160, cg_iters=30):
+    """Gauss-Newton steps on the sine model (S x S modes) at the benchmark's
+    k, grid and directions: factor + solve at the current coefficients, then
+    a fixed number of CG iterations, each one JVP and one VJP over all
+    directions.  The data are the far field of a known contrast."""
+    import torch
+    c = torch.from_numpy(sine_truth(S).ravel()).cuda()
+    q = s.sine_eval(c)
+    scale = 0.5 / float(q.abs().max())
+    c *= scale
+    s.factor(s.sine_eval(c), k)
+    s.solve(dirs)
+    data = s.far_field(th, R).clone()
+    c0 = 0.5 * c
+    out = torch.empty_like(c)
+    s.gn_step(k, dirs, th, R, c0, data, max_iter=cg_iters, tol=0.0, out=out)
+    torch.cuda.synchronize()
+    times, info = [], None
+    for i in range(steps):
+        t0 = time.perf_counter()
+        _, info = s.gn_step(k, dirs, th, R, c0, data, max_iter=cg_iters, tol=0.0, out=out)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        log(f"gn step {i + 1}/{steps}: {times[-1]:.0f} ms, {info['cg_iters']} CG iterations")
+    ms = float(np.median(times))
+    M = len(dirs)
+    # relative model error after the step (the data are exact, so one
+    # Gauss-Newton step from half the true contrast should close most of it)
+    err = float((out - c).norm() / c.norm())
+    return {"ms_per_gn_step": ms, "modes": S * S, "cg_iters": int(info["cg_iters"]),
+            "cg_rel_res": float(info["cg_rel_res"]), "misfit_before": float(info["misfit"]),
+            "rhs_solves_per_step": (2 * int(info["cg_iters"]) + 1) * M,
+            "rhs_solves_per_s": (2 * int(info["cg_iters"]) + 1) * M / (ms * 1e-3),
+            "model_rel_err_after_step": err, "start": "half the true coefficients"}
+
+
 def batch_problems(n=32, seed0=100):
     """32 independent problems: k ~ U[10, 60], leaf grids 8, 16 or 32 per
     side, 16 to 256 directions, contrasts from the 5-bump generator."""
@@ -176,6 +221,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-gn", action="store_true", help="skip the Gauss-Newton step timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (--gpus {args.gpus} "
@@ -263,6 +309,13 @@ def main():
                         "bytes_per_launch": kd["bytes"] / kd["launches"]}
         log("kernel classes: " + ", ".join(f"{n} {v['total_ms']:.1f} ms/{v['launches']}" for n, v in kernels.items()))
 
+    gn = None
+    if not args.no_gn:
+        log("Gauss-Newton steps (160 x 160 sine modes, 30 CG iterations) ...")
+        gn = gn_timing(s, k, dirs, th, R, max(1, min(args.steps, 2)))
+        log(f"gn: {gn['ms_per_gn_step']:.0f} ms per step, model error after the step "
+            f"{gn['model_rel_err_after_step']:.2e}")
+
     mixed = None
     if not args.no_mixed:
         # the same workload in mixed precision (complex64 sweeps + refinement),
@@ -335,6 +388,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "gauss_newton": gn,
     }
     print(json.dumps(out), flush=True)
 

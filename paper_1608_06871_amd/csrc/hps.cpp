@@ -108,6 +108,9 @@ struct hps_ctx {
   DBuf dA0, dMout, dBop, dA1, dA2, dbnode;
   DBuf dPk;  // device [k (P) | k^2 (P) | eta (P)]
   std::vector<DBuf> didx;  // 4 index arrays per level
+  // leaf-edge slots: [1 .. nlev] the shared nodes of a merge ([alpha; beta]
+  // sides), [0] the outer boundary in root order
+  std::vector<DBuf> dSlot;
 
   // mixed precision
   bool mixed = false;
@@ -625,44 +628,20 @@ double mixed_residual(hps_ctx* c, int M, const double2*& froot, const double2*& 
   const int P = c->P, ne = g.ne, nb = c->nb, nl = g.nleaf * P;
   CK(zgemm(st, OP_N, OP_N, ne, M, ne, ONE, c->dRleaf.z(), ne, (ll)ne * ne, c->dFl.z(), ne, (ll)ne * M, ZERO,
            c->dGl.z(), ne, (ll)ne * M, nl));
-  const double2* fc = c->dFl.z();
-  const double2* gc = c->dGl.z();
-  double2* fo[2] = {c->rF0.z(), c->rF1.z()};
-  double2* go[2] = {c->rG0.z(), c->rG1.z()};
   double* partial = c->sNorm.d();
   double* nrm = partial + 256;  // [0] f, [1] rhs, [2] r_b, [3 ..] rho per level
-  int pp = 0;
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
-    const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;
-    const ll sc = 2LL * nc * M, sp = (ll)np * M, s3 = 2LL * s * M;
-    const double2* fa = fc;
-    const double2* fb = fc + (ll)nc * M;
-    const double2* ga = gc;
-    const double2* gb = gc + (ll)nc * M;
-    const int* i1a = c->didx[4 * l].i();
-    const int* i3a = c->didx[4 * l + 1].i();
-    const int* i2b = c->didx[4 * l + 2].i();
-    const int* i3b = c->didx[4 * l + 3].i();
-    double2* fp = fo[pp];
-    double2* gp = go[pp];
-    CK(gather2d(st, m, M, fa, nc, sc, i1a, nullptr, fp, np, sp, 1.0, cnt));
-    CK(gather2d(st, m, M, fb, nc, sc, i2b, nullptr, fp + m, np, sp, 1.0, cnt));
-    CK(gather2d(st, m, M, ga, nc, sc, i1a, nullptr, gp, np, sp, 1.0, cnt));
-    CK(gather2d(st, m, M, gb, nc, sc, i2b, nullptr, gp + m, np, sp, 1.0, cnt));
-    double2* t0 = c->rT0.z();
-    double2* t1 = c->rT1.z();
-    CK(gather2d(st, s, M, fb, nc, sc, i3b, nullptr, t0, 2 * s, s3, 1.0, cnt));
-    CK(gather2d(st, s, M, fa, nc, sc, i3a, nullptr, t0 + s, 2 * s, s3, 1.0, cnt));
-    CK(gather2d(st, s, M, ga, nc, sc, i3a, nullptr, t1, 2 * s, s3, 1.0, cnt));
-    CK(gather2d(st, s, M, gb, nc, sc, i3b, nullptr, t1 + s, 2 * s, s3, 1.0, cnt));
-    const ll nr = (ll)cnt * s3;
-    CK(zadd(st, t0, t1, c->dRho[l].z(), nr));
+    const int cnt = L.count * P, s = L.s;
+    const ll nr = (ll)cnt * 2 * s * M;
+    CK(skel_residual(st, s, M, ne, 1 << l, c->dSlot[l].i(), c->dFl.z(), c->dGl.z(), c->dRho[l].z(), cnt));
     CK(dot(st, (const double*)c->dRho[l].p, (const double*)c->dRho[l].p, 2 * nr, partial, nrm + 2 + l));
-    fc = fp;
-    gc = gp;
-    pp ^= 1;
   }
+  // outer-boundary data in root order
+  double2* fc = c->rF0.z();
+  double2* gc = c->rG0.z();
+  CK(skel_gather(st, nb, M, ne, g.nleaf, c->dSlot[0].i(), c->dFl.z(), fc, P));
+  CK(skel_gather(st, nb, M, ne, g.nleaf, c->dSlot[0].i(), c->dGl.z(), gc, P));
   froot = fc;
   groot = gc;
   const ll sF = (ll)nb * M, sbb = (ll)nb * nb, ntop = (ll)P * sF;
@@ -1190,6 +1169,33 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
       const std::vector<int>* v[4] = {&P.pos1a, &P.pos3a, &P.pos2b, &P.pos3b};
       for (int a = 0; a < 4; ++a)
         upload(c->didx[4 * l + a], v[a]->data(), v[a]->size() * sizeof(int), c->st);
+    }
+    // leaf-edge slot (leaf offset inside the box * ne + edge position) of
+    // every boundary position of a box, level by level: a box lists the
+    // exterior nodes of its alpha child, then those of its beta child
+    {
+      const Geometry& g = c->g;
+      std::vector<int> prev(g.ne), cur;
+      for (int e = 0; e < g.ne; ++e) prev[e] = e;
+      c->dSlot.resize(g.nlev + 1);
+      for (int l = 1; l <= g.nlev; ++l) {
+        const LevelPattern& P = g.lev[l];
+        const int half = (1 << (l - 1)) * g.ne;  // slots of the alpha child
+        std::vector<int> sab(2 * (size_t)P.s);
+        for (int j = 0; j < P.s; ++j) {
+          sab[j] = prev[P.pos3a[j]];
+          sab[P.s + j] = prev[P.pos3b[j]] + half;
+        }
+        upload(c->dSlot[l], sab.data(), sab.size() * sizeof(int), c->st);
+        cur.assign(P.np, 0);
+        for (int i = 0; i < P.m; ++i) {
+          cur[i] = prev[P.pos1a[i]];
+          cur[P.m + i] = prev[P.pos2b[i]] + half;
+        }
+        prev.swap(cur);
+      }
+      if ((int)prev.size() != c->nb) throw HpsError{HPS_EINVAL, "root boundary size mismatch"};
+      upload(c->dSlot[0], prev.data(), prev.size() * sizeof(int), c->st);
     }
     for (auto& e : c->ev) CK(hipEventCreate(&e));
   });

@@ -29,6 +29,16 @@ hipError_t add_f32(hipStream_t st, const float2* x, ll n, double2* y);
 hipError_t to_f64(hipStream_t st, const float2* x, ll n, double2* y);
 hipError_t add_to_f32(hipStream_t st, const double2* x, ll n, float2* y);
 hipError_t zadd(hipStream_t st, const double2* x, const double2* y, double2* z, ll n);
+// Interface residual of one level from leaf-edge data F, G ([leaf][ne][M]):
+// sab = [alpha slots (s); beta slots (s)] relative to a merge's first leaf,
+// lpm leaves per merge, cnt merges; rho = [F(beta) + G(alpha); F(alpha) +
+// G(beta)] per merge, leading dimension 2 s.
+hipError_t skel_residual(hipStream_t st, int s, int M, int ne, int lpm, const int* sab, const double2* F,
+                         const double2* G, double2* rho, int cnt);
+// out[b] (n x M, leading dimension n) = X at the n slots of box b (lpb leaves
+// per box).
+hipError_t skel_gather(hipStream_t st, int n, int M, int ne, int lpb, const int* slot, const double2* X,
+                       double2* out, int nbox);
 // out = off everywhere, diag on the diagonal.
 hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
                  double2 off, int batch);

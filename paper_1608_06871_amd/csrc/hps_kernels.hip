@@ -246,6 +246,50 @@ __global__ void k_zadd(const double2* x, const double2* y, double2* z, ll n) {
     z[i] = make_double2(x[i].x + y[i].x, x[i].y + y[i].y);
 }
 
+// Skeleton data addressing: leaf-edge data X is [leaf][ne][M] (column-major
+// per leaf, leading dimension ne); a slot is (leaf offset inside a box) * ne +
+// (edge position).  Box b of a level owns the leaves [b lpb, (b + 1) lpb).
+__device__ inline ll slot_addr(int slot, ll box_leaf0, int ne, int M, int col) {
+  const int lo = slot / ne, e = slot - lo * ne;
+  return (box_leaf0 + lo) * (ll)ne * M + e + (ll)col * ne;
+}
+
+// Interface residual of one level: for merge t and shared node j with slots
+// sa[j] (alpha side) and sb[j] (beta side),
+//   rho[t][j][col]     = F[sb[j]] + G[sa[j]]   (f of beta + g of alpha),
+//   rho[t][s + j][col] = F[sa[j]] + G[sb[j]],
+// rho column-major per merge with leading dimension 2 s.
+__global__ void k_skel_residual(int s, int M, int ne, int lpm, const int* sab, const double2* F,
+                                const double2* G, double2* rho, ll total) {
+  const int s2 = 2 * s;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const int r = (int)(idx % s2);
+    const ll rest = idx / s2;
+    const int col = (int)(rest % M);
+    const ll t = rest / M;
+    const int j = r < s ? r : r - s;
+    const int fs = r < s ? sab[s + j] : sab[j];
+    const int gs = r < s ? sab[j] : sab[s + j];
+    const ll l0 = t * lpm;
+    const double2 f = F[slot_addr(fs, l0, ne, M, col)];
+    const double2 g = G[slot_addr(gs, l0, ne, M, col)];
+    rho[t * s2 * M + r + (ll)col * s2] = make_double2(f.x + g.x, f.y + g.y);
+  }
+}
+
+// out[b][i][col] = X[slot[i]] of box b (n slots per box, column-major per
+// box with leading dimension n).
+__global__ void k_skel_gather(int n, int M, int ne, int lpb, const int* slot, const double2* X,
+                              double2* out, ll total) {
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const int i = (int)(idx % n);
+    const ll rest = idx / n;
+    const int col = (int)(rest % M);
+    const ll b = rest / M;
+    out[idx] = X[slot_addr(slot[i], b * lpb, ne, M, col)];
+  }
+}
+
 // y = a x + b y
 __global__ void k_axpby(double a, const double* x, double b, double* y, ll n) {
   for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT) y[i] = a * x[i] + b * y[i];
@@ -350,6 +394,26 @@ hipError_t to_f64(hipStream_t st, const float2* x, ll n, double2* y) {
 hipError_t add_to_f32(hipStream_t st, const double2* x, ll n, float2* y) {
   KernelTimer kt(st, K_POINT, 2.0 * (double)n, 32.0 * (double)n);
   hipLaunchKernelGGL(k_add_to_f32, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t skel_residual(hipStream_t st, int s, int M, int ne, int lpm, const int* sab, const double2* F,
+                         const double2* G, double2* rho, int cnt) {
+  const ll total = (ll)cnt * 2 * s * M;
+  if (total <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 2.0 * (double)total, 48.0 * (double)total);
+  hipLaunchKernelGGL(k_skel_residual, dim3(blocks_for(total)), dim3(NT), 0, st, s, M, ne, lpm, sab, F, G, rho,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t skel_gather(hipStream_t st, int n, int M, int ne, int lpb, const int* slot, const double2* X,
+                       double2* out, int nbox) {
+  const ll total = (ll)nbox * n * M;
+  if (total <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)total);
+  hipLaunchKernelGGL(k_skel_gather, dim3(blocks_for(total)), dim3(NT), 0, st, n, M, ne, lpb, slot, X, out,
+                     total);
   return hipGetLastError();
 }
 
