@@ -256,6 +256,27 @@ hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const 
  * pivot.  Allocates its own workspace. */
 hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
 
+/* Tile shapes of the complex FP64 GEMM behind every call of this library,
+ * process-wide (a performance choice; results do not depend on it: every
+ * candidate tile shape accumulates the products of an output element in the
+ * same order, so the bits of every result are the same).
+ *   mode 0: fixed rules (default).
+ *   mode 1: autotuning: the first GEMM of each distinct shape (sizes,
+ *           operations, strides, batch) times every candidate tile shape on
+ *           that call's own operands, saving the output first and restoring it
+ *           before each trial and at the end, and keeps the fastest for the
+ *           later calls of that shape.  A tuning call synchronises its stream
+ *           and allocates a copy of its output, so run one warm-up pass (e.g.
+ *           a factor and solve) before timing.
+ *   force >= 0 pins tile variant `force` for every call (testing and tuning;
+ *   HPS_EINVAL beyond the variant count); -1 clears it.
+ * The table of tuned shapes lives until the process ends. */
+hps_status hps_gemm_tuning(int mode, int force);
+
+/* Number of GEMM tile variants, shapes tuned so far and the seconds spent
+ * tuning them (host outputs; NULL skips one). */
+hps_status hps_gemm_tuning_info(int* variants, int* shapes_tuned, double* seconds);
+
 /* ---- launch profiler (measurement support) ---- */
 
 typedef struct hps_kernel_stat {

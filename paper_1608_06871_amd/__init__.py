@@ -75,6 +75,8 @@ SIGNATURES = [
     ("hps_boundary_operators", _I, [ctypes.POINTER(Opts), _D, _P, _P, _P]),
     ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
     ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
+    ("hps_gemm_tuning", _I, [_I, _I]),
+    ("hps_gemm_tuning_info", _I, [_P, _P, _P]),
     ("hps_profile_start", _I, []),
     ("hps_profile_stop", _I, [ctypes.POINTER(KernelStat), _I]),
 ]
@@ -350,6 +352,24 @@ def zinv(A, stream=None):
     if rc != HPS_OK:
         raise HpsError(rc, "hps_zinv")
     return inv
+
+
+def gemm_tuning(mode=1, force=-1):
+    """Tile-shape selection of the library's complex GEMM (process-wide):
+    mode 0 fixed rules, 1 autotuning per distinct shape (tune in a warm-up
+    pass); force >= 0 pins one tile variant.  Results do not depend on it."""
+    rc = lib().hps_gemm_tuning(int(mode), int(force))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_gemm_tuning")
+
+
+def gemm_tuning_info():
+    """{variants, shapes_tuned, seconds} of the GEMM tile-shape tuning."""
+    v, n, t = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    rc = lib().hps_gemm_tuning_info(ctypes.byref(v), ctypes.byref(n), ctypes.byref(t))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_gemm_tuning_info")
+    return {"variants": v.value, "shapes_tuned": n.value, "seconds": t.value}
 
 
 def profile_start():

@@ -39,6 +39,11 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
 hipError_t cgemm(hipStream_t st, int opA, int opB, int M, int N, int K, float2 alpha,
                  const float2* A, ll lda, ll sA, const float2* B, ll ldb, ll sB, float2 beta,
                  float2* C, ll ldc, ll sC, int batch);
+// Tile-shape selection of the complex FP64 GEMM (process-wide): mode 0 fixed
+// rules, 1 autotuning per distinct shape; force >= 0 pins one variant.
+void gemm_set_tuning(int mode, int force);
+void gemm_tuning_info(int* shapes, double* seconds);
+int gemm_variant_count();
 
 // Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
 size_t zinv_workspace(int n, int batch);

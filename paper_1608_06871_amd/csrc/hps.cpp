@@ -1380,6 +1380,18 @@ hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const 
   return e == hipSuccess ? HPS_OK : HPS_EDEVICE;
 }
 
+hps_status hps_gemm_tuning(int mode, int force) {
+  if (mode < 0 || mode > 1 || force < -1 || force >= gemm_variant_count()) return HPS_EINVAL;
+  gemm_set_tuning(mode, force);
+  return HPS_OK;
+}
+
+hps_status hps_gemm_tuning_info(int* variants, int* shapes_tuned, double* seconds) {
+  if (variants) *variants = gemm_variant_count();
+  gemm_tuning_info(shapes_tuned, seconds);
+  return HPS_OK;
+}
+
 hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv) {
   if (n < 0 || batch < 0 || batch > 65535) return HPS_EINVAL;
   if (n == 0 || batch == 0) return HPS_OK;

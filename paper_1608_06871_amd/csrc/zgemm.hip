@@ -16,7 +16,11 @@
 // shapes are bounds-checked (zero fill).  The tile shape is chosen per call.
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
+#include <chrono>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -291,11 +295,13 @@ struct TileIO64 {
   }
 };
 
-template <int WM, int WN, bool M3, int TK, int WAVES>
+// DB: two LDS buffers, so that the tile of the next K step is stored while
+// the current one is multiplied (one barrier per step instead of two).
+template <int WM, int WN, bool M3, int TK, int WAVES, bool DB = false>
 __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
-  constexpr int TM = 32 * WM, TN = 32 * WN;
-  __shared__ double Are[TK][TM + PAD], Aim[TK][TM + PAD];
-  __shared__ double Bre[TK][TN + PAD], Bim[TK][TN + PAD];
+  constexpr int TM = 32 * WM, TN = 32 * WN, NB = DB ? 2 : 1;
+  __shared__ double Are[NB][TK][TM + PAD], Aim[NB][TK][TM + PAD];
+  __shared__ double Bre[NB][TK][TN + PAD], Bim[NB][TK][TN + PAD];
 
   const int tilesM = (a.M + TM - 1) / TM;
   const int m0 = (blockIdx.x % tilesM) * TM;
@@ -327,11 +333,19 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   TileIO64<TM, TK>::load(A, a.lda, a.M, a.K, m0, 0, a_rows, a_conj, t, ra);
   TileIO64<TN, TK>::load(B, a.ldb, a.N, a.K, n0, 0, b_rows, b_conj, t, rb);
   const int nk = (a.K + TK - 1) / TK;
+  if constexpr (DB) {
+    TileIO64<TM, TK>::store(Are[0], Aim[0], a_rows, t, ra);
+    TileIO64<TN, TK>::store(Bre[0], Bim[0], b_rows, t, rb);
+    __syncthreads();
+  }
   for (int kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-    TileIO64<TM, TK>::store(Are, Aim, a_rows, t, ra);
-    TileIO64<TN, TK>::store(Bre, Bim, b_rows, t, rb);
-    __syncthreads();
+    const int cur = DB ? (kt & 1) : 0;
+    if constexpr (!DB) {
+      __syncthreads();
+      TileIO64<TM, TK>::store(Are[0], Aim[0], a_rows, t, ra);
+      TileIO64<TN, TK>::store(Bre[0], Bim[0], b_rows, t, rb);
+      __syncthreads();
+    }
     if (kt + 1 < nk) {
       TileIO64<TM, TK>::load(A, a.lda, a.M, a.K, m0, (kt + 1) * TK, a_rows, a_conj, t, ra);
       TileIO64<TN, TK>::load(B, a.ldb, a.N, a.K, n0, (kt + 1) * TK, b_rows, b_conj, t, rb);
@@ -342,13 +356,13 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
       double ar[WM], ai[WM], br[WN], bi[WN];
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
-        ar[i] = Are[kk][wm + 16 * i + lr];
-        ai[i] = Aim[kk][wm + 16 * i + lr];
+        ar[i] = Are[cur][kk][wm + 16 * i + lr];
+        ai[i] = Aim[cur][kk][wm + 16 * i + lr];
       }
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
-        br[j] = Bre[kk][wn + 16 * j + lr];
-        bi[j] = Bim[kk][wn + 16 * j + lr];
+        br[j] = Bre[cur][kk][wn + 16 * j + lr];
+        bi[j] = Bim[cur][kk][wn + 16 * j + lr];
       }
       if constexpr (M3) {
 #pragma unroll
@@ -371,6 +385,15 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
             p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], p3[i][j], 0, 0, 0);
           }
       }
+    }
+    if constexpr (DB) {
+      // the other buffer was last read in step kt - 1, before the previous
+      // barrier
+      if (kt + 1 < nk) {
+        TileIO64<TM, TK>::store(Are[cur ^ 1], Aim[cur ^ 1], a_rows, t, ra);
+        TileIO64<TN, TK>::store(Bre[cur ^ 1], Bim[cur ^ 1], b_rows, t, rb);
+      }
+      __syncthreads();
     }
   }
 
@@ -483,13 +506,13 @@ int choose_splits(int M, int N, int K, int batch) {
   if (s > 16) s = 16;
   return s < 2 ? 1 : (int)s;
 }
-template <int WM, int WN, bool M3, int TK, int WAVES>
+template <int WM, int WN, bool M3, int TK, int WAVES, bool DB = false>
 hipError_t launch(hipStream_t st, const Args& a, int batch) {
   constexpr int TM = 32 * WM, TN = 32 * WN;
   const ll tiles = (ll)((a.M + TM - 1) / TM) * ((a.N + TN - 1) / TN);
   if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((zgemm_kernel<WM, WN, M3, TK, WAVES>), dim3((unsigned)tiles, (unsigned)batch), dim3(NT), 0,
-                     st, a);
+  hipLaunchKernelGGL((zgemm_kernel<WM, WN, M3, TK, WAVES, DB>), dim3((unsigned)tiles, (unsigned)batch), dim3(NT),
+                     0, st, a);
   return hipGetLastError();
 }
 
@@ -510,6 +533,10 @@ const LaunchFn VARIANTS[] = {
     launch<2, 2, true, 8, 2>,    // 10
     launch<2, 1, true, 16, 3>,   // 11
     launch<2, 1, true, 8, 3>,    // 12
+    launch<2, 1, true, 16, 2, true>,   // 13
+    launch<2, 2, true, 16, 2, true>,   // 14
+    launch<2, 1, true, 8, 3, true>,    // 15
+    launch<2, 2, true, 16, 1, true>,   // 16
 };
 constexpr int NVARIANT = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
@@ -530,8 +557,10 @@ void trace_call(const Args& a, int batch) {
   std::fflush(f);
 }
 
+std::atomic<int> g_force{-2};  // -2: not read from the environment yet
+
 int forced_variant() {
-  static int v = -2;
+  int v = g_force.load();
   if (v == -2) {
     const char* e = std::getenv("HPS_ZGEMM_VARIANT");
     v = -1;
@@ -539,11 +568,101 @@ int forced_variant() {
       const int x = std::atoi(e);
       if (x >= 0 && x < NVARIANT) v = x;
     }
+    int expect = -2;
+    g_force.compare_exchange_strong(expect, v);
+    v = g_force.load();
   }
   return v;
 }
 
+// ---- tile-shape autotuning ----
+// Candidates are 3M variants only: they all accumulate the K products of an
+// output element in the same order, so the choice never changes a result.
+constexpr int TUNE_CAND[] = {12, 8, 11, 1, 10};
+constexpr int NCAND = sizeof(TUNE_CAND) / sizeof(TUNE_CAND[0]);
+
+struct TuneKey {
+  int M, N, K, batch, opA, opB, beta, mask;
+  ll lda, ldb, ldc, sA, sB, sC;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(M, N, K, batch, opA, opB, beta, mask, lda, ldb, ldc, sA, sB, sC) <
+           std::tie(o.M, o.N, o.K, o.batch, o.opA, o.opB, o.beta, o.mask, o.lda, o.ldb, o.ldc, o.sA, o.sB, o.sC);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+std::atomic<int> g_tune_mode{0};
+double g_tune_seconds = 0.0;
+
+// Times every candidate on the call's own operands (the output span is saved
+// first and restored before each trial and at the end) and returns the index
+// of the fastest in VARIANTS.  Synchronises the stream.
+hipError_t tune_shape(hipStream_t st, const Args& a, int batch, int* best) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const bool rb = (a.beta.x != 0.0 || a.beta.y != 0.0);
+  const ll span = (ll)(batch - 1) * a.sC + (ll)(a.N - 1) * a.ldc + a.M;
+  const size_t bytes = (size_t)span * sizeof(double2);
+  void* save = nullptr;
+  hipEvent_t ev[2 * NCAND];
+  for (auto& e : ev) e = nullptr;
+  hipError_t err = hipSuccess;
+  float ms[NCAND];
+  for (int i = 0; i < NCAND; ++i) ms[i] = 1e30f;
+  do {
+    if (rb) {
+      if ((err = hipMalloc(&save, bytes)) != hipSuccess) break;
+      if ((err = hipMemcpyAsync(save, a.C, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+    }
+    for (auto& e : ev)
+      if ((err = hipEventCreate(&e)) != hipSuccess) break;
+    if (err != hipSuccess) break;
+    for (int round = 0; round < 3 && err == hipSuccess; ++round) {
+      for (int i = 0; i < NCAND && err == hipSuccess; ++i) {
+        if (rb && (err = hipMemcpyAsync(a.C, save, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+        if ((err = hipEventRecord(ev[2 * i], st)) != hipSuccess) break;
+        if ((err = VARIANTS[TUNE_CAND[i]](st, a, batch)) != hipSuccess) break;
+        err = hipEventRecord(ev[2 * i + 1], st);
+      }
+      if (err != hipSuccess || round == 0) continue;  // round 0 warms up
+      if ((err = hipStreamSynchronize(st)) != hipSuccess) break;
+      for (int i = 0; i < NCAND; ++i) {
+        float x = 0.0f;
+        if ((err = hipEventElapsedTime(&x, ev[2 * i], ev[2 * i + 1])) != hipSuccess) break;
+        if (x < ms[i]) ms[i] = x;
+      }
+    }
+    if (err == hipSuccess && rb) err = hipMemcpyAsync(a.C, save, bytes, hipMemcpyDeviceToDevice, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+  } while (0);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (save) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(save);
+  }
+  int b = 0;
+  for (int i = 1; i < NCAND; ++i)
+    if (ms[i] < ms[b]) b = i;
+  *best = TUNE_CAND[b];
+  g_tune_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return err;
+}
+
 }  // namespace
+
+void gemm_set_tuning(int mode, int force) {
+  g_tune_mode.store(mode);
+  forced_variant();
+  g_force.store(force >= 0 && force < NVARIANT ? force : -1);
+}
+
+void gemm_tuning_info(int* shapes, double* seconds) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (shapes) *shapes = (int)g_tuned.size();
+  if (seconds) *seconds = g_tune_seconds;
+}
+
+int gemm_variant_count() { return NVARIANT; }
 
 hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
                  const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB, double2 beta,
@@ -607,11 +726,26 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
                        N, alpha, beta, C, ldc, sC, rpos, srp, plo, phi, batch);
     return hipGetLastError();
   }
-  // Tuned on MI355X over the solver's shapes (rank-32 updates of the
-  // inverses, leaf sweeps, merge products, top solve): all 3M.
-  if (a.K <= 64) return launch<2, 1, true, 8, 3>(st, a, batch);
-  if (M >= 1024 && N >= 1024 && a.K >= 512) return launch<2, 2, true, 16, 2>(st, a, batch);
-  return launch<2, 1, true, 16, 2>(st, a, batch);
+  if (g_tune_mode.load() == 1) {
+    const TuneKey key{M, N, a.K, batch, opA, opB, rb ? 1 : 0, rpos ? 1 : 0, lda, ldb, ldc, sA, sB, sC};
+    int v = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tuned.find(key);
+      if (it != g_tuned.end()) v = it->second;
+    }
+    if (v < 0) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      HPS_HIP_TRY(tune_shape(st, a, batch, &v));
+      g_tuned[key] = v;
+    }
+    return VARIANTS[v](st, a, batch);
+  }
+  // Fixed rules, from timings on MI355X over the solver's shapes: 64 x 32
+  // tiles with K step 8 and three waves per SIMD everywhere except long-K
+  // products with few columns (top solves), which prefer K step 16.
+  if (N <= 256 && a.K >= 1024) return launch<2, 1, true, 16, 2>(st, a, batch);
+  return launch<2, 1, true, 8, 3>(st, a, batch);
 }
 
 hipError_t cgemm(hipStream_t st, int opA, int opB, int M, int N, int K, float2 alpha, const float2* A, ll lda,

@@ -160,3 +160,69 @@ def test_zinv_row_scaled_keeps_accuracy(n):
     # compare column by column relative to each column's scale
     err = np.max(np.abs(inv - ref), axis=0) / np.max(np.abs(ref), axis=0)
     assert np.max(err) < 1e-13 * cond
+
+
+# 3M tile variants (tile shape, K step, waves per SIMD, one or two LDS buffers)
+VARIANTS_3M = [12, 8, 11, 1, 10, 4, 9, 13, 14, 15, 16]
+
+
+def test_gemm_tile_variants_agree_bitwise():
+    """Every 3M tile variant accumulates the products of an output element in
+    the same order, so all of them, and the autotuner's choice, give the same
+    bits (the autotuner relies on this)."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    rng = np.random.default_rng(11)
+    M, N, K, batch = 130, 70, 90, 2
+    A = _colmajor(torch, _rand(rng, (batch, M, K)))
+    B = _colmajor(torch, _rand(rng, (batch, K, N)))
+    C0 = _colmajor(torch, _rand(rng, (batch, M, N)))
+    beta = 0.5 + 0.25j
+    outs = []
+    try:
+        for v in VARIANTS_3M:
+            hps.gemm_tuning(0, v)
+            C = C0.clone()
+            hps.zgemm(A, B, C, alpha=1.0 - 2.0j, beta=beta)
+            outs.append(C.cpu())
+        hps.gemm_tuning(1, -1)
+        n0 = hps.gemm_tuning_info()["shapes_tuned"]
+        C = C0.clone()
+        hps.zgemm(A, B, C, alpha=1.0 - 2.0j, beta=beta)
+        tuned = C.cpu()
+        assert hps.gemm_tuning_info()["shapes_tuned"] == n0 + 1
+        C = C0.clone()
+        hps.zgemm(A, B, C, alpha=1.0 - 2.0j, beta=beta)  # the tuned shape again
+        again = C.cpu()
+    finally:
+        hps.gemm_tuning(0, -1)
+    for v, o in zip(VARIANTS_3M, outs):
+        assert torch.equal(o, outs[0]), f"variant {v}"
+    assert torch.equal(tuned, outs[0]) and torch.equal(again, outs[0])
+    ref = np.einsum("bmk,bkn->bmn", _back(A), _back(B)) * (1.0 - 2.0j) + beta * _back(C0)
+    assert np.max(np.abs(_back(outs[0]) - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_autotuned_solver_gives_identical_results():
+    """A factorisation and solve with GEMM autotuning on (every shape tuned on
+    its first call, the output saved and restored around the trials) gives the
+    same far field, bit for bit, as with the fixed tile rules."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    import synth
+    L, k, M, P = 4, 10.0, 16, 32
+    s = hps.Solver(nleaf=L, p=16, keep_derivs=False)
+    q = torch.from_numpy(synth.gaussian_bumps(s.node_coords(), 5, 1, amp=(0.1, 0.3), width=0.15)).cuda()
+    dirs, th = synth.equispaced_angles(M), synth.equispaced_angles(P)
+    s.factor(q, k)
+    s.solve(dirs)
+    ref = s.far_field(th, 2.0).cpu()
+    try:
+        hps.gemm_tuning(1, -1)
+        s.factor(q, k)
+        s.solve(dirs)
+        tuned = s.far_field(th, 2.0).cpu()
+    finally:
+        hps.gemm_tuning(0, -1)
+    assert hps.gemm_tuning_info()["shapes_tuned"] > 0
+    assert torch.equal(tuned, ref)
