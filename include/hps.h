@@ -280,7 +280,7 @@ hps_status hps_gemm_tuning_info(int* variants, int* shapes_tuned, double* second
 /* ---- launch profiler (measurement support) ---- */
 
 typedef struct hps_kernel_stat {
-  char name[32];     /* kernel class: zgemm, gj_panel, tp_select, tp_block,
+  char name[32];     /* kernel class: zgemm, cgemm, gj_panel, tp_select, tp_exchange,
                         gj_permute, gather_scatter, leaf_assemble, pointwise */
   int64_t launches;  /* launches timed */
   double total_ms;   /* sum of per-launch durations (HIP events on the launch stream) */

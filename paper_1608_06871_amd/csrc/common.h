@@ -62,7 +62,7 @@ enum KernelKind {
   K_CGEMM,      // FP32 complex GEMM (mixed precision)
   K_GJ_PANEL,   // Gauss-Jordan panel elimination (register / LDS / global panel)
   K_TP_SELECT,  // tournament pivot selection (leaves and reductions)
-  K_TP_BLOCK,   // pivot-block inverse of the tournament path
+  K_TP_EXCH,   // panel exchange of the tournament path
   K_GJ_PERM,
   K_MOVE,
   K_LEAF,

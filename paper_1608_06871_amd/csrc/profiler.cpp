@@ -25,7 +25,7 @@ std::vector<hipEvent_t> g_pool;
 size_t g_used = 0;
 
 const char* const KIND_NAMES[KIND_COUNT] = {"zgemm", "cgemm", "gj_panel",       "tp_select",
-                                             "tp_block",   "gj_permute",     "gather_scatter",
+                                             "tp_exchange", "gj_permute",     "gather_scatter",
                                              "leaf_assemble", "pointwise"};
 
 hipEvent_t take() {

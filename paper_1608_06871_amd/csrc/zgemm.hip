@@ -537,6 +537,8 @@ const LaunchFn VARIANTS[] = {
     launch<2, 2, true, 16, 2, true>,   // 14
     launch<2, 1, true, 8, 3, true>,    // 15
     launch<2, 2, true, 16, 1, true>,   // 16
+    launch<1, 2, true, 8, 3>,          // 17
+    launch<1, 1, true, 8, 4>,          // 18
 };
 constexpr int NVARIANT = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
@@ -578,7 +580,7 @@ int forced_variant() {
 // ---- tile-shape autotuning ----
 // Candidates are 3M variants only: they all accumulate the K products of an
 // output element in the same order, so the choice never changes a result.
-constexpr int TUNE_CAND[] = {12, 8, 11, 1, 10};
+constexpr int TUNE_CAND[] = {12, 8, 11, 1, 10, 9, 17, 18};
 constexpr int NCAND = sizeof(TUNE_CAND) / sizeof(TUNE_CAND[0]);
 
 struct TuneKey {

@@ -28,8 +28,8 @@
 //   - n > 512: tournament pivoting (communication-avoiding LU, Grigori,
 //     Demmel and Xiang 2011): chunks of rows pick candidate pivot rows by
 //     partial pivoting, candidate sets are reduced the same way until the
-//     panel's pivot rows remain, whose block is inverted (tp_block); the
-//     panel columns are then exchanged with one GEMM.
+//     panel's pivot rows remain, whose block the last reduction also
+//     inverts; one more kernel exchanges the panel columns.
 #include <cfloat>
 
 #include "common.h"
@@ -414,15 +414,80 @@ __global__ __launch_bounds__(TR) void tp_leaf(const double2* Aall, ll lda, ll sA
   if (t < b) out[t] = selid[t];
 }
 
+// Inverse IB (b x b, column-major) of the block of the selected pivot rows
+// sel[0 .. b) in the panel columns, by the whole workgroup (NB threads, a
+// multiple of 32): Gauss-Jordan elimination in the selection order (the
+// tournament ordered the rows by partial pivoting, so no interchanges are
+// needed), in LDS (mb, padded with the identity to BMAX x BMAX).  Thread t
+// owns row t % 32 in the columns t / 32 + (NB / 32) u.  Also records sig /
+// pos of the panel and flags a zero pivot.
+template <int NB>
+__device__ __forceinline__ void block_inverse(const double2* A, ll lda, int c0, int b, const int* sel,
+                                              double2 (*mb)[BMAX + 1], double2* IB, int* sig, int* pos,
+                                              int* info) {
+  constexpr int CS = NB / BMAX, PER = BMAX / CS;  // column stride, entries per thread
+  const int t = threadIdx.x, r = t % BMAX, j0 = t / BMAX;
+  const int pr = (r < b) ? sel[r] : -1;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int col = j0 + CS * u;
+    mb[r][col] = (r < b && col < b) ? (pr >= 0 ? A[(ll)pr + (ll)(c0 + col) * lda] : make_double2(0.0, 0.0))
+                                    : make_double2(r == col ? 1.0 : 0.0, 0.0);
+  }
+  bool singular = false;
+  for (int c = 0; c < b; ++c) {
+    __syncthreads();
+    const double2 piv = mb[c][c];
+    const double2 f = mb[r][c];
+    double2 pc[PER], own[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      pc[u] = mb[c][j0 + CS * u];
+      own[u] = mb[r][j0 + CS * u];
+    }
+    __syncthreads();
+    const bool zero = (piv.x == 0.0 && piv.y == 0.0);
+    singular |= zero;
+    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(piv);
+    const double2 fi = cmul(f, inv);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int col = j0 + CS * u;
+      double2 v;
+      if (r == c)
+        v = (col == c) ? inv : cmul(pc[u], inv);
+      else
+        v = (col == c) ? make_double2(-fi.x, -fi.y) : cfms(own[u], fi, pc[u]);
+      mb[r][col] = v;
+    }
+  }
+  __syncthreads();
+  if (r < b) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int col = j0 + CS * u;
+      if (col < b) IB[r + col * b] = mb[r][col];
+    }
+    if (j0 == 0 && pr >= 0) {
+      sig[c0 + r] = pr;
+      pos[pr] = c0 + r;
+    }
+  }
+  if (singular && t == 0) *info = 1;
+}
+
 // Reduction: workgroup g merges candidate sets [TF g, TF g + TF) of Gin
 // (entries -1 mark missing candidates); the sets are taken in order, so ties
-// go to the earlier set.
-__global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll lda, ll sA, int c0, int b,
-                                                      int Gin, const int* cin_all, int Gout, int* cout_all) {
+// go to the earlier set.  The last level (one group) also inverts the pivot
+// block of the panel (block_inverse).
+__global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll lda, ll sA, int n, int c0, int b,
+                                                      int Gin, const int* cin_all, int Gout, int* cout_all,
+                                                      double2* IB_all, int* sig_all, int* pos_all, int* info) {
   __shared__ double2 cand[2][TRW][BMAX];
   __shared__ u64 ckey[2][TRW];
   __shared__ double2 cinv[2][TRW];
   __shared__ int selid[BMAX];
+  __shared__ double2 mb[BMAX][BMAX + 1];
   const ll bi = blockIdx.y;
   const int g = blockIdx.x, t = threadIdx.x;
   // slot j of the group: entry j % b of candidate set TF g + j / b (-1: none)
@@ -433,76 +498,64 @@ __global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll ld
 #pragma unroll
   for (int i = 0; i < 4; ++i) id[i] = (base + 16 * i < nslot) ? cin[base + 16 * i] : -1;
   select_rows<TRW>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid);
-  int* out = cout_all + (bi * Gout + g) * (ll)b;
-  if (t < b) out[t] = selid[t];
+  if (Gout > 1) {
+    int* out = cout_all + (bi * Gout + g) * (ll)b;
+    if (t < b) out[t] = selid[t];
+    return;
+  }
+  block_inverse<64 * TRW>(Aall + bi * sA, lda, c0, b, selid, mb, IB_all + bi * (ll)BMAX * BMAX, sig_all + bi * n,
+                          pos_all + bi * n, info + bi);
 }
 
-// Inverse IB of the b x b block of the selected pivot rows (in selection
-// order) and the panel columns, by Gauss-Jordan elimination without
-// interchanges: the tournament ordered the rows by partial pivoting, so
-// elimination in that order makes the same pivot choices.  BMAX x BMAX
-// threads, one element each (the block padded with the identity).  Also
-// records sig / pos for the panel.
-__global__ __launch_bounds__(BMAX * BMAX) void tp_block(const double2* Aall, ll lda, ll sA, int n, int c0,
-                                                        int b, const int* sel_all, double2* IB_all,
-                                                        int* sig_all, int* pos_all, int* info) {
-  __shared__ double2 m[BMAX * BMAX];  // column-major: (r, j) at r + j * BMAX
-  const ll bi = blockIdx.x;
+// Panel columns after the block exchange (one launch): rows picked as pivots
+// of this panel take their row of IB, every other row r takes
+// -A[r, panel] IB.  A workgroup stages its 64 rows of the panel in LDS (the
+// barrier also orders every read before the first write), then four lanes
+// per row each compute every fourth column.
+__global__ __launch_bounds__(NT) void tp_exchange(double2* Aall, ll lda, ll sA, int n, int c0, int b,
+                                                  const double2* IB_all, const int* pos_all) {
+  constexpr int RW = NT / 4;  // rows per workgroup
+  __shared__ double2 ib[BMAX][BMAX + 1];
+  __shared__ double2 ar[RW][BMAX + 1];
+  const ll bi = blockIdx.y;
   const int t = threadIdx.x;
-  const int r = t % BMAX, j = t / BMAX;
-  const double2* A = Aall + bi * sA;
-  const int* sel = sel_all + bi * b;
-  double2* IB = IB_all + bi * (ll)BMAX * BMAX;
-  const int pr = (r < b) ? sel[r] : -1;
-  const bool act = (r < b && j < b);
-  double2 v = act ? (pr >= 0 ? A[(ll)pr + (ll)(c0 + j) * lda] : make_double2(0.0, 0.0))
-                  : make_double2((r == j) ? 1.0 : 0.0, 0.0);
-  bool singular = false;
-  for (int c = 0; c < b; ++c) {
-    m[t] = v;
-    __syncthreads();
-    const double2 piv = m[c + c * BMAX], f = m[r + c * BMAX], pc = m[c + j * BMAX];
-    __syncthreads();
-    const bool zero = (piv.x == 0.0 && piv.y == 0.0);
-    singular |= zero;
-    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(piv);
-    if (r == c) {
-      v = (j == c) ? inv : cmul(pc, inv);
-    } else if (j == c) {
-      const double2 nf = cmul(f, inv);
-      v = make_double2(-nf.x, -nf.y);
-    } else {
-      const double2 d = cmul(f, cmul(pc, inv));
-      v.x -= d.x;
-      v.y -= d.y;
+  const int r0 = blockIdx.x * RW;
+  const double2* IB = IB_all + bi * (ll)BMAX * BMAX;
+  double2* A = Aall + bi * sA;
+  for (int e = t; e < BMAX * BMAX; e += NT) {
+    const int k = e % BMAX, j = e / BMAX;
+    ib[k][j] = (k < b && j < b) ? IB[k + j * b] : make_double2(0.0, 0.0);
+  }
+  for (int e = t; e < RW * BMAX; e += NT) {
+    const int rl = e % RW, k = e / RW, r = r0 + rl;
+    ar[rl][k] = (r < n && k < b) ? A[(ll)r + (ll)(c0 + k) * lda] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int q = t & 3, rl = t >> 2, r = r0 + rl;
+  if (r >= n) return;
+  const int pr = pos_all[bi * n + r];
+  if (pr >= c0 && pr < c0 + b) {
+    for (int j = q; j < b; j += 4) A[(ll)r + (ll)(c0 + j) * lda] = ib[pr - c0][j];
+    return;
+  }
+  double2 acc[BMAX / 4];
+#pragma unroll
+  for (int u = 0; u < BMAX / 4; ++u) acc[u] = make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (int k = 0; k < b; ++k) {
+    const double2 x = ar[rl][k];
+#pragma unroll
+    for (int u = 0; u < BMAX / 4; ++u) {
+      const double2 w = ib[k][q + 4 * u];
+      acc[u].x = fma(x.x, w.x, fma(-x.y, w.y, acc[u].x));
+      acc[u].y = fma(x.x, w.y, fma(x.y, w.x, acc[u].y));
     }
   }
-  if (act) IB[r + j * b] = v;
-  if (j == 0 && r < b && pr >= 0) {
-    sig_all[bi * n + c0 + r] = pr;
-    pos_all[bi * n + pr] = c0 + r;
+#pragma unroll
+  for (int u = 0; u < BMAX / 4; ++u) {
+    const int j = q + 4 * u;
+    if (j < b) A[(ll)r + (ll)(c0 + j) * lda] = make_double2(-acc[u].x, -acc[u].y);
   }
-  if (t == 0 && singular) info[bi] = 1;
-}
-
-// Panel columns after the block exchange: IB on the pivot rows, -A_Q IB
-// (Et = A[:, panel] IB) elsewhere.
-__global__ __launch_bounds__(NT) void tp_fix(double2* Aall, ll lda, ll sA, int n, int c0, int b,
-                                             const double2* IB_all, const double2* Et_all,
-                                             const int* pos_all) {
-  const ll bi = blockIdx.y;
-  const ll idx = (ll)blockIdx.x * NT + threadIdx.x;
-  if (idx >= (ll)n * b) return;
-  const int r = (int)(idx % n), c = (int)(idx / n);
-  const int pr = pos_all[bi * n + r];
-  double2 v;
-  if (pr >= c0 && pr < c0 + b) {
-    v = IB_all[bi * (ll)BMAX * BMAX + (pr - c0) + c * b];
-  } else {
-    const double2 e = Et_all[bi * (ll)n * BMAX + idx];
-    v = make_double2(-e.x, -e.y);
-  }
-  Aall[bi * sA + (ll)r + (ll)(c0 + c) * lda] = v;
 }
 
 size_t cand_ints(int n, int batch) { return (size_t)batch * ((n + TR - 1) / TR) * BMAX; }
@@ -536,7 +589,6 @@ struct Inv {
   int* pos;
   double2* T;
   ll sT;
-  double2* Et;
   double2* IB;
   int* candA;
   int* candB;
@@ -574,33 +626,24 @@ hipError_t tournament_panel(const Inv& v, int c0, int bw) {
   int* cin = v.candA;
   int* cout = v.candB;
   int Gin = G;
-  while (Gin > 1) {
+  // reduction levels; the last one (a single group) also inverts the block
+  do {
     const int Gout = (Gin + TF - 1) / TF;
     {
       KernelTimer kt(v.st, K_TP_SELECT, 8.0 * Gin * (double)bw * bw * bw * batch,
                      16.0 * Gin * (double)bw * bw * batch);
-      hipLaunchKernelGGL(tp_reduce, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, c0, bw,
-                         Gin, cin, Gout, cout);
+      hipLaunchKernelGGL(tp_reduce, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, n, c0, bw,
+                         Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
     }
     HPS_HIP_TRY(hipGetLastError());
     int* tmp = cin;
     cin = cout;
     cout = tmp;
     Gin = Gout;
-  }
-  {
-    KernelTimer kt(v.st, K_TP_BLOCK, 8.0 * bw * (double)bw * bw * batch, 32.0 * bw * (double)bw * batch);
-    hipLaunchKernelGGL(tp_block, dim3(batch), dim3(BMAX * BMAX), 0, v.st, v.work, v.lda, v.sA, n, c0, bw, cin,
-                       v.IB, v.sig, v.pos, v.info);
-  }
-  HPS_HIP_TRY(hipGetLastError());
-  HPS_HIP_TRY(zgemm(v.st, OP_N, OP_N, n, bw, bw, make_double2(1.0, 0.0), v.work + (ll)c0 * v.lda, v.lda, v.sA,
-                    v.IB, bw, (ll)BMAX * BMAX, make_double2(0.0, 0.0), v.Et, n, (ll)n * BMAX, batch));
-  {
-    KernelTimer kt(v.st, K_MOVE, 0.0, 48.0 * n * (double)bw * batch);
-    hipLaunchKernelGGL(tp_fix, dim3((unsigned)(((ll)n * bw + NT - 1) / NT), batch), dim3(NT), 0, v.st, v.work,
-                       v.lda, v.sA, n, c0, bw, v.IB, v.Et, v.pos);
-  }
+  } while (Gin > 1);
+  KernelTimer kt(v.st, K_TP_EXCH, 8.0 * n * (double)bw * bw * batch, 48.0 * n * (double)bw * batch);
+  hipLaunchKernelGGL(tp_exchange, dim3((unsigned)((n + NT / 4 - 1) / (NT / 4)), batch), dim3(NT), 0, v.st, v.work,
+                     v.lda, v.sA, n, c0, bw, v.IB, v.pos);
   return hipGetLastError();
 }
 
@@ -639,7 +682,6 @@ size_t zinv_workspace(int n, int batch) {
   size_t bytes = align256((size_t)batch * n * sizeof(int) * 2);   // sig + pos
   bytes += align256((size_t)batch * t_elems(n) * sizeof(double2));  // pivot rows T
   if (n > NS_MAX_N) {
-    bytes += align256((size_t)batch * n * BMAX * sizeof(double2));    // Et
     bytes += align256((size_t)batch * BMAX * BMAX * sizeof(double2));  // IB
     bytes += 2 * align256(cand_ints(n, batch) * sizeof(int));          // candidates
   }
@@ -666,8 +708,6 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
   v.sT = (ll)t_elems(n);
   p += align256((size_t)batch * t_elems(n) * sizeof(double2));
   if (n > NS_MAX_N) {
-    v.Et = (double2*)p;
-    p += align256((size_t)batch * n * BMAX * sizeof(double2));
     v.IB = (double2*)p;
     p += align256((size_t)batch * BMAX * BMAX * sizeof(double2));
     v.candA = (int*)p;

@@ -115,6 +115,23 @@ def test_zinv_reports_singular():
     assert e.value.code == hps.HPS_ESINGULAR
 
 
+def test_zinv_large_multilevel_tournament():
+    """n = 4200 needs more candidate sets than one reduction merges (the
+    multi-level tournament path): inv A = I to rounding, checked with the
+    library's own GEMM."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    n = 4200
+    rng = np.random.default_rng(n)
+    A = _rand(rng, (1, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    Ag = _colmajor(torch, A)
+    inv = hps.zinv(Ag.clone())
+    prod = hps.zgemm(inv, Ag)
+    err = np.max(np.abs(_back(prod)[0] - np.eye(n)))
+    print(f"zinv n={n}: max |inv A - I| = {err:.2e}", flush=True)
+    assert err < 1e-11
+
+
 @pytest.mark.parametrize("n", [64, 600])
 def test_zinv_equal_magnitudes(n):
     """Every entry of a Fourier matrix has the same magnitude, so every pivot
@@ -163,7 +180,7 @@ def test_zinv_row_scaled_keeps_accuracy(n):
 
 
 # 3M tile variants (tile shape, K step, waves per SIMD, one or two LDS buffers)
-VARIANTS_3M = [12, 8, 11, 1, 10, 4, 9, 13, 14, 15, 16]
+VARIANTS_3M = [12, 8, 11, 1, 10, 4, 9, 13, 14, 15, 16, 17, 18]
 
 
 def test_gemm_tile_variants_agree_bitwise():
