@@ -857,14 +857,15 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
   const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size(), P = c->P;
   const int nl = g.nleaf * P;
   const ll sF = (ll)nb * M, sbb = (ll)nb * nb;
-  c->sB.ensure(zb((size_t)nl * g.mi * M));
+  c->sB.ensure(zb((size_t)nl * g.ne * g.mi));
   c->sST2.ensure(zb((size_t)2 * P * nb * M));
   c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 3, 0);
-  CK(body_load(st, dq, c->du0.z(), c->dPk.d() + P, g.mi, M, nl, g.nleaf, c->sB.z()));
+  // leaf outgoing data of the body load k^2 dq u0: (H diag(k^2 dq)) u0
+  CK(scale_leaf_cols(st, dq, c->dH.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, c->sB.z()));
   double2* Hc = c->dF0.z();
   double2* Ho = c->dF1.z();
-  CK(zgemm(st, OP_N, OP_N, g.ne, M, g.mi, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, c->sB.z(), g.mi,
+  CK(zgemm(st, OP_N, OP_N, g.ne, M, g.mi, ONE, c->sB.z(), g.ne, (ll)g.ne * g.mi, c->du0.z(), g.mi,
            (ll)g.mi * M, ZERO, Hc, g.ne, (ll)g.ne * M, nl));
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
@@ -903,7 +904,7 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
   const int M = c->ndir, nb = c->nb, nt = (int)c->theta.size(), P = c->P;
   const int nl = g.nleaf * P;
   const ll sF = (ll)nb * M, sbb = (ll)nb * nb;
-  c->sB.ensure(zb((size_t)nl * g.mi * M));
+  c->sB.ensure(zb((size_t)nl * g.ne * g.mi));
   c->sST2.ensure(zb((size_t)2 * P * nb * M));
   c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 4, 0);
@@ -926,9 +927,11 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
     scatter_children(c, l, Hc, c->dF3.z(), Ho, M);
     std::swap(Hc, Ho);
   }
-  CK(zgemm(st, OP_C, OP_N, g.mi, M, g.ne, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, Hc, g.ne,
-           (ll)g.ne * M, ZERO, c->sB.z(), g.mi, (ll)g.mi * M, nl));
-  CK(grad_reduce(st, c->du0.z(), c->sB.z(), c->dPk.d() + P, g.mi, M, nl, g.nleaf, grad));
+  // grad = k^2 Re sum_dir conj(u0) (H^H g), summed over the directions first:
+  // Q^T = g u0^H per leaf (ne x mi), then grad_n = k^2 Re sum_e conj(H_en) Q^T_en
+  CK(zgemm(st, OP_N, OP_C, g.ne, g.mi, M, ONE, Hc, g.ne, (ll)g.ne * M, c->du0.z(), g.mi, (ll)g.mi * M, ZERO,
+           c->sB.z(), g.ne, (ll)g.ne * g.mi, nl));
+  CK(grad_leaf(st, c->dH.z(), c->sB.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, grad));
   mark(c, 4, 1);
 }
 

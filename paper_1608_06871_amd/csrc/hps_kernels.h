@@ -49,10 +49,13 @@ hipError_t boundary_st(hipStream_t st, const double2* f, const double2* g, const
                        int nb, int ncol, const double* etav, double2* ST, int nprob);
 hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol, const double* etav,
                            double2* fb, double2* gb, int nprob);
-hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, const double* k2v, int mi,
-                     int ndir, ll nleaf, ll lpp, double2* b);
-hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, const double* k2v, int mi,
-                       int ndir, ll nleaf, ll lpp, double* grad);
+// Hs = H diag(k^2 dq) per leaf (H: ne x mi): the Frechet body load folded into
+// the outgoing-impedance maps.
+hipError_t scale_leaf_cols(hipStream_t st, const double* dq, const double2* H, const double* k2v, int ne, int mi,
+                           ll nleaf, ll lpp, double2* Hs);
+// grad[z mi + n] = k^2 Re sum_e conj(H[e][n]) QT[e][n] per leaf.
+hipError_t grad_leaf(hipStream_t st, const double2* H, const double2* QT, const double* k2v, int ne, int mi,
+                     ll nleaf, ll lpp, double* grad);
 hipError_t export_field(hipStream_t st, const double2* u0, int mi, int ndir, ll nleaf,
                         double2* out);
 hipError_t real_to_complex(hipStream_t st, const double* x, ll n, double2* y);

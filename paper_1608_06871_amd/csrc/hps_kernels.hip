@@ -142,31 +142,36 @@ __global__ void k_boundary_st_adj(const double2* STb, int nb, int ncol, const do
 }
 
 // b[z][n + m mi] = k^2 dq[z mi + n] u0[z][n + m mi]  (k^2 of leaf z's problem)
-__global__ void k_body_load(const double* dq, const double2* u0, const double* k2v, int mi, int ndir,
-                            ll nleaf, ll lpp, double2* b) {
-  const ll per = (ll)mi * ndir;
+// Body-load operator of the Frechet derivative, folded into the leaf maps:
+// Hs[z][e + n ne] = k^2 dq[z mi + n] H[z][e + n ne] (H: ne x mi per leaf), so
+// that the outgoing impedance of the load k^2 dq u0 is Hs u0.
+__global__ void k_scale_leaf_cols(const double* dq, const double2* H, const double* k2v, int ne, int mi,
+                                  ll nleaf, ll lpp, double2* Hs) {
+  const ll per = (ll)ne * mi;
   const ll total = per * nleaf;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
     const ll z = idx / per;
-    const int n = (int)(idx % per) % mi;
+    const int n = (int)(idx % per) / ne;
     const double s = k2v[z / lpp] * dq[z * mi + n];
-    const double2 u = u0[idx];
-    b[idx] = make_double2(s * u.x, s * u.y);
+    const double2 h = H[idx];
+    Hs[idx] = make_double2(s * h.x, s * h.y);
   }
 }
 
-// grad[z mi + n] = Re sum_m k^2 conj(u0) bbar   (fixed summation order)
-__global__ void k_grad_reduce(const double2* u0, const double2* bb, const double* k2v, int mi, int ndir,
-                              ll nleaf, ll lpp, double* grad) {
+// Adjoint reduction over the directions, from Q^T = g u0^H (ne x mi per leaf,
+// g the leaf-edge adjoint data): grad[z mi + n] = k^2 Re sum_e conj(H[e][n])
+// Q^T[e][n], which equals Re sum_m k^2 conj(u0[n][m]) (H^H g)[n][m].
+__global__ void k_grad_leaf(const double2* H, const double2* QT, const double* k2v, int ne, int mi, ll nleaf,
+                            ll lpp, double* grad) {
   const ll total = (ll)mi * nleaf;
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
     const ll z = idx / mi;
     const int n = (int)(idx % mi);
-    const ll base = z * (ll)mi * ndir + n;
+    const ll base = z * (ll)ne * mi + (ll)n * ne;
     double acc = 0.0;
-    for (int m = 0; m < ndir; ++m) {
-      const double2 u = u0[base + (ll)m * mi], v = bb[base + (ll)m * mi];
-      acc += u.x * v.x + u.y * v.y;
+    for (int e = 0; e < ne; ++e) {
+      const double2 h = H[base + e], q = QT[base + e];
+      acc += h.x * q.x + h.y * q.y;
     }
     grad[idx] = k2v[z / lpp] * acc;
   }
@@ -456,19 +461,20 @@ hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol,
   return hipGetLastError();
 }
 
-hipError_t body_load(hipStream_t st, const double* dq, const double2* u0, const double* k2v, int mi,
-                     int ndir, ll nleaf, ll lpp, double2* b) {
-  KernelTimer kt(st, K_POINT, 6.0 * mi * (double)ndir * nleaf, (8.0 + 32.0 * ndir) * mi * (double)nleaf);
-  hipLaunchKernelGGL(k_body_load, dim3(blocks_for((ll)mi * ndir * nleaf)), dim3(NT), 0, st, dq, u0,
-                     k2v, mi, ndir, nleaf, lpp, b);
+hipError_t scale_leaf_cols(hipStream_t st, const double* dq, const double2* H, const double* k2v, int ne, int mi,
+                           ll nleaf, ll lpp, double2* Hs) {
+  const ll total = (ll)ne * mi * nleaf;
+  KernelTimer kt(st, K_POINT, 2.0 * (double)total, 40.0 * (double)total);
+  hipLaunchKernelGGL(k_scale_leaf_cols, dim3(blocks_for(total)), dim3(NT), 0, st, dq, H, k2v, ne, mi, nleaf, lpp,
+                     Hs);
   return hipGetLastError();
 }
 
-hipError_t grad_reduce(hipStream_t st, const double2* u0, const double2* bb, const double* k2v, int mi,
-                       int ndir, ll nleaf, ll lpp, double* grad) {
-  KernelTimer kt(st, K_POINT, 4.0 * mi * (double)ndir * nleaf, (8.0 + 32.0 * ndir) * mi * (double)nleaf);
-  hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for((ll)mi * nleaf)), dim3(NT), 0, st, u0, bb, k2v,
-                     mi, ndir, nleaf, lpp, grad);
+hipError_t grad_leaf(hipStream_t st, const double2* H, const double2* QT, const double* k2v, int ne, int mi,
+                     ll nleaf, ll lpp, double* grad) {
+  KernelTimer kt(st, K_POINT, 4.0 * ne * (double)mi * nleaf, (32.0 * ne + 8.0) * mi * (double)nleaf);
+  hipLaunchKernelGGL(k_grad_leaf, dim3(blocks_for((ll)mi * nleaf)), dim3(NT), 0, st, H, QT, k2v, ne, mi, nleaf,
+                     lpp, grad);
   return hipGetLastError();
 }
 
