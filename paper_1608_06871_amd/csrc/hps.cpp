@@ -128,6 +128,9 @@ struct hps_ctx {
   bool factored = false;
   int singular = 0;
   DBuf dY, dH, dRroot, dZinv;
+  // conjugate transposes of the top operators for the adjoint (read as plain
+  // column-major operands, which the matrix cores stream faster)
+  DBuf dRrootH, dZinvH, dA2H;
   std::vector<DBuf> dD, dU;
   DBuf sA, sInv, sZws, sR0, sR1, sBlk, sW, sWinv, sQ, sVin, sV, sTmp, sInfo;
 
@@ -302,6 +305,10 @@ void set_wavenumbers(hps_ctx* c, const double* k) {
     c->kv[b] = k[b];
     c->etav[b] = es * k[b];
   }
+  if (changed && c->o.keep_derivs) {
+    c->dA2H.ensure(zb(sA * P));
+    CK(conj_transpose(c->st, nb, c->dA2.z(), nb, (ll)sA, c->dA2H.z(), nb, (ll)sA, P));
+  }
   std::vector<double> pk(3 * (size_t)P);
   for (int b = 0; b < P; ++b) {
     pk[b] = c->kv[b];
@@ -360,6 +367,10 @@ void plan_factor_buffers(hps_ctx* c) {
   if (c->o.keep_derivs) c->dH.ensure(zb(nl * ne * mi));
   c->dRroot.ensure(zb(P * nb * nb));
   c->dZinv.ensure(zb(P * nb * nb));
+  if (c->o.keep_derivs) {
+    c->dRrootH.ensure(zb(P * nb * nb));
+    c->dZinvH.ensure(zb(P * nb * nb));
+  }
   c->dD.resize(g.nlev + 1);
   c->dU.resize(g.nlev + 1);
   const bool needU = c->o.keep_derivs || c->mixed;
@@ -411,11 +422,17 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   CK(gather2d(st, mi, ne, inv_edge, n, nn, nullptr, nullptr, c->dY.z(), mi, (ll)mi * ne, 1.0, nl));
   double2* Rc = c->sR0.z();
   const ll smo = (ll)ne * n;  // one outgoing map per problem, shared by its leaves
-  CK(zgemm_div(st, OP_N, OP_N, ne, ne, n, ONE, c->dMout.z(), ne, smo, lpp, inv_edge, n, nn, 1, ZERO, Rc,
-               ne, (ll)ne * ne, nl));
-  if (c->o.keep_derivs)
-    CK(zgemm_div(st, OP_N, OP_N, ne, mi, n, ONE, c->dMout.z(), ne, smo, lpp, c->sInv.z(), n, nn, 1, ZERO,
-                 c->dH.z(), ne, (ll)ne * mi, nl));
+  // a single problem broadcasts its map (stride 0); a batch of problems
+  // indexes it by leaf / leaves-per-problem
+  auto mout_gemm = [&](int N, const double2* B, double2* C) {
+    if (P == 1)
+      CK(zgemm(st, OP_N, OP_N, ne, N, n, ONE, c->dMout.z(), ne, 0, B, n, nn, ZERO, C, ne, (ll)ne * N, nl));
+    else
+      CK(zgemm_div(st, OP_N, OP_N, ne, N, n, ONE, c->dMout.z(), ne, smo, lpp, B, n, nn, 1, ZERO, C, ne,
+                   (ll)ne * N, nl));
+  };
+  mout_gemm(ne, inv_edge, Rc);
+  if (c->o.keep_derivs) mout_gemm(mi, c->sInv.z(), c->dH.z());
   if (c->mixed) CK(hipMemcpyAsync(c->dRleaf.p, Rc, zb((size_t)nl * ne * ne), hipMemcpyDeviceToDevice, st));
 
   // merge tree
@@ -503,6 +520,10 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   CK(zgemm(st, OP_N, OP_N, nb, nb, nb, ONE, c->dA2.z(), nb, sbb, c->dRroot.z(), nb, sbb, ONE, Z, nb, sbb,
            P));
   CK(zinv(st, nb, Z, nb, sbb, c->dZinv.z(), nb, sbb, P, c->sZws.p, c->sInfo.i()));
+  if (c->o.keep_derivs) {
+    CK(conj_transpose(st, nb, c->dRroot.z(), nb, sbb, c->dRrootH.z(), nb, sbb, P));
+    CK(conj_transpose(st, nb, c->dZinv.z(), nb, sbb, c->dZinvH.z(), nb, sbb, P));
+  }
   mark(c, 0, 1);
   std::vector<int> info(ninfo);
   CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * ninfo, hipMemcpyDeviceToHost, st));
@@ -916,9 +937,9 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
   double2* fb = Ho;
   double2* gb = Hc;
   CK(boundary_st_adj(st, c->sST2.z(), nb, M, c->dPk.d() + 2 * P, fb, gb, P));
-  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, gb, nb, sF, ONE, fb, nb, sF, P));
-  CK(zgemm(st, OP_C, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, sbb, fb, nb, sF, ZERO, c->sW2.z(), nb, sF, P));
-  CK(zgemm(st, OP_C, OP_N, nb, M, nb, MONE, c->dA2.z(), nb, sbb, c->sW2.z(), nb, sF, ONE, gb, nb, sF, P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRrootH.z(), nb, sbb, gb, nb, sF, ONE, fb, nb, sF, P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinvH.z(), nb, sbb, fb, nb, sF, ZERO, c->sW2.z(), nb, sF, P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dA2H.z(), nb, sbb, c->sW2.z(), nb, sF, ONE, gb, nb, sF, P));
   for (int l = g.nlev; l >= 1; --l) {
     const LevelPattern& L = g.lev[l];
     const int cnt = L.count * P, m = L.m, s = L.s, np = L.np;
@@ -1097,7 +1118,7 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
 int64_t device_bytes(const hps_ctx* c) {
   int64_t s = 0;
   const DBuf* bufs[] = {&c->dA0, &c->dMout, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dPk, &c->dY, &c->dH,
-                        &c->dRroot, &c->dZinv, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
+                        &c->dRroot, &c->dZinv, &c->dRrootH, &c->dZinvH, &c->dA2H, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
                         &c->sBlk, &c->sW, &c->sWinv, &c->sQ, &c->sVin, &c->sV, &c->sTmp, &c->sInfo,
                         &c->d_dirs, &c->dG, &c->dRhs, &c->dF0, &c->dF1, &c->dF3, &c->du0, &c->dST,
                         &c->dg, &c->dPhi, &c->sB, &c->sST2, &c->sW2, &c->dSx, &c->dSy,

@@ -29,6 +29,9 @@ hipError_t add_f32(hipStream_t st, const float2* x, ll n, double2* y);
 hipError_t to_f64(hipStream_t st, const float2* x, ll n, double2* y);
 hipError_t add_to_f32(hipStream_t st, const double2* x, ll n, float2* y);
 hipError_t zadd(hipStream_t st, const double2* x, const double2* y, double2* z, ll n);
+// out_b = in_b^H for batch square n x n matrices (column-major).
+hipError_t conj_transpose(hipStream_t st, int n, const double2* in, ll ldi, ll si, double2* out, ll ldo, ll so,
+                          int batch);
 // Interface residual of one level from leaf-edge data F, G ([leaf][ne][M]):
 // sab = [alpha slots (s); beta slots (s)] relative to a merge's first leaf,
 // lpm leaves per merge, cnt merges; rho = [F(beta) + G(alpha); F(alpha) +

@@ -295,6 +295,28 @@ __global__ void k_skel_gather(int n, int M, int ne, int lpb, const int* slot, co
   }
 }
 
+// out = in^H for square n x n matrices (column-major), 32 x 32 tiles through
+// LDS so that both the reads and the writes are coalesced.
+__global__ __launch_bounds__(256) void k_conj_transpose(int n, const double2* in, ll ldi, ll si, double2* out,
+                                                        ll ldo, ll so) {
+  __shared__ double2 tile[32][33];
+  const ll b = blockIdx.z;
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int j = ty; j < 32; j += 8) {
+    const int r = r0 + tx, c = c0 + j;
+    if (r < n && c < n) tile[j][tx] = in[b * si + (ll)r + (ll)c * ldi];
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int r = c0 + tx, c = r0 + j;  // out(r, c) = conj(in(c, r))
+    if (r < n && c < n) {
+      const double2 v = tile[tx][j];
+      out[b * so + (ll)r + (ll)c * ldo] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
 // y = a x + b y
 __global__ void k_axpby(double a, const double* x, double b, double* y, ll n) {
   for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT) y[i] = a * x[i] + b * y[i];
@@ -399,6 +421,15 @@ hipError_t to_f64(hipStream_t st, const float2* x, ll n, double2* y) {
 hipError_t add_to_f32(hipStream_t st, const double2* x, ll n, float2* y) {
   KernelTimer kt(st, K_POINT, 2.0 * (double)n, 32.0 * (double)n);
   hipLaunchKernelGGL(k_add_to_f32, dim3(blocks_for(n)), dim3(NT), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t conj_transpose(hipStream_t st, int n, const double2* in, ll ldi, ll si, double2* out, ll ldo, ll so,
+                          int batch) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)n * n * batch);
+  const unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_conj_transpose, dim3(t, t, batch), dim3(256), 0, st, n, in, ldi, si, out, ldo, so);
   return hipGetLastError();
 }
 
