@@ -29,11 +29,17 @@ hipError_t zgemm_rowmask(hipStream_t st, int opA, int opB, int M, int N, int K, 
 hipError_t zgemm_div(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
                      const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB,
                      int bdiv, double2 beta, double2* C, ll ldc, ll sC, int batch);
-// Both of the above.
+// zgemm whose output row r is stored at row rmap[r] of C, plus rpart
+// elements for r >= rsplit (a product scattered into two vectors, e.g. the
+// children of a merge).
+hipError_t zgemm_rowmap(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha, const double2* A,
+                        ll lda, ll sA, const double2* B, ll ldb, ll sB, double2 beta, double2* C, ll ldc, ll sC,
+                        const int* rmap, int rsplit, ll rpart, int batch);
+// All of the above.
 hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
                       const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB,
                       int bdiv, double2 beta, double2* C, ll ldc, ll sC, const int* rpos, ll srp,
-                      int plo, int phi, int batch);
+                      int plo, int phi, int batch, const int* rmap, int rsplit, ll rpart);
 
 // FP32 complex GEMM (same conventions as zgemm; FP32 MFMA, FP32 accumulation).
 hipError_t cgemm(hipStream_t st, int opA, int opB, int M, int N, int K, float2 alpha,

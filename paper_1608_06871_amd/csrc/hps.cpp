@@ -111,6 +111,8 @@ struct hps_ctx {
   // leaf-edge slots: [1 .. nlev] the shared nodes of a merge ([alpha; beta]
   // sides), [0] the outer boundary in root order
   std::vector<DBuf> dSlot;
+  // per level: [pos3a; pos3b], the shared-edge rows of the two children
+  std::vector<DBuf> dMap3;
 
   // mixed precision
   bool mixed = false;
@@ -554,18 +556,23 @@ void plan_sweep_buffers(hps_ctx* c, int M) {
   c->du0.ensure(zb(P * g.nleaf * g.mi * M));
 }
 
-// Scatter parent data [f1; f2] and shared-edge data [f3a; f3b] into the two
-// children's boundary orderings (one level of the down-sweep; also the
-// adjoint of the up-sweep's gathers).
-void scatter_children(hps_ctx* c, int l, const double2* Fp, const double2* F3, double2* Fch, int M) {
+// Down-sweep step of one level: F3 = Op [f1; f2] per merge (Op: D, or U^H
+// for the adjoint sweep) written straight into the two children's boundary
+// orderings (rows pos3a of child alpha, pos3b of child beta), then the
+// parent data [f1; f2] copied to the children's exterior rows.
+void down_level(hps_ctx* c, int l, int op, const double2* Op, const double2* Fp, double2* Fch, int M) {
   const LevelPattern& L = c->g.lev[l];
   const int cnt = L.count * c->P, m = L.m, s = L.s, nc = L.nc, np = L.np;
-  const ll sp = (ll)np * M, s3 = 2LL * s * M, sc = 2LL * nc * M;
+  const ll sp = (ll)np * M, sc = 2LL * nc * M;
   hipStream_t st = c->st;
+  if (op == OP_N)
+    CK(zgemm_rowmap(st, OP_N, OP_N, 2 * s, M, np, ONE, Op, 2 * s, 4LL * m * s, Fp, np, sp, ZERO, Fch, nc, sc,
+                    c->dMap3[l].i(), s, (ll)nc * M, cnt));
+  else
+    CK(zgemm_rowmap(st, OP_C, OP_N, 2 * s, M, np, ONE, Op, np, 4LL * m * s, Fp, np, sp, ZERO, Fch, nc, sc,
+                    c->dMap3[l].i(), s, (ll)nc * M, cnt));
   CK(scatter_rows(st, m, M, Fp, np, sp, c->didx[4 * l].i(), Fch, nc, sc, cnt));
-  CK(scatter_rows(st, s, M, F3, 2 * s, s3, c->didx[4 * l + 1].i(), Fch, nc, sc, cnt));
   CK(scatter_rows(st, m, M, Fp + m, np, sp, c->didx[4 * l + 2].i(), Fch + (ll)nc * M, nc, sc, cnt));
-  CK(scatter_rows(st, s, M, F3 + s, 2 * s, s3, c->didx[4 * l + 3].i(), Fch + (ll)nc * M, nc, sc, cnt));
 }
 
 // ---- mixed precision: complex64 sweeps refined on the skeleton system ----
@@ -800,11 +807,7 @@ void solve(hps_ctx* c, int M, const double* ang) {
            P));
   CK(boundary_st(st, Fc, c->dg.z(), c->dG.z(), nb, M, etav, c->dST.z(), P));
   for (int l = g.nlev; l >= 1; --l) {
-    const LevelPattern& L = g.lev[l];
-    const int cnt = L.count * P, m = L.m, s = L.s, np = L.np;
-    CK(zgemm(st, OP_N, OP_N, 2 * s, M, 2 * m, ONE, c->dD[l].z(), 2 * s, 4LL * m * s, Fc, np,
-             (ll)np * M, ZERO, c->dF3.z(), 2 * s, 2LL * s * M, cnt));
-    scatter_children(c, l, Fc, c->dF3.z(), Fo, M);
+    down_level(c, l, OP_N, c->dD[l].z(), Fc, Fo, M);
     std::swap(Fc, Fo);
   }
   CK(zgemm(st, OP_N, OP_N, g.mi, M, g.ne, ONE, c->dY.z(), g.mi, (ll)g.mi * g.ne, Fc, g.ne,
@@ -941,11 +944,7 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinvH.z(), nb, sbb, fb, nb, sF, ZERO, c->sW2.z(), nb, sF, P));
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dA2H.z(), nb, sbb, c->sW2.z(), nb, sF, ONE, gb, nb, sF, P));
   for (int l = g.nlev; l >= 1; --l) {
-    const LevelPattern& L = g.lev[l];
-    const int cnt = L.count * P, m = L.m, s = L.s, np = L.np;
-    CK(zgemm(st, OP_C, OP_N, 2 * s, M, np, ONE, c->dU[l].z(), np, 4LL * m * s, Hc, np, (ll)np * M,
-             ZERO, c->dF3.z(), 2 * s, 2LL * s * M, cnt));
-    scatter_children(c, l, Hc, c->dF3.z(), Ho, M);
+    down_level(c, l, OP_C, c->dU[l].z(), Hc, Ho, M);
     std::swap(Hc, Ho);
   }
   // grad = k^2 Re sum_dir conj(u0) (H^H g), summed over the directions first:
@@ -1188,11 +1187,15 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
     c->n = c->g.mi + c->g.ne;
     c->nb = (int)c->g.root.size();
     c->didx.resize(4 * (size_t)(c->g.nlev + 1));
+    c->dMap3.resize(c->g.nlev + 1);
     for (int l = 1; l <= c->g.nlev; ++l) {
       const LevelPattern& P = c->g.lev[l];
       const std::vector<int>* v[4] = {&P.pos1a, &P.pos3a, &P.pos2b, &P.pos3b};
       for (int a = 0; a < 4; ++a)
         upload(c->didx[4 * l + a], v[a]->data(), v[a]->size() * sizeof(int), c->st);
+      std::vector<int> m3(P.pos3a);
+      m3.insert(m3.end(), P.pos3b.begin(), P.pos3b.end());
+      upload(c->dMap3[l], m3.data(), m3.size() * sizeof(int), c->st);
     }
     // leaf-edge slot (leaf offset inside the box * ne + edge position) of
     // every boundary position of a box, level by level: a box lists the

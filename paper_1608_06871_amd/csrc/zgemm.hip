@@ -78,6 +78,9 @@ struct ArgsT {
   int adiv, bdiv;  // batch index divisors of A and B (operand of batch b: b / div)
   int kchunk;      // split K: slice z of the grid covers [z kchunk, (z + 1) kchunk)
   ll sCz;          // split K: C offset of slice z
+  const int* rmap; // optional: row r of C is stored at row rmap[r] (+ rpart if r >= rsplit)
+  int rsplit;
+  ll rpart;
 };
 typedef ArgsT<double> Args;
 
@@ -414,7 +417,8 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
         const double xr = M3 ? p1[i][j][r] - p2[i][j][r] : p1[i][j][r];
         const double xi = M3 ? p3[i][j][r] - p1[i][j][r] - p2[i][j][r] : p3[i][j][r];
         double2 v = make_double2(a.alpha.x * xr - a.alpha.y * xi, a.alpha.x * xi + a.alpha.y * xr);
-        double2* pc = C + (ll)row + (ll)col * a.ldc;
+        const ll roff = a.rmap ? (ll)a.rmap[row] + (row >= a.rsplit ? a.rpart : 0) : (ll)row;
+        double2* pc = C + roff + (ll)col * a.ldc;
         if (use_beta && !(rp && rp[row] >= a.plo && rp[row] < a.phi)) {
           const double2 c = *pc;
           v.x += a.beta.x * c.x - a.beta.y * c.y;
@@ -438,7 +442,8 @@ hipError_t launch_t(hipStream_t st, const ArgsT<T>& a, int batch, int splits = 1
 // C = alpha sum_z W[z] + beta C (rows in the overwrite range take beta = 0);
 // W[z] holds batch consecutive M x N blocks.
 __global__ void k_splitk_reduce(const double2* W, int splits, ll sz, int M, int N, double2 alpha, double2 beta,
-                                double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi, int batch) {
+                                double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi,
+                                const int* rmap, int rsplit, ll rpart, int batch) {
   const ll per = (ll)M * N, total = per * batch;
   const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
   for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
@@ -452,7 +457,8 @@ __global__ void k_splitk_reduce(const double2* W, int splits, ll sz, int M, int 
       acc.y += w.y;
     }
     double2 v = make_double2(alpha.x * acc.x - alpha.y * acc.y, alpha.x * acc.y + alpha.y * acc.x);
-    double2* pc = C + b * sC + (ll)i + (ll)j * ldc;
+    const ll roff = rmap ? (ll)rmap[i] + (i >= rsplit ? rpart : 0) : (ll)i;
+    double2* pc = C + b * sC + roff + (ll)j * ldc;
     const int* rp = rpos ? rpos + b * srp : nullptr;
     if (use_beta && !(rp && rp[i] >= plo && rp[i] < phi)) {
       const double2 c = *pc;
@@ -677,24 +683,32 @@ hipError_t zgemm_rowmask(hipStream_t st, int opA, int opB, int M, int N, int K, 
                          const double2* A, ll lda, ll sA, const double2* B, ll ldb, ll sB, double2 beta,
                          double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi, int batch) {
   return zgemm_full(st, opA, opB, M, N, K, alpha, A, lda, sA, 1, B, ldb, sB, 1, beta, C, ldc, sC, rpos, srp,
-                    plo, phi, batch);
+                    plo, phi, batch, nullptr, 0, 0);
+}
+
+hipError_t zgemm_rowmap(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha, const double2* A,
+                        ll lda, ll sA, const double2* B, ll ldb, ll sB, double2 beta, double2* C, ll ldc, ll sC,
+                        const int* rmap, int rsplit, ll rpart, int batch) {
+  return zgemm_full(st, opA, opB, M, N, K, alpha, A, lda, sA, 1, B, ldb, sB, 1, beta, C, ldc, sC, nullptr, 0, 0,
+                    0, batch, rmap, rsplit, rpart);
 }
 
 hipError_t zgemm_div(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
                      const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB, int bdiv,
                      double2 beta, double2* C, ll ldc, ll sC, int batch) {
   return zgemm_full(st, opA, opB, M, N, K, alpha, A, lda, sA, adiv, B, ldb, sB, bdiv, beta, C, ldc, sC,
-                    nullptr, 0, 0, 0, batch);
+                    nullptr, 0, 0, 0, batch, nullptr, 0, 0);
 }
 
 hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, double2 alpha,
                       const double2* A, ll lda, ll sA, int adiv, const double2* B, ll ldb, ll sB, int bdiv,
                       double2 beta, double2* C, ll ldc, ll sC, const int* rpos, ll srp, int plo, int phi,
-                      int batch) {
+                      int batch, const int* rmap, int rsplit, ll rpart) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535 || adiv < 1 || bdiv < 1) return hipErrorInvalidValue;
+  if (rmap && (adiv != 1 || bdiv != 1)) return hipErrorInvalidValue;
   Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, rpos, srp, plo, phi,
-         adiv, bdiv, K < 0 ? 0 : K, 0};
+         adiv, bdiv, K < 0 ? 0 : K, 0, rmap, rsplit, rpart};
   const bool rb = (beta.x != 0.0 || beta.y != 0.0);
   KernelTimer kt(st, K_ZGEMM, 8.0 * M * N * (double)a.K * batch,
                  16.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);
@@ -718,6 +732,7 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
     p.alpha = make_double2(1.0, 0.0);
     p.beta = make_double2(0.0, 0.0);
     p.rpos = nullptr;
+    p.rmap = nullptr;
     p.kchunk = ((a.K + splits - 1) / splits + 15) / 16 * 16;
     p.sCz = per;
     const int used = (a.K + p.kchunk - 1) / p.kchunk;
@@ -725,11 +740,12 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
     ll blocks = (per + NT - 1) / NT;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(NT), 0, st, (const double2*)ws, used, per, M,
-                       N, alpha, beta, C, ldc, sC, rpos, srp, plo, phi, batch);
+                       N, alpha, beta, C, ldc, sC, rpos, srp, plo, phi, a.rmap, a.rsplit, a.rpart, batch);
     return hipGetLastError();
   }
-  if (g_tune_mode.load() == 1) {
-    const TuneKey key{M, N, a.K, batch, opA, opB, rb ? 1 : 0, rpos ? 1 : 0, lda, ldb, ldc, sA, sB, sC};
+  if (g_tune_mode.load() == 1 && !(rmap && rb)) {
+    const TuneKey key{M, N, a.K, batch, opA, opB, rb ? 1 : 0, (rpos ? 1 : 0) + (rmap ? 2 : 0), lda, ldb, ldc,
+                      sA, sB, sC};
     int v = -1;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
