@@ -126,6 +126,90 @@ def gn_timing(s, k, dirs, th, R, steps, S=160, cg_iters=30):
             "model_rel_err_after_step": err, "start": "half the true coefficients"}
 
 
+GEMM_SOURCE = os.path.join(ROOT, "paper_1608_06871_amd", "csrc", "zgemm.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zgemm_traffic_k80_L64_M256_fp64.json")
+
+
+def source_sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the complex FP64 GEMM class from the committed
+    counter summary, or None when the GEMM source has changed since the
+    counters were taken (or no summary exists)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sha256") != source_sha256(GEMM_SOURCE):
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def copy_probe(mib, reps=4):
+    """Plain device copies of `mib` MiB (hipMemcpy kernels): the calibration
+    of the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": reps + 1}), flush=True)
+
+
+def pmc_sum(csv_path, pattern, counter):
+    """Sum of `counter` (KiB) and the dispatch count over the kernels whose
+    name matches `pattern` in a rocprofv3 counter_collection.csv."""
+    import csv
+    import re
+    tot, disp = 0.0, set()
+    rx = re.compile(pattern)
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"]):
+                tot += float(r["Counter_Value"])
+                disp.add(r["Dispatch_Id"])
+    return tot, len(disp)
+
+
+def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, out_path):
+    """Writes the GEMM-class HBM traffic per launch from four counter runs:
+    FETCH_SIZE and WRITE_SIZE of the benchmark's timed steps and of a plain
+    copy of copy_bytes bytes, which calibrates each counter (bytes per KiB
+    counted)."""
+    # bytes of every kernel of a GEMM call (split-K slices and their
+    # reduction included); launches = GEMM calls = main-kernel dispatches
+    gemm = r"zgemm_kernel|gemm_kernel<double|k_splitk_reduce"
+    main = r"zgemm_kernel|gemm_kernel<double"
+    copy = r"copyBuffer"
+    f_kib, _ = pmc_sum(fetch_csv, gemm, "FETCH_SIZE")
+    w_kib, _ = pmc_sum(write_csv, gemm, "WRITE_SIZE")
+    _, nf = pmc_sum(fetch_csv, main, "FETCH_SIZE")
+    _, nw = pmc_sum(write_csv, main, "WRITE_SIZE")
+    cf_kib, ncf = pmc_sum(copy_fetch_csv, copy, "FETCH_SIZE")
+    cw_kib, ncw = pmc_sum(copy_write_csv, copy, "WRITE_SIZE")
+    # each copy reads and writes copy_bytes once
+    sf = copy_bytes * ncf / (cf_kib * 1024.0)
+    sw = copy_bytes * ncw / (cw_kib * 1024.0)
+    launches = max(nf, nw)
+    per = (f_kib * 1024.0 * sf + w_kib * 1024.0 * sw) / launches
+    res = {"source": os.path.relpath(GEMM_SOURCE, ROOT), "sha256": source_sha256(GEMM_SOURCE),
+           "launches": launches, "fetch_kib": f_kib, "write_kib": w_kib,
+           "copy_bytes": copy_bytes, "copy_fetch_kib_per_copy": cf_kib / ncf, "copy_write_kib_per_copy": cw_kib / ncw,
+           "scale_fetch": sf, "scale_write": sw, "traffic_bytes_per_launch": per}
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res), flush=True)
+
+
 def batch_problems(n=32, seed0=100):
     """32 independent problems: k ~ U[10, 60], leaf grids 8, 16 or 32 per
     side, 16 to 256 directions, contrasts from the 5-bump generator."""
@@ -208,6 +292,7 @@ def run_batch(args):
                    "problems": len(probs), "rhs": nrhs},
         "one_by_one_ms": dt1 * 1e3, "one_by_one_rhs_per_s": nrhs / dt1, "speedup_vs_one_by_one": dt1 / dt,
         "max_rel_diff_vs_one_by_one": maxdiff, "t_wavenumber_setup_s": t_set,
+        "gemm_tuning": hps.gemm_tuning_info(),
     }
     print(json.dumps(res), flush=True)
 
@@ -222,9 +307,20 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-gn", action="store_true", help="skip the Gauss-Newton step timing")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="fixed GEMM tile rules instead of autotuning in the warm-up pass")
+    ap.add_argument("--tune", choices=["auto", "on", "off"], default="auto",
+                    help="GEMM tile autotuning in the warm-up pass (auto: on for the batch workload, off for "
+                         "the single-problem workload, whose profiles then hold no tuning trials)")
+    ap.add_argument("--copy-probe", type=int, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--traffic-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                           "COPY_WRITE_CSV", "COPY_BYTES"),
+                    help="write the GEMM traffic summary from four rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.traffic_summary:
+        a = args.traffic_summary
+        return traffic_summary(a[0], a[1], a[2], a[3], int(a[4]), TRAFFIC_FILE)
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (--gpus {args.gpus} "
               "requested). Run with --gpus 1.", file=sys.stderr)
@@ -233,7 +329,7 @@ def main():
     import torch
     import paper_1608_06871_amd as hps
     import synth
-    tune = not args.no_tune and args.warmup >= 1
+    tune = args.warmup >= 1 and (args.tune == "on" or (args.tune == "auto" and args.config == "batch32"))
     if tune:
         # every GEMM shape is tuned on its first call, in the untimed warm-up
         hps.gemm_tuning(1)
@@ -304,7 +400,8 @@ def main():
         if kd["flops"] > 0:
             achieved = kd["flops"] / (kd["total_ms"] * 1e-3) / 1e12
             roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                        "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                        "frac": achieved / PEAK_FP64_TFLOPS,
+                        "traffic": stored_traffic() if dom == "zgemm" else None, "kernel": dom,
                         "launches": kd["launches"], "avg_launch_ms": per_launch_ms,
                         "flops_per_launch": kd["flops"] / kd["launches"]}
         else:

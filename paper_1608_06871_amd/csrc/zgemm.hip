@@ -251,6 +251,18 @@ __global__ __launch_bounds__(NT, WAVES) void gemm_kernel(ArgsT<T> a) {
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (the
+// i-th one of a grid in linear order x, then y runs on XCD i % 8), and each
+// XCD has its own L2.  The work item of workgroup i is renumbered so that
+// every XCD takes a contiguous range of the grid's (tile, batch) items: the
+// tiles of one small matrix, or neighbouring tiles of a large one, then share
+// their operand panels in one L2 instead of fetching them on several XCDs.
+constexpr unsigned NXCD = 8;
+__device__ inline unsigned xcd_order(unsigned i, unsigned n) {
+  const unsigned x = i % NXCD, k = i / NXCD, q = n / NXCD, r = n % NXCD;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // The FP64 kernel used by default.  It is kept as its own (non-template)
 // source: the same loop written through the precision template above
 // compiles to code that runs about 10% slower on MI355X (measured), so the
@@ -307,9 +319,11 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   __shared__ double Bre[NB][TK][TN + PAD], Bim[NB][TK][TN + PAD];
 
   const int tilesM = (a.M + TM - 1) / TM;
-  const int m0 = (blockIdx.x % tilesM) * TM;
-  const int n0 = (blockIdx.x / tilesM) * TN;
-  const ll b = blockIdx.y;
+  const unsigned wg = xcd_order(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  const unsigned tile = wg % gridDim.x;
+  const int m0 = (tile % tilesM) * TM;
+  const int n0 = (tile / tilesM) * TN;
+  const ll b = wg / gridDim.x;
   const double2* A = a.A + b * a.sA;
   const double2* B = a.B + b * a.sB;
   double2* C = a.C + b * a.sC;
@@ -403,7 +417,7 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   // D layout of the 16x16x4 f64 MFMA: item r of a lane is row lane/16 + 4 r,
   // column lane % 16.
   const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
-  const int* rp = a.rpos ? a.rpos + (ll)blockIdx.y * a.srp : nullptr;
+  const int* rp = a.rpos ? a.rpos + b * a.srp : nullptr;
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -550,7 +564,9 @@ constexpr int NVARIANT = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
 // HPS_ZGEMM_TRACE=<file> appends one line per call (M N K batch opA opB
 // beta!=0 rowmask) for offline analysis of the call shapes.
-void trace_call(const Args& a, int batch) {
+// HPS_ZGEMM_TRACE=<file>: one line per call (sizes, batch, ops, beta != 0,
+// row mask / row map, tile variant; -1 split-K, -2 shared-operand path).
+void trace_call(const Args& a, int batch, int variant) {
   static FILE* f = nullptr;
   static int state = 0;
   if (state == 0) {
@@ -560,8 +576,8 @@ void trace_call(const Args& a, int batch) {
   }
   if (!f) return;
   const bool rb = (a.beta.x != 0.0 || a.beta.y != 0.0);
-  std::fprintf(f, "%d %d %d %d %d %d %d %d\n", a.M, a.N, a.K, batch, a.opA, a.opB, rb ? 1 : 0,
-               a.rpos ? 1 : 0);
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d\n", a.M, a.N, a.K, batch, a.opA, a.opB, rb ? 1 : 0,
+               (a.rpos ? 1 : 0) + (a.rmap ? 2 : 0), variant);
   std::fflush(f);
 }
 
@@ -656,6 +672,16 @@ hipError_t tune_shape(hipStream_t st, const Args& a, int batch, int* best) {
   return err;
 }
 
+// Fixed rules, from the autotuner's choices on MI355X over the solver's
+// shapes (with the XCD-contiguous work order): 32 x 64 tiles with K step 8
+// and three waves per SIMD, 32 x 32 tiles with four waves per SIMD for
+// products of at most 64 columns (the rank-32/64 updates of the inverses).
+int rule_variant(int M, int N, int K) {
+  (void)M;
+  (void)K;
+  return N <= 64 ? 18 : 17;
+}
+
 }  // namespace
 
 void gemm_set_tuning(int mode, int force) {
@@ -712,15 +738,19 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
   const bool rb = (beta.x != 0.0 || beta.y != 0.0);
   KernelTimer kt(st, K_ZGEMM, 8.0 * M * N * (double)a.K * batch,
                  16.0 * ((double)M * a.K + (double)a.K * N + (rb ? 2.0 : 1.0) * M * N) * batch);
-  trace_call(a, batch);
   if (adiv != 1 || bdiv != 1) {
+    trace_call(a, batch, -2);
     if (a.K <= 64) return launch_t<double, 2, 1, true, 8, 3, false, true>(st, a, batch);
     return launch_t<double, 2, 1, true, 16, 2, false, true>(st, a, batch);
   }
   const int fv = forced_variant();
-  if (fv >= 0) return VARIANTS[fv](st, a, batch);
+  if (fv >= 0) {
+    trace_call(a, batch, fv);
+    return VARIANTS[fv](st, a, batch);
+  }
   const int splits = choose_splits(M, N, a.K, batch);
   if (splits > 1) {
+    trace_call(a, batch, -1);
     // partial products of K slices into the workspace, then one reduction
     const ll per = (ll)M * N * batch;
     void* ws = nullptr;
@@ -757,13 +787,12 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
       HPS_HIP_TRY(tune_shape(st, a, batch, &v));
       g_tuned[key] = v;
     }
+    trace_call(a, batch, v);
     return VARIANTS[v](st, a, batch);
   }
-  // Fixed rules, from timings on MI355X over the solver's shapes: 64 x 32
-  // tiles with K step 8 and three waves per SIMD everywhere except long-K
-  // products with few columns (top solves), which prefer K step 16.
-  if (N <= 256 && a.K >= 1024) return launch<2, 1, true, 16, 2>(st, a, batch);
-  return launch<2, 1, true, 8, 3>(st, a, batch);
+  const int v = rule_variant(M, N, a.K);
+  trace_call(a, batch, v);
+  return VARIANTS[v](st, a, batch);
 }
 
 hipError_t cgemm(hipStream_t st, int opA, int opB, int M, int N, int K, float2 alpha, const float2* A, ll lda,
