@@ -40,20 +40,24 @@ class BatchForward:
     runs once per group.  Problems with many directions (more than m_split)
     form their own group on a grid; within a group the direction count is
     padded to the largest one by cycling each problem's own directions
-    (padded columns are computed and dropped).  Contexts are kept between
-    calls."""
+    (padded columns are computed and dropped).  Groups run concurrently, each
+    on its own stream and host thread (the library releases the interpreter
+    lock during its calls), so the launches of small groups overlap the work
+    of large ones.  Contexts and streams are kept between calls."""
 
-    def __init__(self, p=16, keep_derivs=False, m_split=64):
+    def __init__(self, p=16, keep_derivs=False, m_split=64, concurrent=True):
         self.p = p
         self.keep_derivs = keep_derivs
         self.m_split = m_split  # problems with more directions than this batch separately
+        self.concurrent = concurrent
         self._ctx = {}
 
     def _solver(self, key, L, nprob):
         from . import Solver
         key = key + (nprob,)
         if key not in self._ctx:
-            self._ctx[key] = Solver(nleaf=L, p=self.p, nprob=nprob, keep_derivs=self.keep_derivs)
+            stream = torch.cuda.Stream() if self.concurrent else None
+            self._ctx[key] = Solver(nleaf=L, p=self.p, nprob=nprob, keep_derivs=self.keep_derivs, stream=stream)
         return self._ctx[key]
 
     def groups(self, problems):
@@ -69,20 +73,38 @@ class BatchForward:
         for key, idx in self.groups(problems).items():
             self._solver(key, key[0], len(idx)).set_wavenumber([problems[i]["k"] for i in idx])
 
-    def run(self, problems, thetas, R):
-        """problems: dicts with L, k, q (float64 GPU tensor [npde]) and dirs
-        (angles).  Returns the far fields (complex128 GPU tensors [M_i, P])."""
-        out = [None] * len(problems)
-        for key, idx in self.groups(problems).items():
-            s = self._solver(key, key[0], len(idx))
+    def _run_group(self, s, problems, idx, thetas, R, ready):
+        with torch.cuda.stream(s.stream):
+            s.stream.wait_event(ready)
             M = max(len(problems[i]["dirs"]) for i in idx)
             dirs = np.stack([np.resize(np.asarray(problems[i]["dirs"], dtype=np.float64), M) for i in idx])
             q = torch.stack([problems[i]["q"] for i in idx]).contiguous()
             s.factor(q, [problems[i]["k"] for i in idx])
             s.solve(dirs)
             ff = s.far_field(thetas, R)
-            if ff.dim() == 2:  # a group of one problem has no problem axis
-                ff = ff.unsqueeze(0)
+        if ff.dim() == 2:  # a group of one problem has no problem axis
+            ff = ff.unsqueeze(0)
+        return ff
+
+    def run(self, problems, thetas, R):
+        """problems: dicts with L, k, q (float64 GPU tensor [npde]) and dirs
+        (angles).  Returns the far fields (complex128 GPU tensors [M_i, P]),
+        ready for use on the caller's current stream."""
+        out = [None] * len(problems)
+        cur = torch.cuda.current_stream()
+        ready = torch.cuda.Event()
+        ready.record(cur)  # the inputs were produced on the caller's stream
+        work = [(self._solver(key, key[0], len(idx)), idx) for key, idx in self.groups(problems).items()]
+        if self.concurrent and len(work) > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=len(work)) as ex:
+                futs = [ex.submit(self._run_group, s, problems, idx, thetas, R, ready) for s, idx in work]
+                results = [f.result() for f in futs]
+        else:
+            results = [self._run_group(s, problems, idx, thetas, R, ready) for s, idx in work]
+        for (s, idx), ff in zip(work, results):
+            cur.wait_stream(s.stream)
+            ff.record_stream(cur)
             for j, i in enumerate(idx):
                 out[i] = ff[j, :len(problems[i]["dirs"])]
         return out
