@@ -31,6 +31,9 @@
 //     panel's pivot rows remain, whose block the last reduction also
 //     inverts; one more kernel exchanges the panel columns.
 #include <cfloat>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 
@@ -662,6 +665,88 @@ hipError_t block_update(const Inv& v, int s0, int s1, int d0, int d1) {
                        v.n, s0, s1, v.batch);
 }
 
+// Second stream per caller stream for the look-ahead updates (created on
+// first use, kept for the process lifetime like the GEMM workspaces).
+std::mutex g_side_mu;
+std::vector<std::pair<hipStream_t, hipStream_t>> g_side;
+
+hipError_t side_stream(hipStream_t st, hipStream_t* out) {
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  for (auto& e : g_side)
+    if (e.first == st) {
+      *out = e.second;
+      return hipSuccess;
+    }
+  hipStream_t x = nullptr;
+  HPS_HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+  g_side.push_back({st, x});
+  *out = x;
+  return hipSuccess;
+}
+
+// Right-looking elimination with one panel of look-ahead, for the
+// tournament path: after panel p is exchanged, the caller's stream applies it
+// to the next panel's columns only and goes on with that panel's (latency-
+// bound) tournament, while the second stream applies it to every other
+// column (those of earlier panels included: Gauss-Jordan applies every pivot
+// to every column).  The caller's stream waits for the second stream only before it
+// gathers the next pivot rows.  The second stream never writes the current
+// or the next panel's columns; its row mask (pivot positions of panel p)
+// is unaffected by the positions the next panel assigns meanwhile.
+hipError_t lookahead_inverse(const Inv& v) {
+  const int n = v.n;
+  hipStream_t X = nullptr;
+  HPS_HIP_TRY(side_stream(v.st, &X));
+  hipEvent_t t_ready = nullptr, x_done = nullptr;
+  HPS_HIP_TRY(hipEventCreateWithFlags(&t_ready, hipEventDisableTiming));
+  hipError_t err = hipEventCreateWithFlags(&x_done, hipEventDisableTiming);
+  bool pending = false;  // an update on X not yet waited for
+  for (int c0 = 0; c0 < n && err == hipSuccess; c0 += BMAX) {
+    const int b = n - c0 < BMAX ? n - c0 : BMAX;
+    if ((err = tournament_panel(v, c0, b)) != hipSuccess) break;
+    const int c1 = c0 + b;
+    const int b1 = n - c1 < BMAX ? n - c1 : BMAX;  // next panel (0 after the last)
+    // the pivot rows of panel p in every column, once X has applied panel p-1
+    if (pending && (err = hipStreamWaitEvent(v.st, x_done, 0)) != hipSuccess) break;
+    {
+      KernelTimer kt(v.st, K_MOVE, 0.0, 32.0 * b * (double)n * v.batch);
+      hipLaunchKernelGGL(gj_pivot_rows, dim3((unsigned)(((ll)b * n + NT - 1) / NT), v.batch), dim3(NT), 0, v.st,
+                         v.work, v.lda, v.sA, v.sig, n, c0, b, 0, n, v.T, v.sT);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) break;
+    if ((err = hipEventRecord(t_ready, v.st)) != hipSuccess) break;
+    const double2 one = make_double2(1.0, 0.0);
+    const double2* S = v.work + (ll)c0 * v.lda;
+    // next panel's columns, on the caller's stream
+    if (b1 > 0 &&
+        (err = zgemm_rowmask(v.st, OP_N, OP_N, n, b1, b, one, S, v.lda, v.sA, v.T + (ll)c1 * b, b, v.sT, one,
+                             v.work + (ll)c1 * v.lda, v.lda, v.sA, v.pos, n, c0, c1, v.batch)) != hipSuccess)
+      break;
+    // every other column, on X
+    if ((err = hipStreamWaitEvent(X, t_ready, 0)) != hipSuccess) break;
+    if (c0 > 0 && (err = zgemm_rowmask(X, OP_N, OP_N, n, c0, b, one, S, v.lda, v.sA, v.T, b, v.sT, one, v.work,
+                                       v.lda, v.sA, v.pos, n, c0, c1, v.batch)) != hipSuccess)
+      break;
+    const int c2 = c1 + b1;
+    if (c2 < n && (err = zgemm_rowmask(X, OP_N, OP_N, n, n - c2, b, one, S, v.lda, v.sA, v.T + (ll)c2 * b, b,
+                                       v.sT, one, v.work + (ll)c2 * v.lda, v.lda, v.sA, v.pos, n, c0, c1,
+                                       v.batch)) != hipSuccess)
+      break;
+    if ((err = hipEventRecord(x_done, X)) != hipSuccess) break;
+    pending = true;
+  }
+  // everything on X before the caller's stream goes on
+  if (pending) {
+    const hipError_t e2 = hipStreamWaitEvent(v.st, x_done, 0);
+    if (err == hipSuccess) err = e2;
+  }
+  // the events may be destroyed while recorded work is pending (HIP defers
+  // the release)
+  (void)hipEventDestroy(t_ready);
+  if (x_done) (void)hipEventDestroy(x_done);
+  return err;
+}
+
 hipError_t process_block(const Inv& v, int c0, int c1) {
   const int w = c1 - c0;
   if (w <= BMAX) {
@@ -719,7 +804,7 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
     hipLaunchKernelGGL(gj_init, dim3((n + 255) / 256, batch), dim3(256), 0, st, v.pos, n);
   }
   HPS_HIP_TRY(hipGetLastError());
-  HPS_HIP_TRY(process_block(v, 0, n));
+  HPS_HIP_TRY(n > NS_MAX_N ? lookahead_inverse(v) : process_block(v, 0, n));
   {
     KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
     hipLaunchKernelGGL(gj_unpermute, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, v.sig, v.pos,
