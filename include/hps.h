@@ -256,6 +256,20 @@ hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const 
  * pivot.  Allocates its own workspace. */
 hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
 
+/* Column blocking of the inverses of order above 512 (hps_zinv and the
+ * factorisation's W and Z inverses), process-wide; a performance choice, both
+ * give the inverse to rounding (the merges and the top of the Section 2
+ * direct solver only use the products with W^{-1} and Z^{-1}):
+ *   mode 1: right-looking with one panel of look-ahead (the next panel's
+ *           pivot search overlaps the update of the other columns on a
+ *           second stream);
+ *   mode 0: recursive column blocking (fewer, larger GEMM updates);
+ *   mode -1 (default): mode 1 while the batch of matrices fits the 256 MB
+ *           last-level cache (batch * n * n * 16 bytes), else mode 0.
+ * HPS_ZINV_LOOKAHEAD = 0 / 1 in the environment sets the initial mode.
+ * HPS_EINVAL for other modes. */
+hps_status hps_zinv_blocking(int mode);
+
 /* Tile shapes of the complex FP64 GEMM behind every call of this library,
  * process-wide (a performance choice; results do not depend on it: every
  * candidate tile shape accumulates the products of an output element in the

@@ -76,6 +76,7 @@ SIGNATURES = [
     ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
     ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
     ("hps_gemm_tuning", _I, [_I, _I]),
+    ("hps_zinv_blocking", _I, [_I]),
     ("hps_gemm_tuning_info", _I, [_P, _P, _P]),
     ("hps_profile_start", _I, []),
     ("hps_profile_stop", _I, [ctypes.POINTER(KernelStat), _I]),
@@ -361,6 +362,15 @@ def gemm_tuning(mode=1, force=-1):
     rc = lib().hps_gemm_tuning(int(mode), int(force))
     if rc != HPS_OK:
         raise HpsError(rc, "hps_gemm_tuning")
+
+
+def zinv_blocking(mode=-1):
+    """Column blocking of the inverses of order above 512 (process-wide):
+    1 right-looking with look-ahead, 0 recursive, -1 by size (look-ahead while
+    the batch fits the last-level cache)."""
+    rc = lib().hps_zinv_blocking(int(mode))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_zinv_blocking")
 
 
 def gemm_tuning_info():

@@ -51,6 +51,10 @@ void gemm_set_tuning(int mode, int force);
 void gemm_tuning_info(int* shapes, double* seconds);
 int gemm_variant_count();
 
+// Blocking of zinv for orders above 512 (process-wide): -1 by size (look-ahead
+// while the batch fits the last-level cache), 0 recursive, 1 look-ahead.
+void zinv_set_blocking(int mode);
+
 // Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
 size_t zinv_workspace(int n, int batch);
 

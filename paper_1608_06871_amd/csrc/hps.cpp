@@ -1413,6 +1413,12 @@ hps_status hps_gemm_tuning(int mode, int force) {
   return HPS_OK;
 }
 
+hps_status hps_zinv_blocking(int mode) {
+  if (mode < -1 || mode > 1) return HPS_EINVAL;
+  zinv_set_blocking(mode);
+  return HPS_OK;
+}
+
 hps_status hps_gemm_tuning_info(int* variants, int* shapes_tuned, double* seconds) {
   if (variants) *variants = gemm_variant_count();
   gemm_tuning_info(shapes_tuned, seconds);

@@ -30,7 +30,9 @@
 //     partial pivoting, candidate sets are reduced the same way until the
 //     panel's pivot rows remain, whose block the last reduction also
 //     inverts; one more kernel exchanges the panel columns.
+#include <atomic>
 #include <cfloat>
+#include <cstdlib>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -761,7 +763,30 @@ hipError_t process_block(const Inv& v, int c0, int c1) {
   return block_update(v, m, c1, c0, m);
 }
 
+// Orders above the register-panel limit: right-looking with look-ahead, or
+// the recursive column blocking.  The right-looking scheme reads and writes
+// every matrix of the batch once per 32-column panel, which pays while the
+// batch stays resident in the 256 MB last-level cache; larger batches take
+// the recursive blocking, whose fewer, larger products need less traffic.
+// g_blocking: -2 not read yet, -1 that rule, 0 / 1 recursive / look-ahead
+// (zinv_set_blocking, or HPS_ZINV_LOOKAHEAD = 0 / 1 in the environment).
+std::atomic<int> g_blocking{-2};
+
+bool use_lookahead(int n, int batch) {
+  int m = g_blocking.load();
+  if (m == -2) {
+    const char* e = std::getenv("HPS_ZINV_LOOKAHEAD");
+    int want = (e && (*e == '0' || *e == '1')) ? *e - '0' : -1;
+    g_blocking.compare_exchange_strong(m, want);
+    m = g_blocking.load();
+  }
+  if (m >= 0) return m == 1;
+  return (double)batch * n * n * sizeof(double2) <= 256.0 * 1024 * 1024;
+}
+
 }  // namespace
+
+void zinv_set_blocking(int mode) { g_blocking.store(mode); }
 
 size_t zinv_workspace(int n, int batch) {
   size_t bytes = align256((size_t)batch * n * sizeof(int) * 2);   // sig + pos
@@ -804,7 +829,7 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
     hipLaunchKernelGGL(gj_init, dim3((n + 255) / 256, batch), dim3(256), 0, st, v.pos, n);
   }
   HPS_HIP_TRY(hipGetLastError());
-  HPS_HIP_TRY(n > NS_MAX_N ? lookahead_inverse(v) : process_block(v, 0, n));
+  HPS_HIP_TRY(n > NS_MAX_N && use_lookahead(n, batch) ? lookahead_inverse(v) : process_block(v, 0, n));
   {
     KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
     hipLaunchKernelGGL(gj_unpermute, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, v.sig, v.pos,

@@ -132,6 +132,30 @@ def test_zinv_large_multilevel_tournament():
     assert err < 1e-11
 
 
+@pytest.mark.parametrize("n,batch", [(513, 1), (1100, 2), (4200, 1)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_zinv_blockings_agree(n, batch, mode):
+    """Both column blockings of the orders above 512 (recursive; right-looking
+    with look-ahead, whose last panel is partial for 513 and 1100) give
+    inv A = I to rounding; 4200 also takes the multi-level tournament."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    print(f"zinv n={n} batch={batch} blocking={mode}", flush=True)
+    rng = np.random.default_rng(n + 7 * batch)
+    A = _rand(rng, (batch, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    A[:, 0, 0] = 1e-12
+    Ag = _colmajor(torch, A)
+    hps.zinv_blocking(mode)
+    try:
+        inv = hps.zinv(Ag.clone())
+    finally:
+        hps.zinv_blocking(-1)
+    prod = _back(hps.zgemm(inv, Ag))
+    for b in range(batch):
+        err = np.max(np.abs(prod[b] - np.eye(n)))
+        assert err < 1e-11, (b, err)
+
+
 @pytest.mark.parametrize("n", [64, 600])
 def test_zinv_equal_magnitudes(n):
     """Every entry of a Fourier matrix has the same magnitude, so every pivot
