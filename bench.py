@@ -126,26 +126,32 @@ def gn_timing(s, k, dirs, th, R, steps, S=160, cg_iters=30):
             "model_rel_err_after_step": err, "start": "half the true coefficients"}
 
 
-GEMM_SOURCE = os.path.join(ROOT, "paper_1608_06871_amd", "csrc", "zgemm.hip")
+# the GEMM kernels and the sources that decide which GEMM calls a step makes
+# (shapes, counts): the stored per-launch traffic holds while none changes
+GEMM_SOURCES = [os.path.join(ROOT, "paper_1608_06871_amd", "csrc", f) for f in ("zgemm.hip", "zinv.hip", "hps.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zgemm_traffic_k80_L64_M256_fp64.json")
 
 
-def source_sha256(path):
+def source_sha256(paths):
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(hashlib.sha256(f.read()).digest())
+    return h.hexdigest()
 
 
 def stored_traffic():
     """HBM bytes per launch of the complex FP64 GEMM class from the committed
-    counter summary, or None when the GEMM source has changed since the
-    counters were taken (or no summary exists)."""
+    counter summary, or None when the GEMM kernels or the code that issues the
+    GEMM calls have changed since the counters were taken (or no summary
+    exists)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("sha256") != source_sha256(GEMM_SOURCE):
+    if t.get("sha256") != source_sha256(GEMM_SOURCES):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -201,7 +207,7 @@ def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_b
     sw = copy_bytes * ncw / (cw_kib * 1024.0)
     launches = max(nf, nw)
     per = (f_kib * 1024.0 * sf + w_kib * 1024.0 * sw) / launches
-    res = {"source": os.path.relpath(GEMM_SOURCE, ROOT), "sha256": source_sha256(GEMM_SOURCE),
+    res = {"sources": [os.path.relpath(p, ROOT) for p in GEMM_SOURCES], "sha256": source_sha256(GEMM_SOURCES),
            "launches": launches, "fetch_kib": f_kib, "write_kib": w_kib,
            "copy_bytes": copy_bytes, "copy_fetch_kib_per_copy": cf_kib / ncf, "copy_write_kib_per_copy": cw_kib / ncw,
            "scale_fetch": sf, "scale_write": sw, "traffic_bytes_per_launch": per}
