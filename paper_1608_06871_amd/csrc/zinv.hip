@@ -308,10 +308,11 @@ constexpr int TRW = TF * BMAX / 64;  // waves of a reduction workgroup
 // lanes holding c and reach the other three lanes of each row by a lane
 // permutation (ds_bpermute).  The outer loop over k is unrolled (static
 // register indices); the inner loop over the four columns of a k block is not.
-template <int SW>
+template <int SW, bool JORDAN>
 __device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, const int (&id)[4], int b,
                                             double2 (*cand)[SW][BMAX], u64 (*ckey)[SW],
-                                            double2 (*cinv)[SW], int* selid) {
+                                            double2 (*cinv)[SW], int* selid, double2* IB, int* sig, int* pos,
+                                            int* info) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, rg = lane & 15, cb = lane >> 4;
   double2 v[4][8];
 #pragma unroll
@@ -330,6 +331,8 @@ __device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, co
   }
   bool out = false;
   int cend = b;  // first column without a pivot row
+  int mycol[4] = {-1, -1, -1, -1};  // selection index of each own row (JORDAN)
+  bool singular = false;
 #define HPS_SEL_POST(I, K)                                                            \
   do {                                                                               \
     _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) cand[par][w][cb + 4 * k_] = v[I][k_]; \
@@ -364,10 +367,15 @@ __device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, co
       break;                                                                         \
     }                                                                                \
     const int p = key_index(bk), pw = p >> 6, pi = (p >> 4) & 3;                     \
-    if (w == pw && rg == (p & 15)) {                                                 \
-      _Pragma("unroll") for (int i = 0; i < 4; ++i) done[i] = done[i] || (i == pi);  \
+    const bool prow = (w == pw && rg == (p & 15)); /* lanes of row p */              \
+    if (prow) {                                                                      \
+      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                \
+        done[i] = done[i] || (i == pi);                                              \
+        if (JORDAN && i == pi) mycol[i] = c;                                         \
+      }                                                                              \
       if (cb == 0) selid[c] = pi == 0 ? id[0] : pi == 1 ? id[1] : pi == 2 ? id[2] : id[3]; \
     }                                                                                \
+    singular = singular || key_zero(bk);                                             \
     const double2 inv = key_zero(bk) ? make_double2(0.0, 0.0) : cinv[par][pw];      \
     const int src = (rg + 16 * cbc) << 2;                                            \
     double2 l[4];                                                                    \
@@ -375,11 +383,24 @@ __device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, co
       const double2 m = cmul(v[i][K], inv);                                          \
       l[i].x = bperm_f64(src, m.x);                                                  \
       l[i].y = bperm_f64(src, m.y);                                                  \
+      if (JORDAN && prow && i == pi) l[i] = make_double2(0.0, 0.0);                  \
     }                                                                                \
     const double2* pr = cand[par][pw];                                               \
-    _Pragma("unroll") for (int k = (K); k < 8; ++k) {                                \
+    _Pragma("unroll") for (int k = (JORDAN ? 0 : (K)); k < 8; ++k) {                 \
       const double2 pv = pr[cb + 4 * k];                                             \
       _Pragma("unroll") for (int i = 0; i < 4; ++i) v[i][k] = cfms(v[i][k], l[i], pv); \
+    }                                                                                \
+    if (JORDAN) {                                                                    \
+      if (prow) {                                                                    \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                \
+          if (i == pi) {                                                             \
+            _Pragma("unroll") for (int k = 0; k < 8; ++k) v[i][k] = cmul(v[i][k], inv); \
+          }                                                                          \
+      }                                                                              \
+      if (mine) {                                                                    \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                \
+          v[i][K] = (prow && i == pi) ? inv : make_double2(-l[i].x, -l[i].y);        \
+      }                                                                              \
     }                                                                                \
   }
   HPS_SEL_STEP(0)
@@ -394,6 +415,24 @@ __device__ __forceinline__ void select_rows(const double2* A, ll lda, int c0, co
 #undef HPS_SEL_POST
   if (out)
     for (int k = cend + t; k < b; k += 64 * SW) selid[k] = -1;
+  if (JORDAN) {
+    // the pivot rows now hold the inverse of the pivot block (rows in
+    // selection order, panel columns): IB[r + col b]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (mycol[i] >= 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int col = cb + 4 * k;
+          if (col < b) IB[mycol[i] + col * b] = v[i][k];
+        }
+        if (cb == 0) {
+          sig[c0 + mycol[i]] = id[i];
+          pos[id[i]] = c0 + mycol[i];
+        }
+      }
+    if ((singular || out) && t == 0) *info = 1;
+  }
   __syncthreads();
 }
 
@@ -414,77 +453,19 @@ __global__ __launch_bounds__(TR) void tp_leaf(const double2* Aall, ll lda, ll sA
     const int r = base + 16 * i;
     id[i] = (r < n && pos_all[bi * n + r] < 0) ? r : -1;
   }
-  select_rows<TLW>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid);
+  select_rows<TLW, false>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid, nullptr, nullptr, nullptr,
+                          nullptr);
   int* out = cand_all + (bi * G + g) * (ll)b;
   if (t < b) out[t] = selid[t];
 }
 
-// Inverse IB (b x b, column-major) of the block of the selected pivot rows
-// sel[0 .. b) in the panel columns, by the whole workgroup (NB threads, a
-// multiple of 32): Gauss-Jordan elimination in the selection order (the
-// tournament ordered the rows by partial pivoting, so no interchanges are
-// needed), in LDS (mb, padded with the identity to BMAX x BMAX).  Thread t
-// owns row t % 32 in the columns t / 32 + (NB / 32) u.  Also records sig /
-// pos of the panel and flags a zero pivot.
-template <int NB>
-__device__ __forceinline__ void block_inverse(const double2* A, ll lda, int c0, int b, const int* sel,
-                                              double2 (*mb)[BMAX + 1], double2* IB, int* sig, int* pos,
-                                              int* info) {
-  constexpr int CS = NB / BMAX, PER = BMAX / CS;  // column stride, entries per thread
-  const int t = threadIdx.x, r = t % BMAX, j0 = t / BMAX;
-  const int pr = (r < b) ? sel[r] : -1;
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int col = j0 + CS * u;
-    mb[r][col] = (r < b && col < b) ? (pr >= 0 ? A[(ll)pr + (ll)(c0 + col) * lda] : make_double2(0.0, 0.0))
-                                    : make_double2(r == col ? 1.0 : 0.0, 0.0);
-  }
-  bool singular = false;
-  for (int c = 0; c < b; ++c) {
-    __syncthreads();
-    const double2 piv = mb[c][c];
-    const double2 f = mb[r][c];
-    double2 pc[PER], own[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      pc[u] = mb[c][j0 + CS * u];
-      own[u] = mb[r][j0 + CS * u];
-    }
-    __syncthreads();
-    const bool zero = (piv.x == 0.0 && piv.y == 0.0);
-    singular |= zero;
-    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(piv);
-    const double2 fi = cmul(f, inv);
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int col = j0 + CS * u;
-      double2 v;
-      if (r == c)
-        v = (col == c) ? inv : cmul(pc[u], inv);
-      else
-        v = (col == c) ? make_double2(-fi.x, -fi.y) : cfms(own[u], fi, pc[u]);
-      mb[r][col] = v;
-    }
-  }
-  __syncthreads();
-  if (r < b) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int col = j0 + CS * u;
-      if (col < b) IB[r + col * b] = mb[r][col];
-    }
-    if (j0 == 0 && pr >= 0) {
-      sig[c0 + r] = pr;
-      pos[pr] = c0 + r;
-    }
-  }
-  if (singular && t == 0) *info = 1;
-}
-
 // Reduction: workgroup g merges candidate sets [TF g, TF g + TF) of Gin
 // (entries -1 mark missing candidates); the sets are taken in order, so ties
-// go to the earlier set.  The last level (one group) also inverts the pivot
-// block of the panel (block_inverse).
+// go to the earlier set.  The last level (FINAL, one group) eliminates with
+// Gauss-Jordan updates instead (every panel column, pivot rows scaled), so
+// that its pivot rows end with the inverse IB of the panel's pivot block,
+// and records sig / pos of the panel.
+template <bool FINAL>
 __global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll lda, ll sA, int n, int c0, int b,
                                                       int Gin, const int* cin_all, int Gout, int* cout_all,
                                                       double2* IB_all, int* sig_all, int* pos_all, int* info) {
@@ -492,7 +473,6 @@ __global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll ld
   __shared__ u64 ckey[2][TRW];
   __shared__ double2 cinv[2][TRW];
   __shared__ int selid[BMAX];
-  __shared__ double2 mb[BMAX][BMAX + 1];
   const ll bi = blockIdx.y;
   const int g = blockIdx.x, t = threadIdx.x;
   // slot j of the group: entry j % b of candidate set TF g + j / b (-1: none)
@@ -502,14 +482,15 @@ __global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll ld
   int id[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) id[i] = (base + 16 * i < nslot) ? cin[base + 16 * i] : -1;
-  select_rows<TRW>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid);
-  if (Gout > 1) {
+  if (FINAL) {
+    select_rows<TRW, true>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid,
+                           IB_all + bi * (ll)BMAX * BMAX, sig_all + bi * n, pos_all + bi * n, info + bi);
+  } else {
+    select_rows<TRW, false>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid, nullptr, nullptr, nullptr,
+                            nullptr);
     int* out = cout_all + (bi * Gout + g) * (ll)b;
     if (t < b) out[t] = selid[t];
-    return;
   }
-  block_inverse<64 * TRW>(Aall + bi * sA, lda, c0, b, selid, mb, IB_all + bi * (ll)BMAX * BMAX, sig_all + bi * n,
-                          pos_all + bi * n, info + bi);
 }
 
 // Panel columns after the block exchange (one launch): rows picked as pivots
@@ -637,8 +618,12 @@ hipError_t tournament_panel(const Inv& v, int c0, int bw) {
     {
       KernelTimer kt(v.st, K_TP_SELECT, 8.0 * Gin * (double)bw * bw * bw * batch,
                      16.0 * Gin * (double)bw * bw * batch);
-      hipLaunchKernelGGL(tp_reduce, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, n, c0, bw,
-                         Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
+      if (Gout > 1)
+        hipLaunchKernelGGL(tp_reduce<false>, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, n,
+                           c0, bw, Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
+      else
+        hipLaunchKernelGGL(tp_reduce<true>, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, n, c0,
+                           bw, Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
     }
     HPS_HIP_TRY(hipGetLastError());
     int* tmp = cin;
