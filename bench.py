@@ -171,35 +171,47 @@ def copy_probe(mib, reps=4):
     print(json.dumps({"copy_bytes": n, "copies": reps + 1}), flush=True)
 
 
-def pmc_sum(csv_path, pattern, counter):
+STEP_MARK = r"k_leaf_assemble"  # first kernel of every benchmark step
+
+
+def pmc_sum(csv_path, pattern, counter, after=None):
     """Sum of `counter` (KiB) and the dispatch count over the kernels whose
-    name matches `pattern` in a rocprofv3 counter_collection.csv."""
+    name matches `pattern` in a rocprofv3 counter_collection.csv; with
+    `after`, only dispatches issued after the last kernel matching it (the
+    last benchmark step, without the warm-up's tuning trials)."""
     import csv
     import re
+    rows = []
+    with open(csv_path) as f:
+        rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+    lo = -1
+    if after:
+        ra = re.compile(after)
+        marks = [int(r["Dispatch_Id"]) for r in rows if ra.search(r["Kernel_Name"])]
+        lo = max(marks) if marks else -1
     tot, disp = 0.0, set()
     rx = re.compile(pattern)
-    with open(csv_path) as f:
-        for r in csv.DictReader(f):
-            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"]):
-                tot += float(r["Counter_Value"])
-                disp.add(r["Dispatch_Id"])
+    for r in rows:
+        if rx.search(r["Kernel_Name"]) and int(r["Dispatch_Id"]) > lo:
+            tot += float(r["Counter_Value"])
+            disp.add(r["Dispatch_Id"])
     return tot, len(disp)
 
 
 def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, out_path):
     """Writes the GEMM-class HBM traffic per launch from four counter runs:
-    FETCH_SIZE and WRITE_SIZE of the benchmark's timed steps and of a plain
-    copy of copy_bytes bytes, which calibrates each counter (bytes per KiB
-    counted)."""
+    FETCH_SIZE and WRITE_SIZE of the benchmark's last step (the dispatches
+    after its leaf assembly) and of a plain copy of copy_bytes bytes, which
+    calibrates each counter (bytes per KiB counted)."""
     # bytes of every kernel of a GEMM call (split-K slices and their
     # reduction included); launches = GEMM calls = main-kernel dispatches
     gemm = r"zgemm_kernel|gemm_kernel<double|k_splitk_reduce"
     main = r"zgemm_kernel|gemm_kernel<double"
     copy = r"copyBuffer"
-    f_kib, _ = pmc_sum(fetch_csv, gemm, "FETCH_SIZE")
-    w_kib, _ = pmc_sum(write_csv, gemm, "WRITE_SIZE")
-    _, nf = pmc_sum(fetch_csv, main, "FETCH_SIZE")
-    _, nw = pmc_sum(write_csv, main, "WRITE_SIZE")
+    f_kib, _ = pmc_sum(fetch_csv, gemm, "FETCH_SIZE", STEP_MARK)
+    w_kib, _ = pmc_sum(write_csv, gemm, "WRITE_SIZE", STEP_MARK)
+    _, nf = pmc_sum(fetch_csv, main, "FETCH_SIZE", STEP_MARK)
+    _, nw = pmc_sum(write_csv, main, "WRITE_SIZE", STEP_MARK)
     cf_kib, ncf = pmc_sum(copy_fetch_csv, copy, "FETCH_SIZE")
     cw_kib, ncw = pmc_sum(copy_write_csv, copy, "WRITE_SIZE")
     # each copy reads and writes copy_bytes once
@@ -314,8 +326,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-gn", action="store_true", help="skip the Gauss-Newton step timing")
     ap.add_argument("--tune", choices=["auto", "on", "off"], default="auto",
-                    help="GEMM tile autotuning in the warm-up pass (auto: on for the batch workload, off for "
-                         "the single-problem workload, whose profiles then hold no tuning trials)")
+                    help="GEMM tile autotuning (every distinct GEMM shape times its candidate tile shapes on its "
+                         "first call, in the untimed warm-up; results are bitwise the same); auto: on whenever "
+                         "there is a warm-up step")
     ap.add_argument("--copy-probe", type=int, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--traffic-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
@@ -335,7 +348,7 @@ def main():
     import torch
     import paper_1608_06871_amd as hps
     import synth
-    tune = args.warmup >= 1 and (args.tune == "on" or (args.tune == "auto" and args.config == "batch32"))
+    tune = args.warmup >= 1 and args.tune in ("on", "auto")
     if tune:
         # every GEMM shape is tuned on its first call, in the untimed warm-up
         hps.gemm_tuning(1)

@@ -66,6 +66,13 @@ size_t zinv_workspace(int n, int batch);
 hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo,
                 ll sO, int batch, void* ws, int* info);
 
+// zinv without the final permutation: `work` is left holding M with
+// inv[c][k] = M[sig[c]][pos[k]] for every matrix of the batch; sig and pos
+// (batch x n ints each, in ws) are returned for the caller's own gathers and
+// stay valid until ws is reused.
+hipError_t zinv_perm(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info,
+                     const int** sig, const int** pos);
+
 // Kernel classes of the optional launch profiler.
 enum KernelKind {
   K_ZGEMM = 0,

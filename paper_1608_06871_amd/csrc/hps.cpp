@@ -353,7 +353,7 @@ void plan_factor_buffers(hps_ctx* c) {
   }
   zws = std::max(zws, zinv_workspace((int)nb, (int)P));
   c->sA.ensure(zb(std::max(nl * n * n, P * nb * nb)));
-  c->sInv.ensure(zb(nl * n * n));
+  c->sInv.ensure(zb(2 * nl * (size_t)g.ne * n));  // leaf stage: Mout column-gathered, then Mout inv
   c->sZws.ensure(zws);
   c->sR0.ensure(zb(rmax));
   c->sR1.ensure(zb(rmax));
@@ -419,22 +419,28 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
 
   // leaf stage (all leaves of all problems)
   CK(leaf_assemble(st, c->dA0.z(), nn, q, k2v, n, mi, c->sA.z(), nl, lpp));
-  CK(zinv(st, n, c->sA.z(), n, nn, c->sInv.z(), n, nn, nl, c->sZws.p, c->sInfo.i()));
-  const double2* inv_edge = c->sInv.z() + (ll)mi * n;  // columns for the edge unknowns
-  CK(gather2d(st, mi, ne, inv_edge, n, nn, nullptr, nullptr, c->dY.z(), mi, (ll)mi * ne, 1.0, nl));
+  // Leaf inverses without their final permutation: M = sA with
+  // inv[c][k] = M[sig[c]][pos[k]] per leaf; the products below read M
+  // through the maps instead of an unpermuted copy.
+  const int* sig = nullptr;
+  const int* pos = nullptr;
+  CK(zinv_perm(st, n, c->sA.z(), n, nn, nl, c->sZws.p, c->sInfo.i(), &sig, &pos));
+  const double2* M = c->sA.z();
+  // Y = inv[0:mi, mi:n] (interior values of the edge-data solutions)
+  CK(gather_perm(st, mi, ne, M, n, nn, 1, sig, n, n, pos + mi, n, n, c->dY.z(), mi, (ll)mi * ne, nl));
+  // Mout inv = (Mout[:, pos] M)[:, pos]: with r = sig[c],
+  // sum_c Mout[o][c] M[sig[c]][pos[k]] = sum_r Mout[o][pos[r]] M[r][pos[k]].
+  // The outgoing map is one per problem (leaf z of problem z / lpp).
+  double2* Mp = c->sInv.z();
+  double2* T = Mp + (ll)nl * ne * n;
+  const ll smo = (ll)ne * n;
+  CK(gather_perm(st, ne, n, c->dMout.z(), ne, P == 1 ? 0 : smo, lpp, nullptr, 0, ne, pos, n, n, Mp, ne, smo, nl));
+  CK(zgemm(st, OP_N, OP_N, ne, n, n, ONE, Mp, ne, smo, M, n, nn, ZERO, T, ne, smo, nl));
   double2* Rc = c->sR0.z();
-  const ll smo = (ll)ne * n;  // one outgoing map per problem, shared by its leaves
-  // a single problem broadcasts its map (stride 0); a batch of problems
-  // indexes it by leaf / leaves-per-problem
-  auto mout_gemm = [&](int N, const double2* B, double2* C) {
-    if (P == 1)
-      CK(zgemm(st, OP_N, OP_N, ne, N, n, ONE, c->dMout.z(), ne, 0, B, n, nn, ZERO, C, ne, (ll)ne * N, nl));
-    else
-      CK(zgemm_div(st, OP_N, OP_N, ne, N, n, ONE, c->dMout.z(), ne, smo, lpp, B, n, nn, 1, ZERO, C, ne,
-                   (ll)ne * N, nl));
-  };
-  mout_gemm(ne, inv_edge, Rc);
-  if (c->o.keep_derivs) mout_gemm(mi, c->sInv.z(), c->dH.z());
+  // R = Mout inv[:, mi:n] (leaf ItI maps), H = Mout inv[:, 0:mi]
+  CK(gather_perm(st, ne, ne, T, ne, smo, 1, nullptr, 0, ne, pos + mi, n, n, Rc, ne, (ll)ne * ne, nl));
+  if (c->o.keep_derivs)
+    CK(gather_perm(st, ne, mi, T, ne, smo, 1, nullptr, 0, ne, pos, n, n, c->dH.z(), ne, (ll)ne * mi, nl));
   if (c->mixed) CK(hipMemcpyAsync(c->dRleaf.p, Rc, zb((size_t)nl * ne * ne), hipMemcpyDeviceToDevice, st));
 
   // merge tree

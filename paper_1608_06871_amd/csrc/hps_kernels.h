@@ -15,6 +15,12 @@ hipError_t leaf_assemble(hipStream_t st, const double2* A0, ll sA0, const double
 hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
                     const int* ridx, const int* cidx, double2* out, ll ldo, ll so, double sc,
                     int batch);
+// out_b(i, j) = in_{b / idiv}(r, c) with per-matrix index maps
+// r = ridx ? ridx[b sri + i] : i and c = cidx ? cidx[b sci + j] : j; an
+// index outside [0, rlim) / [0, clim) gives 0 (maps of a singular matrix).
+hipError_t gather_perm(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si, int idiv,
+                       const int* ridx, ll sri, int rlim, const int* cidx, ll sci, int clim, double2* out, ll ldo,
+                       ll so, int batch);
 // out(ridx[i], j) = in(i, j).
 hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
                         const int* ridx, double2* out, ll ldo, ll so, int batch);

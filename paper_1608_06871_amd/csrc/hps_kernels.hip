@@ -52,6 +52,21 @@ __global__ void k_gather2d(int M, int N, const T2* in, ll ldi, ll si, const int*
   }
 }
 
+__global__ void k_gather_perm(int M, int N, const double2* in, ll ldi, ll si, int idiv, const int* ridx, ll sri,
+                              int rlim, const int* cidx, ll sci, int clim, double2* out, ll ldo, ll so, int batch) {
+  const ll per = (ll)M * N;
+  const ll total = per * batch;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll b = idx / per;
+    const int e = (int)(idx % per);
+    const int i = e % M, j = e / M;
+    const int ri = ridx ? ridx[b * sri + i] : i;
+    const int cj = cidx ? cidx[b * sci + j] : j;
+    const bool ok = (unsigned)ri < (unsigned)rlim && (unsigned)cj < (unsigned)clim;
+    out[b * so + (ll)i + (ll)j * ldo] = ok ? in[(b / idiv) * si + (ll)ri + (ll)cj * ldi] : make_double2(0.0, 0.0);
+  }
+}
+
 template <typename T2>
 __global__ void k_scatter_rows(int M, int N, const T2* in, ll ldi, ll si, const int* ridx, T2* out, ll ldo,
                                ll so, int batch) {
@@ -388,6 +403,17 @@ hipError_t gather2d(hipStream_t st, int M, int N, const float2* in, ll ldi, ll s
   KernelTimer kt(st, K_MOVE, 0.0, 16.0 * (double)M * N * batch);
   hipLaunchKernelGGL((k_gather2d<float2, float>), dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
                      in, ldi, si, ridx, cidx, out, ldo, so, sc, batch);
+  return hipGetLastError();
+}
+
+hipError_t gather_perm(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si, int idiv,
+                       const int* ridx, ll sri, int rlim, const int* cidx, ll sci, int clim, double2* out, ll ldo,
+                       ll so, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (idiv < 1) return hipErrorInvalidValue;
+  KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
+  hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, in, ldi, si, idiv,
+                     ridx, sri, rlim, cidx, sci, clim, out, ldo, so, batch);
   return hipGetLastError();
 }
 

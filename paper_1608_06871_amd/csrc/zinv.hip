@@ -783,12 +783,11 @@ size_t zinv_workspace(int n, int batch) {
   return bytes;
 }
 
-hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO, int batch,
-                void* ws, int* info) {
-  if (n <= 0 || batch <= 0) return hipSuccess;
-  if (batch > 65535) return hipErrorInvalidValue;
+namespace {
+
+// Elimination without the final permutation; v.sig / v.pos left in ws.
+hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info, Inv& v) {
   char* p = (char*)ws;
-  Inv v{};
   v.st = st;
   v.n = n;
   v.batch = batch;
@@ -814,13 +813,34 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
     hipLaunchKernelGGL(gj_init, dim3((n + 255) / 256, batch), dim3(256), 0, st, v.pos, n);
   }
   HPS_HIP_TRY(hipGetLastError());
-  HPS_HIP_TRY(n > NS_MAX_N && use_lookahead(n, batch) ? lookahead_inverse(v) : process_block(v, 0, n));
+  return n > NS_MAX_N && use_lookahead(n, batch) ? lookahead_inverse(v) : process_block(v, 0, n);
+}
+
+}  // namespace
+
+hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO, int batch,
+                void* ws, int* info) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  if (batch > 65535) return hipErrorInvalidValue;
+  Inv v{};
+  HPS_HIP_TRY(zinv_core(st, n, work, lda, sA, batch, ws, info, v));
   {
     KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
     hipLaunchKernelGGL(gj_unpermute, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, v.sig, v.pos,
                        n);
   }
   return hipGetLastError();
+}
+
+hipError_t zinv_perm(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info,
+                     const int** sig, const int** pos) {
+  if (n <= 0 || batch <= 0) return hipErrorInvalidValue;
+  if (batch > 65535) return hipErrorInvalidValue;
+  Inv v{};
+  HPS_HIP_TRY(zinv_core(st, n, work, lda, sA, batch, ws, info, v));
+  *sig = v.sig;
+  *pos = v.pos;
+  return hipSuccess;
 }
 
 }  // namespace hps
