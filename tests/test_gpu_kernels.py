@@ -156,6 +156,27 @@ def test_zinv_blockings_agree(n, batch, mode):
         assert err < 1e-11, (b, err)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_zinv_reports_singular_tournament(mode):
+    """A zero column in an order-700 matrix (tournament path; the zero pivot is
+    met in the last reduction of its panel) is reported as singular by both
+    column blockings."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    n = 700
+    print(f"zinv singular n={n} blocking={mode}", flush=True)
+    rng = np.random.default_rng(11)
+    A = _rand(rng, (1, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    A[:, :, 37] = 0.0
+    hps.zinv_blocking(mode)
+    try:
+        with pytest.raises(hps.HpsError) as e:
+            hps.zinv(_colmajor(torch, A))
+    finally:
+        hps.zinv_blocking(-1)
+    assert e.value.code == hps.HPS_ESINGULAR
+
+
 @pytest.mark.parametrize("n", [64, 600])
 def test_zinv_equal_magnitudes(n):
     """Every entry of a Fourier matrix has the same magnitude, so every pivot
