@@ -652,22 +652,35 @@ hipError_t block_update(const Inv& v, int s0, int s1, int d0, int d1) {
                        v.n, s0, s1, v.batch);
 }
 
-// Second stream per caller stream for the look-ahead updates (created on
-// first use, kept for the process lifetime like the GEMM workspaces).
+// Second stream for the look-ahead updates of a caller's stream: caller
+// streams are assigned round-robin to a fixed pool of NSIDE non-blocking
+// streams (created on first use, kept for the process lifetime like the GEMM
+// workspaces), so that callers which keep creating streams do not grow the
+// number of streams.  Callers sharing a side stream only serialise their
+// updates there: each waits on its own events, recorded after its own work,
+// and each event a side stream waits for depends only on work enqueued there
+// earlier, so sharing cannot deadlock.  Only rank-32 updates run on these
+// streams (inner dimension <= 32), so they never take the GEMM's per-stream
+// split-K workspace, which is not meant for concurrent callers.
+constexpr int NSIDE = 8;
 std::mutex g_side_mu;
-std::vector<std::pair<hipStream_t, hipStream_t>> g_side;
+hipStream_t g_side_pool[NSIDE] = {};
+std::vector<std::pair<hipStream_t, int>> g_side;  // caller stream -> pool slot
+unsigned g_side_next = 0;
 
 hipError_t side_stream(hipStream_t st, hipStream_t* out) {
   std::lock_guard<std::mutex> lk(g_side_mu);
   for (auto& e : g_side)
     if (e.first == st) {
-      *out = e.second;
+      *out = g_side_pool[e.second];
       return hipSuccess;
     }
-  hipStream_t x = nullptr;
-  HPS_HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-  g_side.push_back({st, x});
-  *out = x;
+  const int slot = (int)(g_side_next % NSIDE);
+  if (!g_side_pool[slot]) HPS_HIP_TRY(hipStreamCreateWithFlags(&g_side_pool[slot], hipStreamNonBlocking));
+  ++g_side_next;
+  if (g_side.size() >= 256) g_side.clear();  // associations only; the pool streams stay
+  g_side.push_back({st, slot});
+  *out = g_side_pool[slot];
   return hipSuccess;
 }
 
