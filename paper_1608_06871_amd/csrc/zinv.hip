@@ -465,13 +465,15 @@ __global__ __launch_bounds__(TR) void tp_leaf(const double2* Aall, ll lda, ll sA
 // Gauss-Jordan updates instead (every panel column, pivot rows scaled), so
 // that its pivot rows end with the inverse IB of the panel's pivot block,
 // and records sig / pos of the panel.
-template <bool FINAL>
-__global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll lda, ll sA, int n, int c0, int b,
-                                                      int Gin, const int* cin_all, int Gout, int* cout_all,
-                                                      double2* IB_all, int* sig_all, int* pos_all, int* info) {
-  __shared__ double2 cand[2][TRW][BMAX];
-  __shared__ u64 ckey[2][TRW];
-  __shared__ double2 cinv[2][TRW];
+// RW waves (64 RW candidate slots; the last level takes as few waves as its
+// candidates need, so that no idle wave joins the per-column barriers).
+template <bool FINAL, int RW>
+__global__ __launch_bounds__(64 * RW) void tp_reduce(const double2* Aall, ll lda, ll sA, int n, int c0, int b,
+                                                     int Gin, const int* cin_all, int Gout, int* cout_all,
+                                                     double2* IB_all, int* sig_all, int* pos_all, int* info) {
+  __shared__ double2 cand[2][RW][BMAX];
+  __shared__ u64 ckey[2][RW];
+  __shared__ double2 cinv[2][RW];
   __shared__ int selid[BMAX];
   const ll bi = blockIdx.y;
   const int g = blockIdx.x, t = threadIdx.x;
@@ -483,11 +485,11 @@ __global__ __launch_bounds__(64 * TRW) void tp_reduce(const double2* Aall, ll ld
 #pragma unroll
   for (int i = 0; i < 4; ++i) id[i] = (base + 16 * i < nslot) ? cin[base + 16 * i] : -1;
   if (FINAL) {
-    select_rows<TRW, true>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid,
-                           IB_all + bi * (ll)BMAX * BMAX, sig_all + bi * n, pos_all + bi * n, info + bi);
+    select_rows<RW, true>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid,
+                          IB_all + bi * (ll)BMAX * BMAX, sig_all + bi * n, pos_all + bi * n, info + bi);
   } else {
-    select_rows<TRW, false>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid, nullptr, nullptr, nullptr,
-                            nullptr);
+    select_rows<RW, false>(Aall + bi * sA, lda, c0, id, b, cand, ckey, cinv, selid, nullptr, nullptr, nullptr,
+                           nullptr);
     int* out = cout_all + (bi * Gout + g) * (ll)b;
     if (t < b) out[t] = selid[t];
   }
@@ -618,12 +620,19 @@ hipError_t tournament_panel(const Inv& v, int c0, int bw) {
     {
       KernelTimer kt(v.st, K_TP_SELECT, 8.0 * Gin * (double)bw * bw * bw * batch,
                      16.0 * Gin * (double)bw * bw * batch);
+      const int rows = Gin * bw;  // candidate slots of the last level
       if (Gout > 1)
-        hipLaunchKernelGGL(tp_reduce<false>, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, n,
-                           c0, bw, Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
-      else
-        hipLaunchKernelGGL(tp_reduce<true>, dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, n, c0,
+        hipLaunchKernelGGL((tp_reduce<false, TRW>), dim3(Gout, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda,
+                           v.sA, n, c0, bw, Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
+      else if (rows <= 64)
+        hipLaunchKernelGGL((tp_reduce<true, 1>), dim3(1, batch), dim3(64), 0, v.st, v.work, v.lda, v.sA, n, c0, bw,
+                           Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
+      else if (rows <= 128)
+        hipLaunchKernelGGL((tp_reduce<true, 2>), dim3(1, batch), dim3(128), 0, v.st, v.work, v.lda, v.sA, n, c0,
                            bw, Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
+      else
+        hipLaunchKernelGGL((tp_reduce<true, TRW>), dim3(1, batch), dim3(64 * TRW), 0, v.st, v.work, v.lda, v.sA, n,
+                           c0, bw, Gin, cin, Gout, cout, v.IB, v.sig, v.pos, v.info);
     }
     HPS_HIP_TRY(hipGetLastError());
     int* tmp = cin;
