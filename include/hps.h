@@ -73,7 +73,8 @@ typedef enum {
   HPS_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
   HPS_ESTATE = -4,     /* call order violated (solve before factor, ...) */
   HPS_ESINGULAR = -5,  /* a zero pivot was met in a factorisation */
-  HPS_ENOCONV = -6     /* HPS_MIXED: refinement stopped above refine_tol (results kept) */
+  HPS_ENOCONV = -6,    /* HPS_MIXED: refinement stopped above refine_tol (results kept) */
+  HPS_ENONFINITE = -7  /* a NaN or infinity in the contrast or in the factorisation */
 } hps_status;
 
 /* HPS_FP64: everything in complex128.
@@ -144,8 +145,10 @@ hps_status hps_set_wavenumbers(hps_ctx* ctx, const double* k_host);
 /* Factorises the discrete interior + exterior problem for the real contrast
  * q_nodes (device, npde doubles, PDE-node order) at wavenumber k > 0: leaf
  * impedance maps, the merge tree, and the inverse of the top (boundary)
- * system.  Synchronises the stream once to read the pivot flags; returns
- * HPS_ESINGULAR if a zero pivot occurred.  Invalidates earlier solves. */
+ * system.  Synchronises the stream once to read the pivot and finiteness
+ * flags; returns HPS_ENONFINITE if q holds a NaN or infinity (checked on the
+ * device) or the top inverse came out non-finite, HPS_ESINGULAR if a zero
+ * pivot occurred.  Invalidates earlier solves. */
 hps_status hps_factor(hps_ctx* ctx, const double* q_nodes, double k);
 
 /* hps_factor for a batch: problem b has contrast q_nodes[b][.] and
@@ -224,6 +227,7 @@ typedef struct hps_stats {
   int64_t device_bytes;   /* device memory held by the context */
   int ndir;               /* directions of the last solve */
   int singular;           /* 1 if the last factorisation met a zero pivot */
+  int nonfinite;          /* last factorisation: bit 0 non-finite contrast, bit 1 non-finite top inverse */
   int refine_iters;       /* HPS_MIXED: corrections made by the last solve */
   double refine_residual; /* HPS_MIXED: its final relative interface residual */
 } hps_stats;

@@ -15,9 +15,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhps.so")
 _LIB = None
 
-HPS_OK, HPS_EINVAL, HPS_ENOMEM, HPS_EDEVICE, HPS_ESTATE, HPS_ESINGULAR, HPS_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+HPS_OK, HPS_EINVAL, HPS_ENOMEM, HPS_EDEVICE, HPS_ESTATE, HPS_ESINGULAR, HPS_ENOCONV, HPS_ENONFINITE = \
+    0, -1, -2, -3, -4, -5, -6, -7
 _NAMES = {0: "HPS_OK", -1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESTATE",
-          -5: "HPS_ESINGULAR", -6: "HPS_ENOCONV"}
+          -5: "HPS_ESINGULAR", -6: "HPS_ENOCONV", -7: "HPS_ENONFINITE"}
 
 
 class HpsError(RuntimeError):
@@ -40,7 +41,7 @@ class Stats(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("t_far_field_ms", ctypes.c_double),
                 ("t_jvp_ms", ctypes.c_double), ("t_vjp_ms", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int),
-                ("refine_iters", ctypes.c_int), ("refine_residual", ctypes.c_double)]
+                ("nonfinite", ctypes.c_int), ("refine_iters", ctypes.c_int), ("refine_residual", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):

@@ -6,7 +6,8 @@ factors (Theorem 2 in discrete form), which for a real input and a complex
 output returns Re(J^H g) -- PyTorch's convention for real-to-complex maps.
 The solver keeps one factorisation; if it has been refactored since this
 forward (e.g. by another forward), backward first restores the forward's
-state (factor + solve + far field again) before the adjoint solve."""
+state (factor + solve again); it always re-selects the forward's measurement
+set (theta, R) before the adjoint solve."""
 import torch
 
 
@@ -24,11 +25,14 @@ class FarField(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u):
         s = ctx.solver
+        q, k, dirs, thetas, R = ctx.args
         if s.generation != ctx.generation:
-            q, k, dirs, thetas, R = ctx.args
             s.factor(q, k)
             s.solve(dirs)
-            s.far_field(thetas, R)
+        # the adjoint uses the measurement set of the last far-field call:
+        # re-select this forward's (theta, R) in case another call changed it
+        # (no host work when it is unchanged)
+        s.far_field(thetas, R)
         g = s.vjp(grad_u.contiguous())
         return g, None, None, None, None, None
 

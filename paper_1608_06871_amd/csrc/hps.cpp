@@ -129,6 +129,7 @@ struct hps_ctx {
   // factorisation
   bool factored = false;
   int singular = 0;
+  int nonfinite = 0;  // last factorisation: 1 non-finite contrast, 2 non-finite top inverse
   DBuf dY, dH, dRroot, dZinv;
   // conjugate transposes of the top operators for the adjoint (read as plain
   // column-major operands, which the matrix cores stream faster)
@@ -364,7 +365,7 @@ void plan_factor_buffers(hps_ctx* c) {
   c->sVin.ensure(zb(v));
   c->sV.ensure(zb(v));
   c->sTmp.ensure(zb(v));
-  c->sInfo.ensure(sizeof(int) * std::max<size_t>(nl, P));
+  c->sInfo.ensure(sizeof(int) * (std::max<size_t>(nl, P) + 1));
   c->dY.ensure(zb(nl * mi * ne));
   if (c->o.keep_derivs) c->dH.ensure(zb(nl * ne * mi));
   c->dRroot.ensure(zb(P * nb * nb));
@@ -415,7 +416,11 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   c->solved = false;
   mark(c, 0, 0);
   const int ninfo = std::max(nl, P);
-  CK(hipMemsetAsync(c->sInfo.p, 0, sizeof(int) * ninfo, st));
+  // info[0 .. ninfo): zero pivots per matrix; info[ninfo]: non-finite flags
+  // (1: the contrast, 2: the top inverse)
+  int* nonfinite = c->sInfo.i() + ninfo;
+  CK(hipMemsetAsync(c->sInfo.p, 0, sizeof(int) * (ninfo + 1), st));
+  CK(flag_nonfinite(st, q, (ll)P * g.nleaf * mi, 1, nonfinite));
 
   // leaf stage (all leaves of all problems)
   CK(leaf_assemble(st, c->dA0.z(), nn, q, k2v, n, mi, c->sA.z(), nl, lpp));
@@ -532,13 +537,17 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
     CK(conj_transpose(st, nb, c->dRroot.z(), nb, sbb, c->dRrootH.z(), nb, sbb, P));
     CK(conj_transpose(st, nb, c->dZinv.z(), nb, sbb, c->dZinvH.z(), nb, sbb, P));
   }
+  CK(flag_nonfinite(st, (const double*)c->dZinv.p, 2 * (ll)P * sbb, 2, nonfinite));
   mark(c, 0, 1);
-  std::vector<int> info(ninfo);
-  CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * ninfo, hipMemcpyDeviceToHost, st));
+  std::vector<int> info(ninfo + 1);
+  CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * (ninfo + 1), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   c->singular = 0;
-  for (int v : info) c->singular |= (v != 0);
+  for (int i = 0; i < ninfo; ++i) c->singular |= (info[i] != 0);
+  c->nonfinite = info[ninfo];
+  if (c->nonfinite & 1) throw HpsError{HPS_ENONFINITE, "the contrast q holds a NaN or infinite value"};
   if (c->singular) throw HpsError{HPS_ESINGULAR, "zero pivot in the factorisation"};
+  if (c->nonfinite) throw HpsError{HPS_ENONFINITE, "the factorisation produced a NaN or infinite value"};
   c->factored = true;
 }
 
@@ -1363,6 +1372,7 @@ hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
     out->device_bytes = device_bytes(c);
     out->ndir = c->ndir;
     out->singular = c->singular;
+    out->nonfinite = c->nonfinite;
     out->refine_iters = c->refine_iters;
     out->refine_residual = c->refine_res;
   });

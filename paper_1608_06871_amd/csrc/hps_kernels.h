@@ -71,6 +71,8 @@ hipError_t real_to_complex(hipStream_t st, const double* x, ll n, double2* y);
 hipError_t complex_real_part(hipStream_t st, const double2* x, ll n, double* y);
 // *out = sum x[i] y[i] (deterministic two-stage reduction; partial holds 256 doubles).
 hipError_t dot(hipStream_t st, const double* x, const double* y, ll n, double* partial, double* out);
+// *flag |= bit when any of x[0 .. n) is NaN or infinite.
+hipError_t flag_nonfinite(hipStream_t st, const double* x, ll n, int bit, int* flag);
 // y = a x + b y
 hipError_t axpby(hipStream_t st, double a, const double* x, double b, double* y, ll n);
 // z = x - y (complex)

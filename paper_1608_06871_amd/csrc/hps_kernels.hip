@@ -356,6 +356,23 @@ __global__ void k_zsub(const double2* x, const double2* y, double2* z, ll n) {
 
 constexpr int DOT_BLOCKS = 256;
 
+// *flag |= bit if any of the n doubles of x is NaN or infinite (one atomic
+// per workgroup that saw one).
+__global__ __launch_bounds__(256) void k_flag_nonfinite(const double* x, ll n, int bit, int* flag) {
+  int bad = 0;
+  for (ll i = (ll)blockIdx.x * 256 + threadIdx.x; i < n; i += (ll)gridDim.x * 256) bad |= !isfinite(x[i]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, bit);
+}
+
+hipError_t flag_nonfinite(hipStream_t st, const double* x, ll n, int bit, int* flag) {
+  if (n <= 0) return hipSuccess;
+  ll blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  KernelTimer kt(st, K_POINT, 0.0, 8.0 * n);
+  hipLaunchKernelGGL(k_flag_nonfinite, dim3((unsigned)blocks), dim3(256), 0, st, x, n, bit, flag);
+  return hipGetLastError();
+}
+
 hipError_t dot(hipStream_t st, const double* x, const double* y, ll n, double* partial, double* out) {
   {
     KernelTimer kt(st, K_POINT, 2.0 * n, 16.0 * n);

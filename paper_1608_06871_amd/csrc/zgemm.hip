@@ -618,14 +618,38 @@ std::map<TuneKey, int> g_tuned;
 std::atomic<int> g_tune_mode{0};
 double g_tune_seconds = 0.0;
 
-// Times every candidate on the call's own operands (the output span is saved
+// Copies the M x N output block of every batch entry of a strided C to a
+// packed buffer (dir 0) or back (dir 1).  Only those elements: other
+// columns of the same arrays may be written concurrently by another stream
+// (the look-ahead updates of the inverse).
+__global__ void k_block_copy(double2* C, ll ldc, ll sC, int M, int N, int batch, double2* buf, int dir) {
+  const ll per = (ll)M * N, total = per * batch;
+  for (ll e = (ll)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (ll)gridDim.x * blockDim.x) {
+    const ll b = e / per, r = e % per, i = r % M, j = r / M;
+    double2* c = C + b * sC + j * ldc + i;
+    if (dir == 0)
+      buf[e] = *c;
+    else
+      *c = buf[e];
+  }
+}
+
+hipError_t block_copy(hipStream_t st, const Args& a, int batch, double2* buf, int dir) {
+  const ll total = (ll)a.M * a.N * batch;
+  ll blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_block_copy, dim3((unsigned)blocks), dim3(256), 0, st, a.C, a.ldc, a.sC, a.M, a.N, batch, buf,
+                     dir);
+  return hipGetLastError();
+}
+
+// Times every candidate on the call's own operands (the output block is saved
 // first and restored before each trial and at the end) and returns the index
 // of the fastest in VARIANTS.  Synchronises the stream.
 hipError_t tune_shape(hipStream_t st, const Args& a, int batch, int* best) {
   const auto t0 = std::chrono::steady_clock::now();
   const bool rb = (a.beta.x != 0.0 || a.beta.y != 0.0);
-  const ll span = (ll)(batch - 1) * a.sC + (ll)(a.N - 1) * a.ldc + a.M;
-  const size_t bytes = (size_t)span * sizeof(double2);
+  const size_t bytes = (size_t)a.M * a.N * batch * sizeof(double2);
   void* save = nullptr;
   hipEvent_t ev[2 * NCAND];
   for (auto& e : ev) e = nullptr;
@@ -635,14 +659,14 @@ hipError_t tune_shape(hipStream_t st, const Args& a, int batch, int* best) {
   do {
     if (rb) {
       if ((err = hipMalloc(&save, bytes)) != hipSuccess) break;
-      if ((err = hipMemcpyAsync(save, a.C, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+      if ((err = block_copy(st, a, batch, (double2*)save, 0)) != hipSuccess) break;
     }
     for (auto& e : ev)
       if ((err = hipEventCreate(&e)) != hipSuccess) break;
     if (err != hipSuccess) break;
     for (int round = 0; round < 3 && err == hipSuccess; ++round) {
       for (int i = 0; i < NCAND && err == hipSuccess; ++i) {
-        if (rb && (err = hipMemcpyAsync(a.C, save, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+        if (rb && (err = block_copy(st, a, batch, (double2*)save, 1)) != hipSuccess) break;
         if ((err = hipEventRecord(ev[2 * i], st)) != hipSuccess) break;
         if ((err = VARIANTS[TUNE_CAND[i]](st, a, batch)) != hipSuccess) break;
         err = hipEventRecord(ev[2 * i + 1], st);
@@ -655,7 +679,7 @@ hipError_t tune_shape(hipStream_t st, const Args& a, int batch, int* best) {
         if (x < ms[i]) ms[i] = x;
       }
     }
-    if (err == hipSuccess && rb) err = hipMemcpyAsync(a.C, save, bytes, hipMemcpyDeviceToDevice, st);
+    if (err == hipSuccess && rb) err = block_copy(st, a, batch, (double2*)save, 1);
     if (err == hipSuccess) err = hipStreamSynchronize(st);
   } while (0);
   for (auto& e : ev)

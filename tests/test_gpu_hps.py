@@ -121,3 +121,25 @@ def test_call_order_errors():
     with pytest.raises(hps.HpsError) as e:
         s.factor(q, -1.0)
     assert e.value.code == hps.HPS_EINVAL
+
+
+def test_nonfinite_contrast_is_reported():
+    """A NaN or an infinity in q is found on the device during the factor
+    (no extra synchronisation) and reported as HPS_ENONFINITE; the context
+    stays usable for the next, finite contrast."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    L, k, M, P = 2, 5.0, 4, 16
+    prob, q, th = _case(L, k, M, P, 3)
+    s = _solver(L)
+    for bad in (np.nan, np.inf):
+        qb = q.copy()
+        qb[17] = bad
+        with pytest.raises(hps.HpsError) as e:
+            s.factor(torch.from_numpy(qb).cuda(), k)
+        assert e.value.code == hps.HPS_ENONFINITE
+        assert s.stats()["nonfinite"] & 1
+    s.factor(torch.from_numpy(q).cuda(), k)
+    assert s.stats()["nonfinite"] == 0
+    s.solve(directions(M))
+    assert _rel(s.far_field(th, 2.0).cpu().numpy(), prob.far_field()) < 1e-9

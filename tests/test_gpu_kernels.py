@@ -288,3 +288,28 @@ def test_autotuned_solver_gives_identical_results():
         hps.gemm_tuning(0, -1)
     assert hps.gemm_tuning_info()["shapes_tuned"] > 0
     assert torch.equal(tuned, ref)
+
+
+def test_autotuned_lookahead_inverse_is_bitwise_identical():
+    """Autotuning inside the look-ahead inverse (order 1100, two matrices):
+    the two streams update disjoint column ranges of the same matrices, and
+    each tuning call saves and restores only its own output block, so the
+    result equals the untuned one bit for bit."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    n, batch = 1100, 2
+    print(f"zinv tuned look-ahead n={n} batch={batch}", flush=True)
+    rng = np.random.default_rng(1234)
+    A = _rand(rng, (batch, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    Ag = _colmajor(torch, A)
+    hps.zinv_blocking(1)
+    try:
+        ref = hps.zinv(Ag.clone())
+        hps.gemm_tuning(1, -1)
+        tuned = hps.zinv(Ag.clone())
+        again = hps.zinv(Ag.clone())  # tuned shapes reused
+    finally:
+        hps.gemm_tuning(0, -1)
+        hps.zinv_blocking(-1)
+    torch.cuda.synchronize()
+    assert torch.equal(tuned, ref) and torch.equal(again, ref)

@@ -50,3 +50,14 @@ def test_default_opts_and_invalid_create_on_cpu():
     assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
     bad.p, bad.x1 = 16, 3.0  # not square
     assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
+
+
+def test_status_codes_match_the_header():
+    """The binding's status constants equal the header's enum values."""
+    import paper_1608_06871_amd as hps
+    text = open(HEADER).read()
+    enum = dict((n, int(v)) for n, v in re.findall(r"\b(HPS_E[A-Z]+|HPS_OK)\s*=\s*(-?\d+)", text))
+    assert enum["HPS_OK"] == 0
+    for name, val in enum.items():
+        assert getattr(hps, name) == val, name
+        assert hps._NAMES[val] == name
