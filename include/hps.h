@@ -260,6 +260,26 @@ hps_status hps_zgemm(void* stream, int opA, int opB, int M, int N, int K, const 
  * pivot.  Allocates its own workspace. */
 hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
 
+/* hps_zinv without any device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the workspace lives in the library's static device scratch
+ * array of HPS_NOALLOC_SCRATCH_BYTES (one per GPU, held until the process
+ * ends); no GEMM autotuning or split-K runs inside the call.
+ *   Limits: n <= 512, and the workspace (about batch * (n^2/4 + n) * 16
+ *   bytes) must fit the array, else HPS_EINVAL before any launch; e.g.
+ *   n = 512: batch <= 63, n = 448: <= 83, n = 252: <= 262, n = 128: <= 1008.
+ *   A: destroyed; inv: the inverses (both device, column-major, leading
+ *   dimension n, contiguous batch), as hps_zinv.
+ *   status_dev == NULL: synchronous, returns HPS_ESINGULAR on a zero pivot;
+ *   status_dev != NULL (device, one int): enqueued on `stream` only, the int
+ *   receives 1 on a zero pivot, else 0.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (different streams, or host threads) race and must be
+ * serialised by the caller.  The array keeps the last call's contents; each
+ * call clears what it needs itself. */
+#define HPS_NOALLOC_SCRATCH_BYTES (64LL << 20)
+hps_status hps_zinv_noalloc(void* stream, int n, int batch, double* A, double* inv, int* status_dev);
+
 /* Column blocking of the inverses of order above 512 (hps_zinv and the
  * factorisation's W and Z inverses), process-wide; a performance choice, both
  * give the inverse to rounding (the merges and the top of the Section 2

@@ -76,6 +76,7 @@ SIGNATURES = [
     ("hps_boundary_operators", _I, [ctypes.POINTER(Opts), _D, _P, _P, _P]),
     ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
     ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
+    ("hps_zinv_noalloc", _I, [_P, _I, _I, _P, _P, _P]),
     ("hps_gemm_tuning", _I, [_I, _I]),
     ("hps_zinv_blocking", _I, [_I]),
     ("hps_gemm_tuning_info", _I, [_P, _P, _P]),
@@ -353,6 +354,23 @@ def zinv(A, stream=None):
     rc = lib().hps_zinv(st, n, batch, _dev(A, torch.complex128), _dev(inv, torch.complex128))
     if rc != HPS_OK:
         raise HpsError(rc, "hps_zinv")
+    return inv
+
+
+def zinv_noalloc(A, inv=None, status=None, stream=None):
+    """hps_zinv_noalloc: the inverse of [batch, n, n] complex128 GPU matrices
+    (A destroyed) with the library's static scratch array as workspace.
+    status: optional int32 GPU tensor of one element (asynchronous call);
+    without it the call is synchronous and raises on a zero pivot."""
+    torch = _torch()
+    batch, n, _ = A.shape
+    if inv is None:
+        inv = torch.empty_like(A)
+    sp = _dev(status, torch.int32, 1, "status") if status is not None else None
+    st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    rc = lib().hps_zinv_noalloc(st, n, batch, _dev(A, torch.complex128), _dev(inv, torch.complex128), sp)
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_zinv_noalloc")
     return inv
 
 

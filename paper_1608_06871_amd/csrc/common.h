@@ -73,6 +73,36 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
 hipError_t zinv_perm(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info,
                      const int** sig, const int** pos);
 
+// While a NoAllocScope lives on a thread, the library calls made from that
+// thread allocate no device memory and create no HIP objects: GEMMs take the
+// fixed tile rules (no autotuning trials, which save their output in a new
+// buffer) and never split K (the split-K workspace is allocated on first use
+// per stream), and the launch profiler records nothing (it creates events).
+class NoAllocScope {
+ public:
+  NoAllocScope();
+  ~NoAllocScope();
+  NoAllocScope(const NoAllocScope&) = delete;
+  NoAllocScope& operator=(const NoAllocScope&) = delete;
+
+ private:
+  bool prev_;
+};
+bool no_alloc_active();
+
+// Allocation-free batched inverse for n <= 512 with its workspace in the
+// library's static device scratch array (one per GPU, kept until the process
+// ends).  Enqueued on st; status_dev (device, one int) receives 1 if a zero
+// pivot was met, else 0.  Returns hipErrorInvalidValue when the workspace
+// does not fit the array (see zinv_noalloc_bytes).
+hipError_t zinv_noalloc(hipStream_t st, int n, double2* A, double2* inv, int batch, int* status_dev);
+// Scratch bytes zinv_noalloc needs, and the size of the scratch array.
+size_t zinv_noalloc_bytes(int n, int batch);
+size_t zinv_noalloc_capacity();
+// Device address of this GPU's scratch array's status slot (for the host
+// to read a synchronous call's status); resolved once per device.
+hipError_t zinv_noalloc_status_slot(int** out);
+
 // Kernel classes of the optional launch profiler.
 enum KernelKind {
   K_ZGEMM = 0,

@@ -1470,4 +1470,21 @@ hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv) {
   return s;
 }
 
+hps_status hps_zinv_noalloc(void* stream, int n, int batch, double* A, double* inv, int* status_dev) {
+  if (n < 0 || batch < 0 || batch > 65535) return HPS_EINVAL;
+  if (n == 0 || batch == 0) return HPS_OK;
+  if (!A || !inv) return HPS_EINVAL;
+  if (n > 512 || zinv_noalloc_bytes(n, batch) > zinv_noalloc_capacity()) return HPS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (zinv_noalloc(st, n, (double2*)A, (double2*)inv, batch, status_dev) != hipSuccess) return HPS_EDEVICE;
+  if (status_dev) return HPS_OK;
+  int* slot = nullptr;
+  int h = 0;
+  if (zinv_noalloc_status_slot(&slot) != hipSuccess ||
+      hipMemcpyAsync(&h, slot, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return HPS_EDEVICE;
+  return h ? HPS_ESINGULAR : HPS_OK;
+}
+
 }  // extern "C"

@@ -42,7 +42,7 @@ hipEvent_t take() {
 KernelTimer::KernelTimer(hipStream_t st, int kind, double flops, double bytes) {
   st_ = st;
   idx_ = -1;
-  if (!g_on.load(std::memory_order_relaxed)) return;
+  if (!g_on.load(std::memory_order_relaxed) || no_alloc_active()) return;
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t a = take(), b = take();
   if (!a || !b) return;

@@ -583,6 +583,8 @@ void trace_call(const Args& a, int batch, int variant) {
 
 std::atomic<int> g_force{-2};  // -2: not read from the environment yet
 
+thread_local bool g_noalloc = false;  // NoAllocScope active on this thread
+
 int forced_variant() {
   int v = g_force.load();
   if (v == -2) {
@@ -708,6 +710,10 @@ int rule_variant(int M, int N, int K) {
 
 }  // namespace
 
+NoAllocScope::NoAllocScope() : prev_(g_noalloc) { g_noalloc = true; }
+NoAllocScope::~NoAllocScope() { g_noalloc = prev_; }
+bool no_alloc_active() { return g_noalloc; }
+
 void gemm_set_tuning(int mode, int force) {
   g_tune_mode.store(mode);
   forced_variant();
@@ -772,7 +778,7 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
     trace_call(a, batch, fv);
     return VARIANTS[fv](st, a, batch);
   }
-  const int splits = choose_splits(M, N, a.K, batch);
+  const int splits = g_noalloc ? 1 : choose_splits(M, N, a.K, batch);
   if (splits > 1) {
     trace_call(a, batch, -1);
     // partial products of K slices into the workspace, then one reduction
@@ -797,7 +803,7 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
                        N, alpha, beta, C, ldc, sC, rpos, srp, plo, phi, a.rmap, a.rsplit, a.rpart, batch);
     return hipGetLastError();
   }
-  if (g_tune_mode.load() == 1 && !(rmap && rb)) {
+  if (g_tune_mode.load() == 1 && !(rmap && rb) && !g_noalloc) {
     const TuneKey key{M, N, a.K, batch, opA, opB, rb ? 1 : 0, (rpos ? 1 : 0) + (rmap ? 2 : 0), lda, ldb, ldc,
                       sA, sB, sC};
     int v = -1;

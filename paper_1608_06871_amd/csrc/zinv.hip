@@ -854,6 +854,88 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free inverse (for callers that cannot allocate device memory).
+//
+// Its workspace lives in `scratch`, a static device array of fixed size.  In
+// host code the array's name is only a stand-in: its device address is
+// resolved once per GPU with hipGetSymbolAddress (with that GPU current) and
+// only that address is ever handed to kernels.  Every GPU holds its own copy
+// until the process ends.  Layout: [status slot | per-matrix pivot flags |
+// zinv workspace], each 256-byte aligned.  Calls that overlap on one GPU
+// share the array and race; the pivot flags and the status are cleared by a
+// fill kernel at the start of every call.
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_N = NS_MAX_N;  // register-panel path only: no look-ahead streams, no split K
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_scr_mu;
+unsigned char* g_scr_ptr[NOALLOC_MAX_DEVICES] = {};  // device address of `scratch`, per GPU
+
+hipError_t scratch_address(unsigned char** out) {
+  int dev = 0;
+  HPS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  if (!g_scr_ptr[dev]) {
+    void* p = nullptr;
+    HPS_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return hipErrorInvalidSymbol;
+    g_scr_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scr_ptr[dev];
+  return hipSuccess;
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+// *flag |= (info[b] != 0) over the batch (flag cleared beforehand).
+__global__ void k_or_flags(const int* info, int n, int* flag) {
+  int any = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) any |= (info[i] != 0);
+  if (any) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+size_t zinv_noalloc_capacity() { return NOALLOC_BYTES; }
+
+size_t zinv_noalloc_bytes(int n, int batch) {
+  return 256 + align256((size_t)batch * sizeof(int)) + zinv_workspace(n, batch);
+}
+
+hipError_t zinv_noalloc_status_slot(int** out) {
+  unsigned char* base = nullptr;
+  HPS_HIP_TRY(scratch_address(&base));
+  *out = (int*)base;
+  return hipSuccess;
+}
+
+hipError_t zinv_noalloc(hipStream_t st, int n, double2* A, double2* inv, int batch, int* status_dev) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  if (n > NOALLOC_MAX_N || batch > 65535 || zinv_noalloc_bytes(n, batch) > NOALLOC_BYTES)
+    return hipErrorInvalidValue;
+  unsigned char* base = nullptr;
+  HPS_HIP_TRY(scratch_address(&base));
+  int* status = status_dev ? status_dev : (int*)base;
+  int* info = (int*)(base + 256);
+  void* ws = base + 256 + align256((size_t)batch * sizeof(int));
+  NoAllocScope na;
+  hipLaunchKernelGGL(k_fill_int, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch, 0);
+  HPS_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, status, 1, 0);
+  HPS_HIP_TRY(hipGetLastError());
+  HPS_HIP_TRY(zinv(st, n, A, n, (ll)n * n, inv, n, (ll)n * n, batch, ws, info));
+  hipLaunchKernelGGL(k_or_flags, dim3((batch + 255) / 256), dim3(256), 0, st, (const int*)info, batch, status);
+  return hipGetLastError();
+}
+
 hipError_t zinv_perm(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info,
                      const int** sig, const int** pos) {
   if (n <= 0 || batch <= 0) return hipErrorInvalidValue;

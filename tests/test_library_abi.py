@@ -61,3 +61,20 @@ def test_status_codes_match_the_header():
     for name, val in enum.items():
         assert getattr(hps, name) == val, name
         assert hps._NAMES[val] == name
+
+
+def test_noalloc_rejects_oversized_calls_on_the_host():
+    """hps_zinv_noalloc refuses orders above 512 and workspaces beyond its
+    static array before touching the device (so this runs without a GPU)."""
+    import paper_1608_06871_amd as hps
+    if not os.path.exists(hps.LIB_PATH):
+        pytest.skip("libhps.so not built")
+    L = hps.lib()
+    p = ctypes.c_void_p(16)  # never dereferenced: the calls stop at the size checks
+    assert L.hps_zinv_noalloc(None, 513, 1, p, p, None) == hps.HPS_EINVAL
+    assert L.hps_zinv_noalloc(None, 512, 64, p, p, None) == hps.HPS_EINVAL   # 64 MiB + headers
+    assert L.hps_zinv_noalloc(None, 252, 263, p, p, None) == hps.HPS_EINVAL
+    assert L.hps_zinv_noalloc(None, 128, 1009, p, p, None) == hps.HPS_EINVAL
+    assert L.hps_zinv_noalloc(None, -1, 1, p, p, None) == hps.HPS_EINVAL
+    assert L.hps_zinv_noalloc(None, 0, 5, p, p, None) == hps.HPS_OK
+    assert L.hps_zinv_noalloc(None, 16, 2, None, p, None) == hps.HPS_EINVAL
