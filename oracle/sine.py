@@ -3,8 +3,10 @@ its adjoint, in the form sin(m pi (x - x0)/(x1 - x0)) sin(n pi (y - y0)/(y1 - y0
 on Omega = [x0, x1] x [y0, y1] with the square index set 1 <= m, n <= S.
 
 E maps coefficients C [S, S] (row m = x mode, column n = y mode) to values at
-points; E^T is its transpose (real).  Pinned by tests: orthogonality of the
-modes under the trapezoid sum on a uniform grid, E^T as the exact transpose.
+points; E^T is its transpose (real).  Pinned by tests: single-mode values at
+points where they are exact fractions of pi (tests/golden/sine_mode_values.txt),
+orthonormality of the modes under a tensor Gauss-Legendre rule, E^T as the
+exact transpose, and vanishing on the boundary of Omega.
 """
 import numpy as np
 

@@ -40,3 +40,26 @@ def sine_coefficients(S, seed, scale=0.3, decay=800.0):
 def equispaced_angles(n):
     """2 pi m / n, m = 0..n-1."""
     return 2.0 * np.pi * np.arange(n) / n
+
+
+def parity_inputs(xy, M, P, seed, nbumps=5, nsample_u=64, nsample_g=256, nprobe=4):
+    """Seeded inputs of one library-vs-oracle parity case at PDE-node
+    coordinates xy [npde, 2]:
+      q      contrast, `nbumps` bumps (centres U[-0.6, 0.6]^2, amplitudes
+             U[0.1, 0.3], width 0.15; seed `seed`);
+      dq     perturbation: 3 wide bumps (amplitudes U[0.01, 0.02], width
+             0.3; seed + 100) plus 1e-3 N(0, 1) noise per node;
+      r      complex N(0, 1) + i N(0, 1) array [M, P] (adjoint input);
+      iu     sorted PDE-node indices where total fields are compared;
+      ig     sorted PDE-node indices where gradients are compared;
+      probes [nprobe, npde] N(0, 1) vectors for gradient dot products."""
+    xy = np.asarray(xy, dtype=np.float64)
+    npde = xy.shape[0]
+    q = gaussian_bumps(xy, nbumps, seed, amp=(0.1, 0.3), width=0.15)
+    rng = np.random.default_rng(seed + 200)
+    dq = gaussian_bumps(xy, 3, seed + 100, amp=(0.01, 0.02), width=0.3) + 1e-3 * rng.standard_normal(npde)
+    r = rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))
+    iu = np.sort(rng.choice(npde, size=min(nsample_u, npde), replace=False))
+    ig = np.sort(rng.choice(npde, size=min(nsample_g, npde), replace=False))
+    probes = rng.standard_normal((nprobe, npde))
+    return {"q": q, "dq": dq, "r": r, "iu": iu, "ig": ig, "probes": probes}

@@ -78,7 +78,7 @@ def test_batch_shared_directions_and_oracle():
     prob.factor(qs[1])
     prob.solve(dirs)
     ref = np.asarray(prob.far_field())
-    err = np.linalg.norm(ff[1] - ref) / np.linalg.norm(ref)
+    err = np.max(np.abs(ff[1] - ref)) / np.max(np.abs(ref))
     print(f"batch oracle rel err {err:.2e}", flush=True)
     assert err <= 1e-9
 

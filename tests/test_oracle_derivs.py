@@ -99,3 +99,30 @@ def test_gauss_newton_reduces_misfit():
     C1, r0, _, _ = gn.gauss_newton_step(L, k, C0, data, directions(M), P, 2.0)
     r1 = data - _F(prob, sine.evaluate(xy, C1), M)
     assert np.linalg.norm(r1) < 0.2 * np.linalg.norm(r0)
+
+
+def test_sine_mode_values_at_known_points():
+    """Single modes at points where both factors are exact fractions of pi
+    (tests/golden/sine_mode_values.txt; a doubled or halved frequency, a
+    swapped axis or a shifted origin changes some of these values)."""
+    import os
+    tab = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "sine_mode_values.txt"))
+    for m, n, x, y, val in tab:
+        S = int(max(m, n))
+        C = np.zeros((S, S))
+        C[int(m) - 1, int(n) - 1] = 1.0
+        got = sine.evaluate(np.array([[x, y]]), C)[0]
+        assert abs(got - val) < 1e-14, (m, n, x, y, got, val)
+
+
+def test_sine_modes_orthonormal_under_gauss_quadrature():
+    """int_Omega phi_mn phi_m'n' = delta (each factor has unit L2 norm on
+    [-1, 1]): the Gram matrix of the modes under a tensor Gauss-Legendre rule
+    that integrates these trigonometric products to rounding is the identity."""
+    S = 6
+    x, w = np.polynomial.legendre.leggauss(40)
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    W = np.outer(w, w).ravel()
+    B = sine.basis(np.stack([X.ravel(), Y.ravel()], axis=1), S)
+    G = B.T @ (W[:, None] * B)
+    assert np.max(np.abs(G - np.eye(S * S))) < 1e-13
