@@ -294,6 +294,29 @@ hps_status hps_zinv_noalloc(void* stream, int n, int batch, double* A, double* i
  * HPS_EINVAL for other modes. */
 hps_status hps_zinv_blocking(int mode);
 
+/* Pivoting of the explicit inverses of hps_zinv and of the factorisation's
+ * W and Z inverses (the merges and the top of the Section 2 direct solver
+ * only use the products with W^{-1} and Z^{-1}), process-wide:
+ *   mode -1 (default): orders above 512 that are multiples of 4 are first
+ *           mixed by a depth-2 random butterfly transform (Parker 1995;
+ *           Baboulin, Dongarra, Herrmann, Tomov 2013), A~ = U^T A V, then
+ *           eliminated without searching the rows for pivots (Gauss-Jordan
+ *           with each 32-column panel pivoting on its own rows), and
+ *           A^{-1} = V A~^{-1} U^T.  The result is checked on two fixed probe
+ *           vectors x: ||A^{-1}(A x) - x|| <= tol ||x||; a failed check or a
+ *           zero pivot re-inverts the batch with pivoting.  Other orders:
+ *           partial / tournament pivoting.
+ *   mode 0: partial / tournament pivoting for every order.
+ *   mode 1: the butterfly path for every order that is a multiple of 4.
+ * tol >= 0 sets the probe tolerance (default 1e-10; 0 forces the fallback,
+ * for testing); tol = -1 keeps it.  HPS_ZINV_PIVOTING = 0 / 1 in the
+ * environment sets the initial mode.  HPS_EINVAL for other values. */
+hps_status hps_zinv_pivoting(int mode, double tol);
+
+/* Butterfly-path inverse calls so far, how many fell back to pivoting, and
+ * the largest probe error seen (host outputs; NULL skips one). */
+hps_status hps_zinv_pivoting_info(int64_t* calls, int64_t* fallbacks, double* max_err);
+
 /* Tile shapes of the complex FP64 GEMM behind every call of this library,
  * process-wide (a performance choice; results do not depend on it: every
  * candidate tile shape accumulates the products of an output element in the

@@ -79,6 +79,8 @@ SIGNATURES = [
     ("hps_zinv_noalloc", _I, [_P, _I, _I, _P, _P, _P]),
     ("hps_gemm_tuning", _I, [_I, _I]),
     ("hps_zinv_blocking", _I, [_I]),
+    ("hps_zinv_pivoting", _I, [_I, _D]),
+    ("hps_zinv_pivoting_info", _I, [_P, _P, _P]),
     ("hps_gemm_tuning_info", _I, [_P, _P, _P]),
     ("hps_profile_start", _I, []),
     ("hps_profile_stop", _I, [ctypes.POINTER(KernelStat), _I]),
@@ -390,6 +392,25 @@ def zinv_blocking(mode=-1):
     rc = lib().hps_zinv_blocking(int(mode))
     if rc != HPS_OK:
         raise HpsError(rc, "hps_zinv_blocking")
+
+
+def zinv_pivoting(mode=-1, tol=-1.0):
+    """Pivoting of the large explicit inverses (process-wide): -1 butterfly
+    transform + pivot-free elimination above order 512 (probe-checked, with a
+    pivoted fallback), 0 always pivoted, 1 butterfly for every multiple of 4;
+    tol >= 0 sets the probe tolerance (-1 keeps it)."""
+    rc = lib().hps_zinv_pivoting(int(mode), float(tol))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_zinv_pivoting")
+
+
+def zinv_pivoting_info():
+    """{calls, fallbacks, max_err} of the butterfly-path inverses so far."""
+    c, f, e = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_double(0.0)
+    rc = lib().hps_zinv_pivoting_info(ctypes.byref(c), ctypes.byref(f), ctypes.byref(e))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_zinv_pivoting_info")
+    return {"calls": c.value, "fallbacks": f.value, "max_err": e.value}
 
 
 def gemm_tuning_info():

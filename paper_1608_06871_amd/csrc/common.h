@@ -55,8 +55,16 @@ int gemm_variant_count();
 // while the batch fits the last-level cache), 0 recursive, 1 look-ahead.
 void zinv_set_blocking(int mode);
 
+// Pivoting of zinv (process-wide): -1 butterfly transform + pivot-free
+// elimination for orders above 512 (checked on probe vectors, pivoted
+// fallback), 0 always pivoted, 1 butterfly for every order that is a multiple
+// of 4; tol >= 0 sets the probe-check tolerance.
+void zinv_set_pivoting(int mode, double tol);
+void zinv_pivoting_info(long* calls, long* fallbacks, double* max_err);
+
 // Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
 size_t zinv_workspace(int n, int batch);
+size_t zinv_perm_workspace(int n, int batch);
 
 // Batched inverse by swap-free Gauss-Jordan elimination with partial
 // pivoting (recursive column blocking: panel eliminations and GEMM updates).  `work`
@@ -66,6 +74,7 @@ size_t zinv_workspace(int n, int batch);
 hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo,
                 ll sO, int batch, void* ws, int* info);
 
+// zinv_perm never takes the butterfly path.
 // zinv without the final permutation: `work` is left holding M with
 // inv[c][k] = M[sig[c]][pos[k]] for every matrix of the batch; sig and pos
 // (batch x n ints each, in ws) are returned for the caller's own gathers and

@@ -340,7 +340,7 @@ void plan_factor_buffers(hps_ctx* c) {
   const Geometry& g = c->g;
   const size_t P = c->P;
   const size_t nl = (size_t)g.nleaf * P, n = c->n, ne = g.ne, mi = g.mi, nb = c->nb;
-  size_t zws = zinv_workspace((int)n, (int)nl);
+  size_t zws = zinv_perm_workspace((int)n, (int)nl);
   size_t rmax = nl * ne * ne, blk = 0, w = 0, q = 0, v = 0;
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
@@ -1432,6 +1432,22 @@ hps_status hps_gemm_tuning(int mode, int force) {
 hps_status hps_zinv_blocking(int mode) {
   if (mode < -1 || mode > 1) return HPS_EINVAL;
   zinv_set_blocking(mode);
+  return HPS_OK;
+}
+
+hps_status hps_zinv_pivoting(int mode, double tol) {
+  if (mode < -1 || mode > 1 || !(tol >= 0.0 || tol == -1.0)) return HPS_EINVAL;
+  zinv_set_pivoting(mode, tol);
+  return HPS_OK;
+}
+
+hps_status hps_zinv_pivoting_info(int64_t* calls, int64_t* fallbacks, double* max_err) {
+  long c = 0, f = 0;
+  double e = 0.0;
+  zinv_pivoting_info(&c, &f, &e);
+  if (calls) *calls = c;
+  if (fallbacks) *fallbacks = f;
+  if (max_err) *max_err = e;
   return HPS_OK;
 }
 

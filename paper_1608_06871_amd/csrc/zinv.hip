@@ -31,6 +31,7 @@
 //     panel's pivot rows remain, whose block the last reduction also
 //     inverts; one more kernel exchanges the panel columns.
 #include <atomic>
+#include <cmath>
 #include <cfloat>
 #include <cstdlib>
 #include <mutex>
@@ -546,6 +547,231 @@ __global__ __launch_bounds__(NT) void tp_exchange(double2* Aall, ll lda, ll sA, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pivot-free path for large orders: a random butterfly transform first,
+// then Gauss-Jordan without a search over the rows.
+
+// Pivot-free panel: the pivot rows of panel [c0, c0 + b) are the rows
+// c0 .. c0 + b - 1 themselves.  One workgroup inverts their b x b block
+// D[i][j] = A[c0 + i][c0 + j] (as left by the earlier panels) into
+// IB = D^-1 (IB[c + k b] = D^-1[c][k]) and records sig / pos of the panel.
+// Inside the block each column is still eliminated on its largest remaining
+// entry (swap-free), which only reorders the block's own work; a zero
+// column in the block sets info.
+//
+// Layout: four waves; lane l of wave w holds row ri = l & 31 of the block in
+// the columns q + 8 s (s < 4), q = 2 w + (l >> 5).  The block state is also
+// kept in LDS, double-buffered by column parity, so that the pivot row and
+// column of every step are read from there after one barrier: per column the
+// wave holding the column finds the pivot (wave maximum of packed keys) and
+// posts its row; after the barrier every lane updates its four entries with
+// new = a v + b pr (a = 0, b = 1/piv on the pivot row; a = 1, b = -g
+// elsewhere) and writes them to the other buffer.
+constexpr int NPW = 4;  // waves of np_block
+__global__ __launch_bounds__(64 * NPW) void np_block(const double2* Aall, ll lda, ll sA, int c0, int b,
+                                                     double2* IB_all, int* sig_all, int* pos_all, int n, int* info) {
+  __shared__ double2 Dl[2][BMAX][BMAX + 1];
+  __shared__ int pidx[2];
+  __shared__ int bsig[BMAX];
+  __shared__ int bpos[BMAX];
+  const ll bi = blockIdx.x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int ri = l & (BMAX - 1), q = 2 * w + (l >> 5);
+  const double2* A = Aall + bi * sA;
+  double2 v[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int j = q + 8 * s;
+    v[s] = (ri < b && j < b) ? A[(ll)(c0 + ri) + (ll)(c0 + j) * lda] : make_double2(ri == j ? 1.0 : 0.0, 0.0);
+    Dl[0][ri][j] = v[s];
+  }
+  if (t < BMAX) {
+    bsig[t] = t;  // identity until assigned (a zero pivot leaves some unassigned)
+    bpos[t] = t;
+  }
+  bool used = ri >= b;  // this lane's row already pivoted (or outside the block)
+  int mycol = -1;
+  bool singular = false;
+  __syncthreads();
+  // Column c = 8 S + cl lives in register slot S of the lanes with q == cl.
+#define HPS_NP_STEP(S)                                                                          \
+  _Pragma("unroll 1") for (int cl = 0; cl < 8; ++cl) {                                         \
+    const int c = 8 * (S) + cl;                                                                 \
+    if (c >= b) break;                                                                          \
+    const int cur = c & 1;                                                                      \
+    if (w == (cl >> 1)) { /* the wave holding column c (uniform) */                            \
+      const u64 key = (q == cl && !used) ? pivkey(v[S], ri) : 0ull;                             \
+      const u64 wk = wave_max_key(key);                                                         \
+      if (l == 0) pidx[cur] = key_zero(wk) ? -1 : key_index(wk);                                \
+    }                                                                                           \
+    __syncthreads();                                                                            \
+    const int pp = pidx[cur];                                                                   \
+    const bool zero = pp < 0;                                                                   \
+    const int p = zero ? 0 : pp;                                                                \
+    const double2 piv = Dl[cur][p][c];                                                          \
+    const double2 mine = Dl[cur][ri][c];                                                        \
+    double2 pr[4];                                                                              \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s) pr[s] = Dl[cur][p][q + 8 * s];                \
+    const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(piv);                            \
+    const bool prowl = (ri == p);                                                               \
+    const double2 g = cmul(mine, inv);                                                          \
+    const double a = prowl ? 0.0 : 1.0;                                                         \
+    const double2 bb = prowl ? inv : make_double2(-g.x, -g.y);                                  \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                             \
+      double2 r;                                                                                \
+      r.x = fma(bb.x, pr[s].x, fma(-bb.y, pr[s].y, a * v[s].x));                                \
+      r.y = fma(bb.x, pr[s].y, fma(bb.y, pr[s].x, a * v[s].y));                                 \
+      v[s] = r;                                                                                 \
+    }                                                                                           \
+    if (q == cl) v[S] = bb; /* the column itself: 1/piv on the pivot row, -g elsewhere */       \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s) Dl[cur ^ 1][ri][q + 8 * s] = v[s];            \
+    if (prowl && !zero) {                                                                       \
+      used = true;                                                                              \
+      mycol = c;                                                                                \
+    }                                                                                           \
+    singular = singular || zero;                                                                \
+  }
+  HPS_NP_STEP(0) HPS_NP_STEP(1) HPS_NP_STEP(2) HPS_NP_STEP(3)
+#undef HPS_NP_STEP
+  __syncthreads();  // the last writes to Dl before the gather (final state: buffer b & 1)
+  if (t < b && mycol >= 0) {  // wave 0, q = 0: one thread per block row
+    bsig[mycol] = t;
+    bpos[t] = mycol;
+  }
+  if (singular && t == 0) info[bi] = 1;
+  __syncthreads();
+  const int fin = b & 1;
+  double2* IB = IB_all + bi * (ll)BMAX * BMAX;
+  for (int e = t; e < b * b; e += 64 * NPW) {
+    const int c = e % b, k = e / b;
+    IB[c + k * b] = Dl[fin][bsig[c]][bpos[k]];
+  }
+  int* sig = sig_all + bi * n;
+  int* pos = pos_all + bi * n;
+  if (t < b) {
+    sig[c0 + t] = c0 + t;
+    pos[c0 + t] = c0 + t;
+  }
+}
+
+// Depth-2 random butterfly transform (Parker 1995; as used for pivot-free
+// LU by Baboulin, Dongarra, Herrmann and Tomov 2013).  A butterfly of order
+// 2h is B = (1/sqrt 2) [R0 R1; R0 -R1] with random diagonal R0, R1 whose
+// entries are exp(u / 10), u ~ U[-1/2, 1/2]; the depth-2 transform of order
+// n = 4m is W = diag(B', B'') B (B of order n, B' and B'' of order n/2).  W
+// couples only the four entries r, m + r, 2m + r, 3m + r of a vector, so it
+// is a 4 x 4 real matrix W_r per residue r < m.  The random numbers come
+// from a counter-based generator (the splitmix64 finaliser of Steele, Lea
+// and Flood 2014) keyed by (seed, entry), so W is the same on every call.
+__device__ __forceinline__ double rbt_diag(unsigned seed, ll idx) {
+  u64 z = ((u64)seed << 40) ^ (u64)idx;
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+  return exp((u - 0.5) * 0.1);
+}
+
+// W_r (4 x 4, row-major) of the transform with the given seed.  Entries of
+// the outer butterfly: R0 = a (a_r for pair (r, 2m + r), a_{m+r} for pair
+// (m + r, 3m + r)), R1 = b; inner butterflies: (c, d) on the first half,
+// (e, f) on the second.
+__device__ __forceinline__ void rbt_block(unsigned seed, int m, int r, double W[4][4]) {
+  const double a0 = rbt_diag(seed, r), a1 = rbt_diag(seed, (ll)m + r);
+  const double b0 = rbt_diag(seed, 2LL * m + r), b1 = rbt_diag(seed, 3LL * m + r);
+  const double c = rbt_diag(seed, 4LL * m + r), d = rbt_diag(seed, 5LL * m + r);
+  const double e = rbt_diag(seed, 6LL * m + r), f = rbt_diag(seed, 7LL * m + r);
+  const double h = 0.5;  // (1/sqrt 2)^2
+  W[0][0] = h * c * a0; W[0][1] = h * d * a1;  W[0][2] = h * c * b0;  W[0][3] = h * d * b1;
+  W[1][0] = h * c * a0; W[1][1] = -h * d * a1; W[1][2] = h * c * b0;  W[1][3] = -h * d * b1;
+  W[2][0] = h * e * a0; W[2][1] = h * f * a1;  W[2][2] = -h * e * b0; W[2][3] = -h * f * b1;
+  W[3][0] = h * e * a0; W[3][1] = -h * f * a1; W[3][2] = -h * e * b0; W[3][3] = h * f * b1;
+}
+
+// out = L in R for square order-n matrices (n = 4m), L = W(seedL) or its
+// transpose, R = W(seedR) or its transpose.  Thread (r, s) transforms the 4
+// x 4 block of rows {q m + r} and columns {t m + s}: out_blk = L_r in_blk R_s.
+__global__ __launch_bounds__(256) void k_rbt(const double2* in, ll ldi, ll si, double2* out, ll ldo, ll so, int m,
+                                             unsigned seedL, int transL, unsigned seedR, int transR) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y;
+  if (r >= m) return;
+  const ll bi = blockIdx.z;
+  double Lw[4][4], Rw[4][4];
+  rbt_block(seedL, m, r, Lw);
+  rbt_block(seedR, m, s, Rw);
+  const double2* I = in + bi * si;
+  double2 x[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[q][t] = I[(ll)q * m + r + ((ll)t * m + s) * ldi];
+  // y = x R
+  double2 y[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double w = transR ? Rw[t][u] : Rw[u][t];
+        acc.x = fma(x[q][u].x, w, acc.x);
+        acc.y = fma(x[q][u].y, w, acc.y);
+      }
+      y[q][t] = acc;
+    }
+  double2* O = out + bi * so;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double w = transL ? Lw[u][q] : Lw[q][u];
+        acc.x = fma(w, y[u][t].x, acc.x);
+        acc.y = fma(w, y[u][t].y, acc.y);
+      }
+      O[(ll)q * m + r + ((ll)t * m + s) * ldo] = acc;
+    }
+}
+
+// Probe vectors X [batch][np][n] with entries in the unit square (fixed,
+// counter-based), and the relative error ||X1 - X0|| / ||X0|| per matrix.
+__global__ void k_probe_fill(double2* X, ll per, int batch) {
+  const ll total = per * batch;
+  for (ll e = (ll)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (ll)gridDim.x * blockDim.x) {
+    const ll k = e % per;
+    X[e] = make_double2(2.0 * rbt_diag(7u, 2 * k) - 2.0, 2.0 * rbt_diag(7u, 2 * k + 1) - 2.0);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_probe_err(const double2* X0, const double2* X1, ll per, double* err) {
+  __shared__ double sn[256], sd[256];
+  const ll bi = blockIdx.x;
+  const double2* a = X0 + bi * per;
+  const double2* b = X1 + bi * per;
+  double num = 0.0, den = 0.0;
+  for (ll i = threadIdx.x; i < per; i += 256) {
+    const double dx = b[i].x - a[i].x, dy = b[i].y - a[i].y;
+    num += dx * dx + dy * dy;
+    den += a[i].x * a[i].x + a[i].y * a[i].y;
+  }
+  sn[threadIdx.x] = num;
+  sd[threadIdx.x] = den;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sn[threadIdx.x] += sn[threadIdx.x + w];
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) err[bi] = sqrt(sn[0] / sd[0]);
+}
+
 size_t cand_ints(int n, int batch) { return (size_t)batch * ((n + TR - 1) / TR) * BMAX; }
 
 // Split point of a block of w > BMAX columns: half of its panels, rounded up.
@@ -581,6 +807,7 @@ struct Inv {
   int* candA;
   int* candB;
   int* info;
+  bool nopiv;  // pivot rows = the panel's own rows (after a butterfly transform)
 };
 
 hipError_t launch_panel(const Inv& v, int c0, int bw) {
@@ -646,6 +873,25 @@ hipError_t tournament_panel(const Inv& v, int c0, int bw) {
   return hipGetLastError();
 }
 
+// Pivot-free panel: block inverse of the panel's own rows, then the same
+// exchange of the panel columns as the tournament path.
+hipError_t np_panel(const Inv& v, int c0, int bw) {
+  {
+    KernelTimer kt(v.st, K_GJ_PANEL, 8.0 * (double)bw * bw * bw * v.batch, 32.0 * (double)bw * bw * v.batch);
+    hipLaunchKernelGGL(np_block, dim3(v.batch), dim3(64 * NPW), 0, v.st, v.work, v.lda, v.sA, c0, bw, v.IB, v.sig,
+                       v.pos, v.n, v.info);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  KernelTimer kt(v.st, K_TP_EXCH, 8.0 * v.n * (double)bw * bw * v.batch, 48.0 * v.n * (double)bw * v.batch);
+  hipLaunchKernelGGL(tp_exchange, dim3((unsigned)((v.n + NT / 4 - 1) / (NT / 4)), v.batch), dim3(NT), 0, v.st,
+                     v.work, v.lda, v.sA, v.n, c0, bw, v.IB, v.pos);
+  return hipGetLastError();
+}
+
+hipError_t wide_panel(const Inv& v, int c0, int bw) {
+  return v.nopiv ? np_panel(v, c0, bw) : tournament_panel(v, c0, bw);
+}
+
 // Applies the exchanges of columns [s0, s1) to columns [d0, d1).
 hipError_t block_update(const Inv& v, int s0, int s1, int d0, int d1) {
   const int w = s1 - s0, nd = d1 - d0;
@@ -702,19 +948,37 @@ hipError_t side_stream(hipStream_t st, hipStream_t* out) {
 // gathers the next pivot rows.  The second stream never writes the current
 // or the next panel's columns; its row mask (pivot positions of panel p)
 // is unaffected by the positions the next panel assigns meanwhile.
+// Panel width of the look-ahead.  Pivoted: 32 (one tournament per panel).
+// Pivot-free: up to 128, so that each pass over the matrix is a rank-128
+// update instead of four rank-32 ones; a wide panel is eliminated by the
+// recursive blocking restricted to its own columns (32-column pivot-free
+// leaves, all rows), with its pivot-row copies in the part of T after the
+// look-ahead's own w x n copies (the side stream still reads those).
+int lookahead_width(int n, bool nopiv) {
+  if (!nopiv) return BMAX;
+  for (int w = 4 * BMAX; w > BMAX; w -= BMAX)
+    if ((size_t)w * n + t_elems_block(w) <= t_elems(n)) return w;
+  return BMAX;
+}
+
+hipError_t process_block(const Inv& v, int c0, int c1);
+
 hipError_t lookahead_inverse(const Inv& v) {
   const int n = v.n;
+  const int PW = lookahead_width(n, v.nopiv);
+  Inv vp = v;  // in-panel elimination: pivot-row copies after the look-ahead's
+  vp.T = v.T + (ll)PW * n;
   hipStream_t X = nullptr;
   HPS_HIP_TRY(side_stream(v.st, &X));
   hipEvent_t t_ready = nullptr, x_done = nullptr;
   HPS_HIP_TRY(hipEventCreateWithFlags(&t_ready, hipEventDisableTiming));
   hipError_t err = hipEventCreateWithFlags(&x_done, hipEventDisableTiming);
   bool pending = false;  // an update on X not yet waited for
-  for (int c0 = 0; c0 < n && err == hipSuccess; c0 += BMAX) {
-    const int b = n - c0 < BMAX ? n - c0 : BMAX;
-    if ((err = tournament_panel(v, c0, b)) != hipSuccess) break;
+  for (int c0 = 0; c0 < n && err == hipSuccess; c0 += PW) {
+    const int b = n - c0 < PW ? n - c0 : PW;
+    if ((err = (b <= BMAX ? wide_panel(v, c0, b) : process_block(vp, c0, c0 + b))) != hipSuccess) break;
     const int c1 = c0 + b;
-    const int b1 = n - c1 < BMAX ? n - c1 : BMAX;  // next panel (0 after the last)
+    const int b1 = n - c1 < PW ? n - c1 : PW;  // next panel (0 after the last)
     // the pivot rows of panel p in every column, once X has applied panel p-1
     if (pending && (err = hipStreamWaitEvent(v.st, x_done, 0)) != hipSuccess) break;
     {
@@ -759,7 +1023,7 @@ hipError_t lookahead_inverse(const Inv& v) {
 hipError_t process_block(const Inv& v, int c0, int c1) {
   const int w = c1 - c0;
   if (w <= BMAX) {
-    if (v.n > NS_MAX_N) return tournament_panel(v, c0, w);
+    if (v.nopiv || v.n > NS_MAX_N) return wide_panel(v, c0, w);
     KernelTimer kt(v.st, K_GJ_PANEL, 8.0 * v.n * (double)w * w * v.batch, 32.0 * v.n * (double)w * v.batch);
     return launch_panel(v, c0, w);
   }
@@ -791,16 +1055,70 @@ bool use_lookahead(int n, int batch) {
   return (double)batch * n * n * sizeof(double2) <= 256.0 * 1024 * 1024;
 }
 
+// Pivoting of the explicit inverses (process-wide):
+//   -1 (default): for orders above the register-panel limit that are
+//      multiples of 4, a random butterfly transform and pivot-free
+//      elimination, checked on probe vectors, with the pivoted
+//      (tournament) elimination as fallback; partial pivoting otherwise;
+//    0: always partial / tournament pivoting;
+//    1: the butterfly path for every order that is a multiple of 4 (>= 8).
+// -2: not read yet (HPS_ZINV_PIVOTING = 0 / 1 in the environment).
+std::atomic<int> g_pivoting{-2};
+std::atomic<double> g_rbt_tol{1e-10};
+std::atomic<long> g_rbt_calls{0}, g_rbt_fallbacks{0};
+std::atomic<double> g_rbt_maxerr{0.0};
+constexpr int NPROBE = 2;
+constexpr unsigned RBT_SEED_U = 0x5a17u, RBT_SEED_V = 0x3c6du;
+
+bool use_rbt(int n, int batch) {
+  (void)batch;
+  if (no_alloc_active() || n % 4 != 0 || n < 8) return false;
+  int m = g_pivoting.load();
+  if (m == -2) {
+    const char* e = std::getenv("HPS_ZINV_PIVOTING");
+    int want = (e && (*e == '0' || *e == '1')) ? *e - '0' : -1;
+    g_pivoting.compare_exchange_strong(m, want);
+    m = g_pivoting.load();
+  }
+  if (m == 0) return false;
+  if (m == 1) return true;
+  return n > NS_MAX_N;
+}
+
+size_t std_workspace(int n, int batch, bool wide) {
+  size_t bytes = align256((size_t)batch * n * sizeof(int) * 2);   // sig + pos
+  bytes += align256((size_t)batch * t_elems(n) * sizeof(double2));  // pivot rows T
+  if (wide) {
+    bytes += align256((size_t)batch * BMAX * BMAX * sizeof(double2));  // IB
+    bytes += 2 * align256(cand_ints(n, batch) * sizeof(int));          // candidates
+  }
+  return bytes;
+}
+
 }  // namespace
 
 void zinv_set_blocking(int mode) { g_blocking.store(mode); }
 
+void zinv_set_pivoting(int mode, double tol) {
+  g_pivoting.store(mode);
+  if (tol >= 0.0) g_rbt_tol.store(tol);
+}
+
+void zinv_pivoting_info(long* calls, long* fallbacks, double* max_err) {
+  if (calls) *calls = g_rbt_calls.load();
+  if (fallbacks) *fallbacks = g_rbt_fallbacks.load();
+  if (max_err) *max_err = g_rbt_maxerr.load();
+}
+
+size_t zinv_perm_workspace(int n, int batch) { return std_workspace(n, batch, n > NS_MAX_N); }
+
 size_t zinv_workspace(int n, int batch) {
-  size_t bytes = align256((size_t)batch * n * sizeof(int) * 2);   // sig + pos
-  bytes += align256((size_t)batch * t_elems(n) * sizeof(double2));  // pivot rows T
-  if (n > NS_MAX_N) {
-    bytes += align256((size_t)batch * BMAX * BMAX * sizeof(double2));  // IB
-    bytes += 2 * align256(cand_ints(n, batch) * sizeof(int));          // candidates
+  const bool rbt = use_rbt(n, batch);
+  size_t bytes = std_workspace(n, batch, n > NS_MAX_N || rbt);
+  if (rbt) {
+    bytes += align256((size_t)batch * n * n * sizeof(double2));            // transformed matrix
+    bytes += 3 * align256((size_t)batch * n * NPROBE * sizeof(double2));   // probes X0, Y, X1
+    bytes += align256((size_t)batch * sizeof(double));                     // probe errors
   }
   return bytes;
 }
@@ -808,8 +1126,11 @@ size_t zinv_workspace(int n, int batch) {
 namespace {
 
 // Elimination without the final permutation; v.sig / v.pos left in ws.
-hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info, Inv& v) {
+// nopiv: pivot-free panels (sig / pos end as the identity).
+hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info, Inv& v,
+                     bool nopiv = false) {
   char* p = (char*)ws;
+  v.nopiv = nopiv;
   v.st = st;
   v.n = n;
   v.batch = batch;
@@ -823,7 +1144,7 @@ hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int ba
   v.T = (double2*)p;
   v.sT = (ll)t_elems(n);
   p += align256((size_t)batch * t_elems(n) * sizeof(double2));
-  if (n > NS_MAX_N) {
+  if (n > NS_MAX_N || nopiv) {
     v.IB = (double2*)p;
     p += align256((size_t)batch * BMAX * BMAX * sizeof(double2));
     v.candA = (int*)p;
@@ -835,7 +1156,86 @@ hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int ba
     hipLaunchKernelGGL(gj_init, dim3((n + 255) / 256, batch), dim3(256), 0, st, v.pos, n);
   }
   HPS_HIP_TRY(hipGetLastError());
+  // (the look-ahead's pivot-row copies, b x n, fit the T buffer only above
+  // the register-panel limit)
   return n > NS_MAX_N && use_lookahead(n, batch) ? lookahead_inverse(v) : process_block(v, 0, n);
+}
+
+hipError_t pivoted_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO,
+                           int batch, void* ws, int* info) {
+  Inv v{};
+  HPS_HIP_TRY(zinv_core(st, n, work, lda, sA, batch, ws, info, v));
+  KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
+  hipLaunchKernelGGL(gj_unpermute, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, v.sig, v.pos,
+                     n);
+  return hipGetLastError();
+}
+
+// Butterfly path: A~ = U^T A V (out of place, A kept), A~^-1 by pivot-free
+// elimination, A^-1 = V A~^-1 U^T.  Check: probe vectors X0, Y = A X0,
+// X1 = A^-1 Y; every matrix must have ||X1 - X0|| <= tol ||X0|| and no zero
+// pivot, else the whole batch is inverted again with pivoting (A is still
+// intact).  Synchronises the stream once for the check.
+hipError_t rbt_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO,
+                       int batch, void* ws, int* info) {
+  const int m = n / 4;
+  char* p = (char*)ws + std_workspace(n, batch, true);
+  double2* T = (double2*)p;
+  const ll nn = (ll)n * n;
+  p += align256((size_t)batch * nn * sizeof(double2));
+  const ll per = (ll)n * NPROBE;
+  double2* X0 = (double2*)p;
+  p += align256((size_t)batch * per * sizeof(double2));
+  double2* Y = (double2*)p;
+  p += align256((size_t)batch * per * sizeof(double2));
+  double2* X1 = (double2*)p;
+  p += align256((size_t)batch * per * sizeof(double2));
+  double* err = (double*)p;
+  const dim3 tg((m + 255) / 256, m, batch);
+  {
+    KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)nn * batch);
+    hipLaunchKernelGGL(k_rbt, tg, dim3(256), 0, st, work, lda, sA, T, (ll)n, nn, m, RBT_SEED_U, 1, RBT_SEED_V, 0);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  Inv v{};
+  HPS_HIP_TRY(zinv_core(st, n, T, n, nn, batch, ws, info, v, true));
+  {
+    KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)nn * batch);
+    hipLaunchKernelGGL(k_rbt, tg, dim3(256), 0, st, T, (ll)n, nn, out, ldo, sO, m, RBT_SEED_V, 0, RBT_SEED_U, 1);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  {
+    const ll tot = per * batch;
+    ll blocks = (tot + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_probe_fill, dim3((unsigned)blocks), dim3(256), 0, st, X0, per, batch);
+    HPS_HIP_TRY(hipGetLastError());
+  }
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, NPROBE, n, one, work, lda, sA, X0, n, per, zero, Y, n, per, batch));
+  HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, NPROBE, n, one, out, ldo, sO, Y, n, per, zero, X1, n, per, batch));
+  hipLaunchKernelGGL(k_probe_err, dim3(batch), dim3(256), 0, st, X0, X1, per, err);
+  HPS_HIP_TRY(hipGetLastError());
+  std::vector<double> he(batch);
+  std::vector<int> hi(batch);
+  HPS_HIP_TRY(hipMemcpyAsync(he.data(), err, sizeof(double) * batch, hipMemcpyDeviceToHost, st));
+  HPS_HIP_TRY(hipMemcpyAsync(hi.data(), info, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+  HPS_HIP_TRY(hipStreamSynchronize(st));
+  const double tol = g_rbt_tol.load();
+  bool ok = true;
+  double worst = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    ok = ok && (he[b] <= tol) && hi[b] == 0;  // a NaN error fails
+    worst = std::isnan(he[b]) || he[b] > worst ? he[b] : worst;
+  }
+  g_rbt_calls.fetch_add(1);
+  double prev = g_rbt_maxerr.load();
+  while ((std::isnan(worst) || worst > prev) && !g_rbt_maxerr.compare_exchange_weak(prev, worst)) {
+  }
+  if (ok) return hipSuccess;
+  g_rbt_fallbacks.fetch_add(1);
+  HPS_HIP_TRY(hipMemsetAsync(info, 0, sizeof(int) * batch, st));
+  return pivoted_inverse(st, n, work, lda, sA, out, ldo, sO, batch, ws, info);
 }
 
 }  // namespace
@@ -844,14 +1244,8 @@ hipError_t zinv(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* ou
                 void* ws, int* info) {
   if (n <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
-  Inv v{};
-  HPS_HIP_TRY(zinv_core(st, n, work, lda, sA, batch, ws, info, v));
-  {
-    KernelTimer kt(st, K_GJ_PERM, 0.0, 32.0 * n * (double)n * batch);
-    hipLaunchKernelGGL(gj_unpermute, dim3(n, batch), dim3(NT), 0, st, work, lda, sA, out, ldo, sO, v.sig, v.pos,
-                       n);
-  }
-  return hipGetLastError();
+  if (use_rbt(n, batch)) return rbt_inverse(st, n, work, lda, sA, out, ldo, sO, batch, ws, info);
+  return pivoted_inverse(st, n, work, lda, sA, out, ldo, sO, batch, ws, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -907,7 +1301,7 @@ __global__ void k_or_flags(const int* info, int n, int* flag) {
 size_t zinv_noalloc_capacity() { return NOALLOC_BYTES; }
 
 size_t zinv_noalloc_bytes(int n, int batch) {
-  return 256 + align256((size_t)batch * sizeof(int)) + zinv_workspace(n, batch);
+  return 256 + align256((size_t)batch * sizeof(int)) + std_workspace(n, batch, false);
 }
 
 hipError_t zinv_noalloc_status_slot(int** out) {

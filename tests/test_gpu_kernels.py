@@ -313,3 +313,69 @@ def test_autotuned_lookahead_inverse_is_bitwise_identical():
         hps.zinv_blocking(-1)
     torch.cuda.synchronize()
     assert torch.equal(tuned, ref) and torch.equal(again, ref)
+
+
+@pytest.mark.parametrize("n,batch,mode", [(8, 3, 1), (64, 2, 1), (100, 3, 1), (252, 2, 1), (516, 1, -1),
+                                          (700, 2, -1), (1100, 1, -1), (700, 2, 0)])
+@pytest.mark.parametrize("blocking", [0, 1])
+def test_zinv_butterfly_path_matches_numpy(n, batch, mode, blocking):
+    """Random butterfly transform + pivot-free elimination (mode 1 forces it
+    at small orders; -1 is the default rule, which takes it above 512), in
+    both column blockings, against numpy; a tiny leading entry would stop a
+    plain pivot-free elimination."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    print(f"zinv butterfly n={n} batch={batch} mode={mode} blocking={blocking}", flush=True)
+    rng = np.random.default_rng(n + 31 * batch)
+    A = _rand(rng, (batch, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    A[:, 0, 0] = 1e-12
+    before = hps.zinv_pivoting_info()
+    hps.zinv_pivoting(mode)
+    hps.zinv_blocking(blocking)
+    try:
+        inv = _back(hps.zinv(_colmajor(torch, A)))
+    finally:
+        hps.zinv_pivoting(-1)
+        hps.zinv_blocking(-1)
+    after = hps.zinv_pivoting_info()
+    took = after["calls"] - before["calls"]
+    assert took == (0 if (mode == 0 or (mode == -1 and n <= 512)) else 1)
+    assert after["fallbacks"] == before["fallbacks"]
+    ref = np.linalg.inv(A)
+    for b in range(batch):
+        cond = np.linalg.cond(A[b])
+        assert np.max(np.abs(inv[b] - ref[b])) < 1e-13 * cond * np.max(np.abs(ref[b]))
+
+
+def test_zinv_butterfly_fallback_forced_from_host():
+    """A probe tolerance of 0 fails every check: the batch is inverted again
+    with pivoting, which still gives the inverse, and the fallback is counted."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    n = 600
+    rng = np.random.default_rng(3)
+    A = _rand(rng, (2, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    before = hps.zinv_pivoting_info()
+    hps.zinv_pivoting(-1, 0.0)
+    try:
+        inv = _back(hps.zinv(_colmajor(torch, A)))
+    finally:
+        hps.zinv_pivoting(-1, 1e-10)
+    after = hps.zinv_pivoting_info()
+    assert after["fallbacks"] == before["fallbacks"] + 1
+    ref = np.linalg.inv(A)
+    assert np.max(np.abs(inv - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_zinv_butterfly_singular_falls_back_and_reports():
+    """An exactly singular order-700 matrix: the butterfly path's check fails,
+    the pivoted fallback meets the zero pivot and reports it."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    n = 700
+    rng = np.random.default_rng(11)
+    A = _rand(rng, (1, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    A[:, :, 37] = 0.0
+    with pytest.raises(hps.HpsError) as e:
+        hps.zinv(_colmajor(torch, A))
+    assert e.value.code == hps.HPS_ESINGULAR
