@@ -208,12 +208,16 @@ hps_status hps_sine_adjoint(hps_ctx* ctx, int S, const double* g, double* coef);
  *   stopping after max_iter iterations or when the CG residual falls to
  *   tol times its initial norm;
  *   coef_out = coef + dc.
+ * band > 0 restricts the unknowns to the modes with m + n <= band (the
+ * triangular index set of eq. sineseries, S(k) = floor(2k) in the paper);
+ * the other entries of dc are zero (coefficients outside the band keep their
+ * values).  band = 0: all S x S modes.
  * coef, coef_out: device, S*S doubles (layout of hps_sine_eval).  Host
  * outputs (may be NULL): CG iterations, final relative CG residual, and the
  * data misfit ||r|| before the step.  Leaves the context factored and solved
  * at q = E coef.  Synchronous.  Requires keep_derivs. */
 hps_status hps_gn_step(hps_ctx* ctx, double k, int ndir, const double* dir_angle_host, int ntheta,
-                       const double* theta_host, double R, int S, const double* coef,
+                       const double* theta_host, double R, int S, int band, const double* coef,
                        const double* data, int max_iter, double tol, double* coef_out,
                        int* iters_host, double* cg_rel_res_host, double* misfit_host);
 

@@ -72,7 +72,7 @@ SIGNATURES = [
     ("hps_sine_eval", _I, [_P, _I, _P, _P]),
     ("hps_sine_adjoint", _I, [_P, _I, _P, _P]),
     ("hps_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
-    ("hps_gn_step", _I, [_P, _D, _I, _P, _I, _P, _D, _I, _P, _P, _I, _D, _P, _P, _P, _P]),
+    ("hps_gn_step", _I, [_P, _D, _I, _P, _I, _P, _D, _I, _I, _P, _P, _I, _D, _P, _P, _P, _P]),
     ("hps_boundary_operators", _I, [ctypes.POINTER(Opts), _D, _P, _P, _P]),
     ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
     ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
@@ -276,8 +276,9 @@ class Solver:
                                            _dev(out, torch.float64, S * S, "coef")), "sine_adjoint")
         return out
 
-    def gn_step(self, k, dirs, thetas, R, coef, data, max_iter=50, tol=1e-12, out=None):
-        """One Gauss-Newton step on the sine model; returns (coef_out, info)."""
+    def gn_step(self, k, dirs, thetas, R, coef, data, max_iter=50, tol=1e-12, out=None, band=0):
+        """One Gauss-Newton step on the sine model; returns (coef_out, info).
+        band > 0: only the modes with m + n <= band are unknowns."""
         torch = _torch()
         a = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).ravel())
         th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).ravel())
@@ -288,7 +289,7 @@ class Solver:
         rel = ctypes.c_double(0.0)
         mis = ctypes.c_double(0.0)
         self._check(lib().hps_gn_step(self._h, float(k), int(a.size), a.ctypes.data_as(ctypes.c_void_p),
-                                      int(th.size), th.ctypes.data_as(ctypes.c_void_p), float(R), S,
+                                      int(th.size), th.ctypes.data_as(ctypes.c_void_p), float(R), S, int(band),
                                       _dev(coef, torch.float64, S * S, "coef"),
                                       _dev(data, torch.complex128, a.size * th.size, "data"),
                                       int(max_iter), float(tol), _dev(out, torch.float64, S * S, "coef_out"),

@@ -1055,11 +1055,11 @@ struct GnResult {
 };
 
 GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const double* th, double R,
-                 int S, const double* coef, const double* data, int max_iter, double tol,
+                 int S, int band, const double* coef, const double* data, int max_iter, double tol,
                  double* coef_out) {
   require(c->o.keep_derivs != 0, HPS_ESTATE, "context created without keep_derivs");
   require(c->P == 1, HPS_EINVAL, "the Gauss-Newton step takes a single-problem context");
-  require(S >= 1 && coef && data && coef_out && max_iter >= 0 && tol >= 0.0, HPS_EINVAL,
+  require(S >= 1 && band >= 0 && coef && data && coef_out && max_iter >= 0 && tol >= 0.0, HPS_EINVAL,
           "bad Gauss-Newton arguments");
   const ll npde = (ll)c->g.nleaf * c->g.mi, ns = (ll)S * S, nd = (ll)M * nt;
   hipStream_t st = c->st;
@@ -1099,6 +1099,7 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
   // b = E^T Re(J^H res)
   vjp(c, (const double*)res, gv);
   sine_adjoint(c, S, gv, r);
+  CK(band_mask(st, r, S, band));  // unknowns: the modes in the band only
   CK(hipMemsetAsync(x, 0, sizeof(double) * ns, st));
   CK(hipMemcpyAsync(pv, r, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
   double rr = dotv(r, r);
@@ -1111,6 +1112,7 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
     jvp(c, q, (double*)jv);
     vjp(c, (const double*)jv, gv);
     sine_adjoint(c, S, gv, Ap);
+    CK(band_mask(st, Ap, S, band));
     const double pAp = dotv(pv, Ap);
     if (!(pAp > 0.0)) break;
     const double alpha = rr / pAp;
@@ -1345,12 +1347,12 @@ hps_status hps_sine_adjoint(hps_ctx* c, int S, const double* g, double* coef) {
 }
 
 hps_status hps_gn_step(hps_ctx* c, double k, int ndir, const double* dir_angle_host, int ntheta,
-                       const double* theta_host, double R, int S, const double* coef,
+                       const double* theta_host, double R, int S, int band, const double* coef,
                        const double* data, int max_iter, double tol, double* coef_out,
                        int* iters_host, double* cg_rel_res_host, double* misfit_host) {
   if (!c) return HPS_EINVAL;
   return guard(c, [&] {
-    const GnResult g = gn_step(c, k, ndir, dir_angle_host, ntheta, theta_host, R, S, coef, data,
+    const GnResult g = gn_step(c, k, ndir, dir_angle_host, ntheta, theta_host, R, S, band, coef, data,
                                max_iter, tol, coef_out);
     if (iters_host) *iters_host = g.iters;
     if (cg_rel_res_host) *cg_rel_res_host = g.cg_rel_res;

@@ -73,6 +73,8 @@ hipError_t complex_real_part(hipStream_t st, const double2* x, ll n, double* y);
 hipError_t dot(hipStream_t st, const double* x, const double* y, ll n, double* partial, double* out);
 // *flag |= bit when any of x[0 .. n) is NaN or infinite.
 hipError_t flag_nonfinite(hipStream_t st, const double* x, ll n, int bit, int* flag);
+// x[(m - 1) S + (n - 1)] = 0 for m + n > band (band <= 0: no-op).
+hipError_t band_mask(hipStream_t st, double* x, int S, int band);
 // y = a x + b y
 hipError_t axpby(hipStream_t st, double a, const double* x, double b, double* y, ll n);
 // z = x - y (complex)

@@ -384,6 +384,21 @@ hipError_t dot(hipStream_t st, const double* x, const double* y, ll n, double* p
   return hipGetLastError();
 }
 
+// Zeroes the sine coefficients outside the band: x[(m - 1) S + (n - 1)] = 0
+// when m + n > band (1-based mode numbers).
+__global__ void k_band_mask(double* x, int S, int band) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S * S) return;
+  const int m = e / S + 1, n = e % S + 1;
+  if (m + n > band) x[e] = 0.0;
+}
+
+hipError_t band_mask(hipStream_t st, double* x, int S, int band) {
+  if (band <= 0 || S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_mask, dim3((S * S + 255) / 256), dim3(256), 0, st, x, S, band);
+  return hipGetLastError();
+}
+
 hipError_t axpby(hipStream_t st, double a, const double* x, double b, double* y, ll n) {
   KernelTimer kt(st, K_POINT, 3.0 * n, 24.0 * n);
   hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(NT), 0, st, a, x, b, y, n);

@@ -63,3 +63,15 @@ def parity_inputs(xy, M, P, seed, nbumps=5, nsample_u=64, nsample_g=256, nprobe=
     ig = np.sort(rng.choice(npde, size=min(nsample_g, npde), replace=False))
     probes = rng.standard_normal((nprobe, npde))
     return {"q": q, "dq": dq, "r": r, "iu": iu, "ig": ig, "probes": probes}
+
+
+def add_noise(u, delta, seed):
+    """Noise of the form used for the measured data in the experiments of
+    Section 4: for each incident direction (row m of u [M, P]),
+    u_m + delta ||u_m|| / ||e_m|| e_m with e_m = e1 + i e2 and e1, e2
+    standard normal over the P angles (so ||noise_m|| = delta ||u_m||)."""
+    u = np.asarray(u, dtype=np.complex128)
+    rng = np.random.default_rng(seed)
+    e = rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)
+    scale = delta * np.linalg.norm(u, axis=-1, keepdims=True) / np.linalg.norm(e, axis=-1, keepdims=True)
+    return u + scale * e

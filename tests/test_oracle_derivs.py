@@ -126,3 +126,25 @@ def test_sine_modes_orthonormal_under_gauss_quadrature():
     B = sine.basis(np.stack([X.ravel(), Y.ravel()], axis=1), S)
     G = B.T @ (W[:, None] * B)
     assert np.max(np.abs(G - np.eye(S * S))) < 1e-13
+
+
+def test_gauss_newton_band_recovers_in_band_perturbation():
+    """With the triangular band (eq. sineseries, modes m + n <= S), linearised
+    data of an in-band perturbation are recovered exactly and the coefficients
+    outside the band keep their values."""
+    L, k, M, P, S, band = 2, 3.0, 6, 12, 3, 3
+    prob = Problem(L, k)
+    xy = prob.grid.pde_coords()
+    _, th = circle_points(2.0, P)
+    prob.set_measurement(th, 2.0)
+    rng = np.random.default_rng(4)
+    C0 = 0.05 * rng.standard_normal((S, S))
+    keep = gn.band_mask(S, band)
+    assert keep.sum() == band * (band - 1) // 2
+    dC = np.where(keep, 1e-7 * rng.standard_normal((S, S)), 0.0)
+    prob.factor(sine.evaluate(xy, C0))
+    prob.solve(directions(M))
+    data = prob.far_field() + prob.jvp(sine.evaluate(xy, dC))
+    C1, _, _, _ = gn.gauss_newton_step(L, k, C0, data, directions(M), P, 2.0, band=band)
+    assert np.array_equal(C1[~keep], C0[~keep])
+    assert np.max(np.abs(C1 - (C0 + dC))) < 1e-6 * np.max(np.abs(dC))
