@@ -126,6 +126,152 @@ def gn_timing(s, k, dirs, th, R, steps, S=160, cg_iters=30):
             "model_rel_err_after_step": err, "start": "half the true coefficients"}
 
 
+def level_table(L, p=16):
+    """Merge levels of the L x L leaf tree (alternating x / y merges):
+    [(count, s = shared nodes, m = exterior nodes per child)] per level."""
+    e = p - 2
+    out = []
+    nlev = 2 * int(round(np.log2(L)))
+    for l in range(1, nlev + 1):
+        s = e * 2 ** (l // 2)
+        out.append((L * L // 2 ** l, s))
+    return out
+
+
+def child_boundary(l, e):
+    """Boundary nodes of a box one level below merge level l (a leaf for
+    l = 1): boxes alternate square (2^a x 2^a leaves) and 2:1 rectangles."""
+    a = (l - 1) // 2
+    if (l - 1) % 2 == 0:
+        return 4 * e * 2 ** a
+    return 6 * e * 2 ** a
+
+
+def algorithmic_work(L, M, p=16):
+    """Algorithmic flops (complex multiply-add = 8) of the factorisation stages
+    as this library executes them, the part of each spent in explicit
+    inverses (8 n^3 per order-n matrix by Gauss-Jordan), and the operator
+    bytes one sweep must read (16 bytes per complex entry)."""
+    e = p - 2
+    mi, ne = e * e, 4 * e
+    n = mi + ne
+    nl = L * L
+    nb = 4 * L * e
+    inv = {"leaf": nl * 8.0 * n ** 3, "merge": 0.0, "top": 8.0 * nb ** 3}
+    D_bytes = 0.0
+    for l, (cnt, s) in enumerate(level_table(L, p), start=1):
+        nc = child_boundary(l, e)
+        m = nc - s
+        inv["merge"] += cnt * 8.0 * s ** 3
+        D_bytes += cnt * 16.0 * (2 * s) * (2 * m)
+    ops = {
+        # Z^-1, R_root, [S, -(K - I/2)], D per level, Y; u0 written once
+        "solve": 16.0 * (2 * nb * nb + 2 * nb * nb) + D_bytes + 16.0 * nl * mi * ne + 16.0 * nl * mi * M,
+        # H (read, scaled copy written and read), U per level, A2, Z^-1, R_root; u0 read
+        "jvp": 16.0 * 3 * nl * ne * mi + D_bytes + 16.0 * 3 * nb * nb + 16.0 * nl * mi * M,
+        # conjugate-transposed top operators, U per level, H; u0 read
+        "vjp": 16.0 * 2 * nl * ne * mi + D_bytes + 16.0 * 3 * nb * nb + 16.0 * nl * mi * M,
+    }
+    return inv, ops
+
+
+def phase_report(kernels, stats, L, M):
+    """Per stage: wall time (HIP events around the stage), kernel time and
+    algorithmic flops from the launch profiler, the rate against the FP64
+    matrix-core peak counting explicit inverses as executed (8 n^3) and
+    LU-equivalent (8 n^3 / 3, as a factorisation by LU would count them), and
+    for the sweeps the operator bytes and their rate against HBM."""
+    inv, ops = algorithmic_work(L, M)
+    out = {}
+    wall = {"leaf": stats["t_leaf_ms"], "merge": stats["t_merge_ms"], "top": stats["t_top_ms"],
+            "solve": stats["t_solve_ms"], "jvp": stats["t_jvp_ms"], "vjp": stats["t_vjp_ms"]}
+    for ph, ms in wall.items():
+        k = kernels.get(f"phase:{ph}")
+        if k is None or ms <= 0:
+            continue
+        r = {"wall_ms": ms, "kernel_ms": k["total_ms"], "launches": k["launches"], "flops": k["flops"],
+             "tflops": k["flops"] / (ms * 1e-3) / 1e12}
+        r["frac_peak"] = r["tflops"] / PEAK_FP64_TFLOPS
+        if ph in inv:
+            lu = k["flops"] - (2.0 / 3.0) * inv[ph]
+            r.update({"flops_explicit_inverses": inv[ph], "flops_lu_equivalent": lu,
+                      "tflops_lu_equivalent": lu / (ms * 1e-3) / 1e12,
+                      "frac_peak_lu_equivalent": lu / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS})
+        if ph in ops:
+            r.update({"operator_bytes": ops[ph], "gbs": ops[ph] / (ms * 1e-3) / 1e9,
+                      "frac_hbm": ops[ph] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                      "arithmetic_intensity": k["flops"] / ops[ph]})
+        out[ph] = r
+    return out
+
+
+def sweep_small_m(s, k, q, th, R, L, dq, M=16, reps=5):
+    """Sweeps with few right-hand sides on the benchmark grid (the regime
+    where they are bound by HBM, not by the matrix cores): solve, jvp and vjp
+    with M directions, median of reps, with the operator bytes they read."""
+    import torch
+    import synth
+    dirs = synth.equispaced_angles(M)
+    rng = np.random.default_rng(5)
+    r = torch.from_numpy(rng.standard_normal((M, len(th))) + 1j * rng.standard_normal((M, len(th)))).cuda()
+    t = {"solve": [], "jvp": [], "vjp": []}
+    for i in range(reps + 1):
+        s.solve(dirs)
+        s.far_field(th, R)
+        s.jvp(dq)
+        s.vjp(r)
+        st = s.stats()
+        if i > 0:
+            for ph in t:
+                t[ph].append(st[f"t_{ph}_ms"])
+    _, ops = algorithmic_work(L, M)
+    out = {"ndir": M}
+    for ph, v in t.items():
+        ms = float(np.median(v))
+        out[ph] = {"ms": ms, "operator_bytes": ops[ph], "gbs": ops[ph] / (ms * 1e-3) / 1e9,
+                   "frac_hbm": ops[ph] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    return out
+
+
+def recursive_linearization_timing(k_max=20.0):
+    """The recursive linearization of Section 3.4 with the Section 4 protocol
+    (k_j = 1 + j/4 up to k_max, M = floor 2k directions, P = floor 4k
+    receivers at R = 20, band m + n <= floor 2k, leaves per k for >= 10
+    points per wavelength, one Newton step per k with the CG (LSQR) tolerance
+    1e-3, q_1 the projection onto the modes (1,1), (1,2), (2,1)); data from
+    the generator on another discretisation (p = 20, >= 15 points per
+    wavelength), no noise.  Times the inversion only (data made first)."""
+    import torch
+    import synth
+    from paper_1608_06871_amd.drivers import (DataGenerator, RecursiveLinearization, initial_projection,
+                                              paper_schedule)
+    qfn = lambda xy: synth.gaussian_bumps(xy, 5, 2, amp=(0.1, 0.3), width=0.15)
+    sched = paper_schedule(k_max, ppw=10.0)
+    gen = DataGenerator(qfn, p=20, ppw=15.0)
+    data = [gen(st) for st in sched]
+    rl = RecursiveLinearization(sched, lambda st: data[st["j"]], newton_max=1, cg_tol=1e-3, cg_max=200)
+    s0 = rl.solver(sched[0]["L"])
+    coef0 = initial_projection(s0, torch.from_numpy(qfn(s0.node_coords())).cuda(), S=2)
+    # contexts and per-k set-up outside the timed run: one pass at the first k
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    coef, S, log = rl.run(coef0, S0=2, resume=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sl = rl.solver(sched[-1]["L"])
+    qm = sl.sine_eval(coef).cpu().numpy()
+    qt = qfn(sl.node_coords())
+    its = [e["newton"][0]["cg_iters"] for e in log]
+    solves = sum((2 * i + 1) * e["M"] for i, e in zip(its, log))
+    return {"k_max": k_max, "frequencies": len(sched), "seconds": dt, "ms_per_frequency": dt / len(sched) * 1e3,
+            "cg_iters_total": int(sum(its)), "rhs_solves": int(solves), "rhs_solves_per_s": solves / dt,
+            "final_grid_leaves": sched[-1]["L"], "final_modes": sched[-1]["modes"],
+            "final_misfit_rel": log[-1]["newton"][0]["misfit_before"],
+            "model_rel_err": float(np.linalg.norm(qm - qt) / np.linalg.norm(qt)),
+            "protocol": "Section 4 schedule, 10 ppw inversion grids, p=20 data grids at 15 ppw, no noise, "
+                        "1 Newton step per k, CG tol 1e-3; inversion only (data generated before timing)"}
+
+
 # the GEMM kernels and the sources that decide which GEMM calls a step makes
 # (shapes, counts): the stored per-launch traffic holds while none changes
 GEMM_SOURCES = [os.path.join(ROOT, "paper_1608_06871_amd", "csrc", f) for f in ("zgemm.hip", "zinv.hip", "hps.cpp")]
@@ -240,7 +386,7 @@ def batch_problems(n=32, seed0=100):
     return out
 
 
-def run_batch(args):
+def run_batch(args, emit=True):
     """Batched forward solves (factor + solve + far field) of 32 problems in
     one context per leaf grid, against the same problems solved one by one."""
     import torch
@@ -262,7 +408,8 @@ def run_batch(args):
     nrhs = sum(pr["M"] for pr in probs)
     log(f"batch: {len(probs)} problems, {nrhs} directions, grids " +
         ", ".join(f"L={L}: {sum(1 for p in probs if p['L'] == L)}" for L in sorted(coords)))
-    bf = BatchForward(keep_derivs=False)
+    prec = getattr(args, "batch_precision", "fp64")
+    bf = BatchForward(keep_derivs=False, precision=prec)
     t0 = time.perf_counter()
     bf.prepare(probs)
     t_set = time.perf_counter() - t0
@@ -304,15 +451,17 @@ def run_batch(args):
         "metric": "RHS solves/sec, 32 independent (q,k) problems, batched per leaf grid",
         "value": nrhs / dt, "unit": "RHS solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if prec == "fp64" else "c64 sweeps + f64 refinement", "data": "synthetic",
         "config": {"workload": "32 problems (seeds 100-131): k ~ U[10,60], 8x8/16x16/32x32 leaves of 16x16, "
-                               "16-256 directions, 64 angles, R=2, factor + solve + far field, FP64",
-                   "problems": len(probs), "rhs": nrhs},
+                               f"16-256 directions, 64 angles, R=2, factor + solve + far field, {prec}",
+                   "problems": len(probs), "rhs": nrhs, "precision": prec},
         "one_by_one_ms": dt1 * 1e3, "one_by_one_rhs_per_s": nrhs / dt1, "speedup_vs_one_by_one": dt1 / dt,
         "max_rel_diff_vs_one_by_one": maxdiff, "t_wavenumber_setup_s": t_set,
         "gemm_tuning": hps.gemm_tuning_info(),
     }
-    print(json.dumps(res), flush=True)
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -325,6 +474,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-gn", action="store_true", help="skip the Gauss-Newton step timing")
+    ap.add_argument("--no-small-m", action="store_true", help="skip the 16-direction sweep timing")
+    ap.add_argument("--no-rl", action="store_true", help="skip the recursive-linearization timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 32-problem batch")
+    ap.add_argument("--batch-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--tune", choices=["auto", "on", "off"], default="auto",
                     help="GEMM tile autotuning (every distinct GEMM shape times its candidate tile shapes on its "
                          "first call, in the untimed warm-up; results are bitwise the same); auto: on whenever "
@@ -388,7 +541,7 @@ def main():
         step()
         torch.cuda.synchronize()
         log(f"warmup {w + 1}/{args.warmup} done")
-    phases = {"factor": [], "solve": [], "far_field": [], "jvp": [], "vjp": []}
+    phases = {"factor": [], "solve": [], "far_field": [], "jvp": [], "vjp": [], "leaf": [], "merge": [], "top": []}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -413,7 +566,7 @@ def main():
         hps.profile_start()
         step()
         kernels = hps.profile_stop()
-        dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
+        dom = max((n for n in kernels if not n.startswith("phase:")), key=lambda n: kernels[n]["total_ms"])
         kd = kernels[dom]
         per_launch_ms = kd["total_ms"] / kd["launches"]
         if kd["flops"] > 0:
@@ -430,6 +583,17 @@ def main():
                         "launches": kd["launches"], "avg_launch_ms": per_launch_ms,
                         "bytes_per_launch": kd["bytes"] / kd["launches"]}
         log("kernel classes: " + ", ".join(f"{n} {v['total_ms']:.1f} ms/{v['launches']}" for n, v in kernels.items()))
+        med_now = {ph: float(np.median(v)) for ph, v in phases.items()}
+        stage = phase_report(kernels, {f"t_{ph}_ms": v for ph, v in med_now.items()}, L, M)
+        log("stages: " + ", ".join(f"{ph} {v['wall_ms']:.1f} ms {v['tflops']:.1f} TF" for ph, v in stage.items()))
+    else:
+        stage = None
+
+    small_m = None
+    if not args.no_small_m:
+        small_m = sweep_small_m(s, k, q, th, R, L, dq)
+        log("16-direction sweeps: " + ", ".join(f"{ph} {v['ms']:.2f} ms {v['gbs']:.0f} GB/s" for ph, v in small_m.items()
+                                               if isinstance(v, dict)))
 
     gn = None
     if not args.no_gn:
@@ -440,9 +604,28 @@ def main():
 
     mixed = None
     if not args.no_mixed:
+        # far-field error after a fixed number of corrections (the refinement
+        # target set out of reach so that exactly that many are made)
+        del s
+        torch.cuda.empty_cache()
+        per_corr = []
+        for nref in (0, 1, 2):
+            sm = hps.Solver(nleaf=L, p=16, keep_derivs=False, precision="mixed", max_refine=nref, refine_tol=1e-300)
+            sm.factor(q, k)
+            try:
+                sm.solve(dirs)
+            except hps.HpsError as e:
+                if e.code != hps.HPS_ENOCONV:
+                    raise
+            um = sm.far_field(th, R)
+            st = sm.stats()
+            per_corr.append({"corrections": nref, "residual": float(st["refine_residual"]),
+                             "far_field_rel_err_vs_fp64": float((um - ufar).abs().max() / ufar.abs().max())})
+            del sm
+        log("mixed per correction: " + ", ".join(f"{c['corrections']}: res {c['residual']:.1e} "
+                                                 f"err {c['far_field_rel_err_vs_fp64']:.1e}" for c in per_corr))
         # the same workload in mixed precision (complex64 sweeps + refinement),
         # timed the same way, with its far-field error against complex128
-        del s
         torch.cuda.empty_cache()
         sm = hps.Solver(nleaf=L, p=16, keep_derivs=False, precision="mixed")
         sm.set_wavenumber(k)
@@ -463,15 +646,36 @@ def main():
             ms.append(st["t_solve_ms"])
         torch.cuda.synchronize()
         dtm = (time.perf_counter() - t0) / args.steps
-        err = float((um - ufar).abs().pow(2).sum().sqrt() / ufar.abs().pow(2).sum().sqrt())
+        err = float((um - ufar).abs().max() / ufar.abs().max())
         mixed = {"ms_per_factor_solve_farfield": dtm * 1e3, "factor_ms": float(np.median(mf)),
                  "solve_ms": float(np.median(ms)), "rhs_per_s_incl_factor": M / dtm,
                  "solve_only_rhs_per_s": M / (float(np.median(ms)) * 1e-3),
                  "refine_iters": int(st["refine_iters"]), "refine_residual": float(st["refine_residual"]),
-                 "far_field_rel_err_vs_fp64": err}
+                 "refine_tol": sm.refine_tol, "far_field_rel_err_vs_fp64": err, "per_correction": per_corr}
         log(f"mixed: factor {mixed['factor_ms']:.1f} ms, solve {mixed['solve_ms']:.1f} ms, "
             f"{mixed['refine_iters']} corrections, far-field error vs fp64 {err:.2e}")
         del sm
+        if not args.no_gn:
+            torch.cuda.empty_cache()
+            sg = hps.Solver(nleaf=L, p=16, keep_derivs=True, precision="mixed")
+            sg.set_wavenumber(k)
+            mixed["gauss_newton"] = gn_timing(sg, k, dirs, th, R, 1)
+            log(f"mixed gn: {mixed['gauss_newton']['ms_per_gn_step']:.0f} ms per step")
+            del sg
+
+    rl = None
+    if not args.no_rl:
+        torch.cuda.empty_cache()
+        log("recursive linearization to k = 20 ...")
+        rl = recursive_linearization_timing(20.0)
+        log(f"recursive linearization: {rl['frequencies']} frequencies in {rl['seconds']:.2f} s, "
+            f"model error {rl['model_rel_err']:.2e}")
+
+    batch = None
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        batch = run_batch(args, emit=False)
+        log(f"batch32: {batch['value']:.0f} RHS solves/s ({batch['config']['precision']})")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -507,10 +711,15 @@ def main():
         "t_wavenumber_ms": t_wave,
         "device_bytes": dev_bytes,
         "roofline": roofline,
-        "kernels": kernels,
+        "stages": stage,
+        "sweeps_16_directions": small_m,
+        "kernels": {n: v for n, v in kernels.items() if not n.startswith("phase:")} if kernels else None,
         "cpu_baseline": cpu,
         "mixed": mixed,
         "gauss_newton": gn,
+        "recursive_linearization": rl,
+        "batch32": batch,
+        "zinv_pivoting": hps.zinv_pivoting_info(),
         "gemm_tuning": dict(hps.gemm_tuning_info(), mode="autotuned" if tune else "fixed rules"),
     }
     print(json.dumps(out), flush=True)

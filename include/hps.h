@@ -107,7 +107,9 @@ typedef struct hps_ctx hps_ctx;
 
 /* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
  * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1,
- * max_refine = 8, refine_tol = 1e-13. */
+ * max_refine = 8, refine_tol = 1e-10 (the far-field error follows the interface
+ * residual closely, so 1e-10 leaves two orders of margin under a 1e-8 far-field
+ * target; one correction reaches it at k = 80). */
 void hps_default_opts(hps_opts* o);
 
 /* Creates a context for the geometry in *opts (host-side set-up only; device
@@ -228,6 +230,9 @@ typedef struct hps_stats {
   double t_far_field_ms;  /* last hps_far_field (device part) */
   double t_jvp_ms;        /* last hps_jvp */
   double t_vjp_ms;        /* last hps_vjp */
+  double t_leaf_ms;       /* last hps_factor: leaf stage (collocation, inverses, leaf maps) */
+  double t_merge_ms;      /* last hps_factor: merge tree (all levels) */
+  double t_top_ms;        /* last hps_factor: top system Z = A1 + A2 R and its inverse */
   int64_t device_bytes;   /* device memory held by the context */
   int ndir;               /* directions of the last solve */
   int singular;           /* 1 if the last factorisation met a zero pivot */
@@ -358,8 +363,11 @@ typedef struct hps_kernel_stat {
 hps_status hps_profile_start(void);
 
 /* Stops timing, synchronises the device and writes up to `max` per-class
- * totals to out (host array); returns their number (or a negative
- * hps_status). */
+ * totals to out (host array), followed by per-phase totals named
+ * "phase:leaf", "phase:merge", "phase:top", "phase:solve", "phase:far_field",
+ * "phase:jvp", "phase:vjp", "phase:other" (the same launches grouped by the
+ * library call and factorisation stage that issued them); returns their
+ * number (or a negative hps_status). */
 int hps_profile_stop(hps_kernel_stat* out, int max);
 
 #ifdef __cplusplus

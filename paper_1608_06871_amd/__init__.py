@@ -40,6 +40,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("t_wavenumber_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_far_field_ms", ctypes.c_double),
                 ("t_jvp_ms", ctypes.c_double), ("t_vjp_ms", ctypes.c_double),
+                ("t_leaf_ms", ctypes.c_double), ("t_merge_ms", ctypes.c_double), ("t_top_ms", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int),
                 ("nonfinite", ctypes.c_int), ("refine_iters", ctypes.c_int), ("refine_residual", ctypes.c_double)]
 
@@ -148,6 +149,7 @@ class Solver:
         if refine_tol is not None:
             o.refine_tol = float(refine_tol)
         self.precision = precision
+        self.max_refine, self.refine_tol = o.max_refine, o.refine_tol
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -211,16 +213,18 @@ class Solver:
         a = np.asarray(angles, dtype=np.float64)
         if a.ndim <= 1:
             a = np.ascontiguousarray(a.ravel())
-            self._check(lib().hps_solve(self._h, int(a.size), a.ctypes.data_as(ctypes.c_void_p)), "solve")
-            self.ndir = int(a.size)
+            rc = lib().hps_solve(self._h, int(a.size), a.ctypes.data_as(ctypes.c_void_p))
+            nd = int(a.size)
         else:
             if a.shape[0] != self.nprob:
                 raise ValueError(f"need directions for {self.nprob} problems, got {a.shape[0]}")
             a = np.ascontiguousarray(a.reshape(self.nprob, -1))
-            self._check(lib().hps_solve_batch(self._h, int(a.shape[1]), a.ctypes.data_as(ctypes.c_void_p)),
-                        "solve")
-            self.ndir = int(a.shape[1])
-        self.generation += 1
+            rc = lib().hps_solve_batch(self._h, int(a.shape[1]), a.ctypes.data_as(ctypes.c_void_p))
+            nd = int(a.shape[1])
+        if rc in (HPS_OK, HPS_ENOCONV):  # HPS_ENOCONV keeps the (unrefined) fields
+            self.ndir = nd
+            self.generation += 1
+        self._check(rc, "solve")
 
     def far_field(self, thetas, R, out=None):
         torch = _torch()
@@ -431,9 +435,10 @@ def profile_start():
 
 
 def profile_stop():
-    """Stops timing; returns {kernel class: {launches, total_ms, flops, bytes}}."""
-    buf = (KernelStat * 16)()
-    n = lib().hps_profile_stop(buf, 16)
+    """Stops timing; returns {kernel class: {launches, total_ms, flops, bytes}},
+    plus "phase:<name>" entries grouping the same launches by stage."""
+    buf = (KernelStat * 32)()
+    n = lib().hps_profile_stop(buf, 32)
     if n < 0:
         raise HpsError(n, "hps_profile_stop")
     return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,

@@ -126,6 +126,11 @@ enum KernelKind {
   KIND_COUNT
 };
 
+// Stage tags of the launch profiler (process-wide: the stage of the library
+// call that is issuing kernels).
+enum Phase { PH_OTHER = 0, PH_LEAF, PH_MERGE, PH_TOP, PH_SOLVE, PH_FAR, PH_JVP, PH_VJP, PHASE_COUNT };
+void profile_set_phase(int phase);
+
 // RAII: when profiling is on, records HIP events around the kernel launched
 // inside its scope, with that launch's algorithmic flops and bytes.
 class KernelTimer {

@@ -158,9 +158,10 @@ struct hps_ctx {
   int sine_S = 0;
   DBuf dSx, dSy, dNodeGrid, sS1, sS2, sS3;
 
-  hipEvent_t ev[10] = {};  // start/end pairs: factor, solve, far field, jvp, vjp
+  hipEvent_t ev[16] = {};  // start/end pairs: factor, solve, far field, jvp, vjp, and the factor's
+                           // leaf stage, merge tree and top system
   double t_wave = 0.0;
-  bool ev_used[5] = {};
+  bool ev_used[8] = {};
 };
 
 namespace {
@@ -415,6 +416,8 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   c->factored = false;
   c->solved = false;
   mark(c, 0, 0);
+  mark(c, 5, 0);
+  profile_set_phase(PH_LEAF);
   const int ninfo = std::max(nl, P);
   // info[0 .. ninfo): zero pivots per matrix; info[ninfo]: non-finite flags
   // (1: the contrast, 2: the top inverse)
@@ -447,8 +450,11 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   if (c->o.keep_derivs)
     CK(gather_perm(st, ne, mi, T, ne, smo, 1, nullptr, 0, ne, pos, n, n, c->dH.z(), ne, (ll)ne * mi, nl));
   if (c->mixed) CK(hipMemcpyAsync(c->dRleaf.p, Rc, zb((size_t)nl * ne * ne), hipMemcpyDeviceToDevice, st));
+  mark(c, 5, 1);
 
   // merge tree
+  mark(c, 6, 0);
+  profile_set_phase(PH_MERGE);
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
     const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;    const int* i1a = c->didx[4 * l].i();
@@ -524,8 +530,11 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
     }
     Rc = Rn;
   }
+  mark(c, 6, 1);
 
   // top: Z = A1 + A2 R_root per problem, inverted
+  mark(c, 7, 0);
+  profile_set_phase(PH_TOP);
   const ll sbb = (ll)nb * nb;
   CK(hipMemcpyAsync(c->dRroot.p, Rc, zb((size_t)P * sbb), hipMemcpyDeviceToDevice, st));
   double2* Z = c->sA.z();
@@ -538,7 +547,9 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
     CK(conj_transpose(st, nb, c->dZinv.z(), nb, sbb, c->dZinvH.z(), nb, sbb, P));
   }
   CK(flag_nonfinite(st, (const double*)c->dZinv.p, 2 * (ll)P * sbb, 2, nonfinite));
+  mark(c, 7, 1);
   mark(c, 0, 1);
+  profile_set_phase(PH_OTHER);
   std::vector<int> info(ninfo + 1);
   CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * (ninfo + 1), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -799,6 +810,7 @@ void solve(hps_ctx* c, int M, const double* ang) {
   upload(c->d_dirs, c->h_dirs.data(), c->h_dirs.size() * sizeof(double), st);
   c->solved = false;
   mark(c, 1, 0);
+  profile_set_phase(PH_SOLVE);
   const double* kv = c->dPk.d();
   const double* etav = c->dPk.d() + 2 * P;
   const ll sG = 2LL * nb * M, sF = (ll)nb * M, sbb = (ll)nb * nb;
@@ -828,6 +840,7 @@ void solve(hps_ctx* c, int M, const double* ang) {
   CK(zgemm(st, OP_N, OP_N, g.mi, M, g.ne, ONE, c->dY.z(), g.mi, (ll)g.mi * g.ne, Fc, g.ne,
            (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf * P));
   mark(c, 1, 1);
+  profile_set_phase(PH_OTHER);
   c->ndir = M;
   c->solved = true;
 }
@@ -882,9 +895,11 @@ void far_field(hps_ctx* c, int nt, const double* th, double R, double* out) {
   set_measurement(c, nt, th, R);
   const int nb = c->nb, M = c->ndir, P = c->P;
   mark(c, 2, 0);
+  profile_set_phase(PH_FAR);
   CK(zgemm(c->st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, (ll)nt * 2 * nb, c->dST.z(), 2 * nb,
            2LL * nb * M, ZERO, (double2*)out, nt, (ll)nt * M, P));
   mark(c, 2, 1);
+  profile_set_phase(PH_OTHER);
 }
 
 void jvp(hps_ctx* c, const double* dq, double* out) {
@@ -900,6 +915,7 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
   c->sST2.ensure(zb((size_t)2 * P * nb * M));
   c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 3, 0);
+  profile_set_phase(PH_JVP);
   // leaf outgoing data of the body load k^2 dq u0: (H diag(k^2 dq)) u0
   CK(scale_leaf_cols(st, dq, c->dH.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, c->sB.z()));
   double2* Hc = c->dF0.z();
@@ -932,6 +948,7 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
   CK(zgemm(st, OP_N, OP_N, nt, M, 2 * nb, ONE, c->dPhi.z(), nt, (ll)nt * 2 * nb, c->sST2.z(), 2 * nb,
            2LL * nb * M, ZERO, (double2*)out, nt, (ll)nt * M, P));
   mark(c, 3, 1);
+  profile_set_phase(PH_OTHER);
 }
 
 void vjp(hps_ctx* c, const double* r, double* grad) {
@@ -947,6 +964,7 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
   c->sST2.ensure(zb((size_t)2 * P * nb * M));
   c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 4, 0);
+  profile_set_phase(PH_VJP);
   // [sbar; tbar] = Phi^H r
   CK(zgemm(st, OP_C, OP_N, 2 * nb, M, nt, ONE, c->dPhi.z(), nt, (ll)nt * 2 * nb, (const double2*)r, nt,
            (ll)nt * M, ZERO, c->sST2.z(), 2 * nb, 2LL * nb * M, P));
@@ -968,6 +986,7 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
            c->sB.z(), g.ne, (ll)g.ne * g.mi, nl));
   CK(grad_leaf(st, c->dH.z(), c->sB.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, grad));
   mark(c, 4, 1);
+  profile_set_phase(PH_OTHER);
 }
 
 void sine_setup(hps_ctx* c, int S) {
@@ -1171,7 +1190,7 @@ void hps_default_opts(hps_opts* o) {
   o->stream = nullptr;
   o->nprob = 1;
   o->max_refine = 8;
-  o->refine_tol = 1e-13;
+  o->refine_tol = 1e-10;
 }
 
 hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
@@ -1371,6 +1390,9 @@ hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
     out->t_far_field_ms = elapsed_ms(c, 2);
     out->t_jvp_ms = elapsed_ms(c, 3);
     out->t_vjp_ms = elapsed_ms(c, 4);
+    out->t_leaf_ms = elapsed_ms(c, 5);
+    out->t_merge_ms = elapsed_ms(c, 6);
+    out->t_top_ms = elapsed_ms(c, 7);
     out->device_bytes = device_bytes(c);
     out->ndir = c->ndir;
     out->singular = c->singular;

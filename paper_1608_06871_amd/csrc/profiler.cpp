@@ -14,11 +14,14 @@ namespace {
 
 struct Rec {
   hipEvent_t a, b;
-  int kind;
+  int kind, phase;
   double flops, bytes;
 };
 
 std::atomic<bool> g_on{false};
+std::atomic<int> g_phase{0};
+const char* const PHASE_NAMES[PHASE_COUNT] = {"phase:other", "phase:leaf", "phase:merge", "phase:top",
+                                              "phase:solve", "phase:far_field", "phase:jvp", "phase:vjp"};
 std::mutex g_mu;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
@@ -47,7 +50,7 @@ KernelTimer::KernelTimer(hipStream_t st, int kind, double flops, double bytes) {
   hipEvent_t a = take(), b = take();
   if (!a || !b) return;
   if (hipEventRecord(a, st) != hipSuccess) return;
-  g_recs.push_back(Rec{a, b, kind, flops, bytes});
+  g_recs.push_back(Rec{a, b, kind, g_phase.load(std::memory_order_relaxed), flops, bytes});
   idx_ = (long)g_recs.size() - 1;
 }
 
@@ -56,6 +59,8 @@ KernelTimer::~KernelTimer() {
   std::lock_guard<std::mutex> lk(g_mu);
   if (idx_ < (long)g_recs.size()) (void)hipEventRecord(g_recs[idx_].b, st_);
 }
+
+void profile_set_phase(int phase) { g_phase.store(phase, std::memory_order_relaxed); }
 
 }  // namespace hps
 
@@ -73,22 +78,28 @@ int hps_profile_stop(hps_kernel_stat* out, int max) {
   hps::g_on.store(false);
   if (hipDeviceSynchronize() != hipSuccess) return HPS_EDEVICE;
   std::lock_guard<std::mutex> lk(hps::g_mu);
-  hps_kernel_stat acc[hps::KIND_COUNT];
+  hps_kernel_stat acc[hps::KIND_COUNT], ph[hps::PHASE_COUNT];
   std::memset(acc, 0, sizeof(acc));
+  std::memset(ph, 0, sizeof(ph));
   for (int k = 0; k < hps::KIND_COUNT; ++k)
     std::strncpy(acc[k].name, hps::KIND_NAMES[k], sizeof(acc[k].name) - 1);
+  for (int k = 0; k < hps::PHASE_COUNT; ++k)
+    std::strncpy(ph[k].name, hps::PHASE_NAMES[k], sizeof(ph[k].name) - 1);
   for (const auto& r : hps::g_recs) {
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
-    hps_kernel_stat& s = acc[r.kind];
-    s.launches += 1;
-    s.total_ms += ms;
-    s.flops += r.flops;
-    s.bytes += r.bytes;
+    for (hps_kernel_stat* s : {&acc[r.kind], &ph[r.phase]}) {
+      s->launches += 1;
+      s->total_ms += ms;
+      s->flops += r.flops;
+      s->bytes += r.bytes;
+    }
   }
   int n = 0;
   for (int k = 0; k < hps::KIND_COUNT && n < max; ++k)
     if (acc[k].launches > 0 && out) out[n++] = acc[k];
+  for (int k = 0; k < hps::PHASE_COUNT && n < max; ++k)
+    if (ph[k].launches > 0 && out) out[n++] = ph[k];
   hps::g_recs.clear();
   hps::g_used = 0;
   return n;

@@ -255,9 +255,10 @@ class BatchForward:
     lock during its calls), so the launches of small groups overlap the work
     of large ones.  Contexts and streams are kept between calls."""
 
-    def __init__(self, p=16, keep_derivs=False, m_split=64, concurrent=True):
+    def __init__(self, p=16, keep_derivs=False, m_split=64, concurrent=True, precision="fp64"):
         self.p = p
         self.keep_derivs = keep_derivs
+        self.precision = precision
         self.m_split = m_split  # problems with more directions than this batch separately
         self.concurrent = concurrent
         self._ctx = {}
@@ -267,7 +268,8 @@ class BatchForward:
         key = key + (nprob,)
         if key not in self._ctx:
             stream = torch.cuda.Stream() if self.concurrent else None
-            self._ctx[key] = Solver(nleaf=L, p=self.p, nprob=nprob, keep_derivs=self.keep_derivs, stream=stream)
+            self._ctx[key] = Solver(nleaf=L, p=self.p, nprob=nprob, keep_derivs=self.keep_derivs, stream=stream,
+                                    precision=self.precision)
         return self._ctx[key]
 
     def groups(self, problems):

@@ -1,7 +1,7 @@
 """Mixed precision (complex64 sweeps refined on the skeleton system) against
 the complex128 path and the oracle: the far field, the total field and the
-derivatives must agree to <= 1e-8 relative (the refinement target is 1e-13
-on the interface residual, so in practice they agree to ~1e-12)."""
+derivatives must agree to <= 1e-8 relative (the default refinement target is
+1e-10 on the interface residual; one correction reaches ~1e-12)."""
 import numpy as np
 import pytest
 
@@ -39,7 +39,7 @@ def test_mixed_far_field_matches_fp64(L, k, M):
     print(f"  rel err {err:.2e}, {st['refine_iters']} corrections, residual {st['refine_residual']:.2e}",
           flush=True)
     assert 1 <= st["refine_iters"] <= 4
-    assert st["refine_residual"] <= 1e-13
+    assert st["refine_residual"] <= 1e-10
     assert err <= 1e-8
 
 
