@@ -916,12 +916,21 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
   c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 3, 0);
   profile_set_phase(PH_JVP);
-  // leaf outgoing data of the body load k^2 dq u0: (H diag(k^2 dq)) u0
-  CK(scale_leaf_cols(st, dq, c->dH.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, c->sB.z()));
+  // leaf outgoing data of the body load k^2 dq u0: H (k^2 dq u0).  With many
+  // directions H diag(k^2 dq) is formed (ne x mi per leaf, fewer bytes than
+  // the scaled fields); with fewer than ne directions the fields are scaled
+  // (mi x M per leaf) and H is read once.
   double2* Hc = c->dF0.z();
   double2* Ho = c->dF1.z();
-  CK(zgemm(st, OP_N, OP_N, g.ne, M, g.mi, ONE, c->sB.z(), g.ne, (ll)g.ne * g.mi, c->du0.z(), g.mi,
-           (ll)g.mi * M, ZERO, Hc, g.ne, (ll)g.ne * M, nl));
+  if (M < g.ne) {
+    CK(scale_leaf_rows(st, dq, c->du0.z(), c->dPk.d() + P, g.mi, M, nl, g.nleaf, c->sB.z()));
+    CK(zgemm(st, OP_N, OP_N, g.ne, M, g.mi, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, c->sB.z(), g.mi,
+             (ll)g.mi * M, ZERO, Hc, g.ne, (ll)g.ne * M, nl));
+  } else {
+    CK(scale_leaf_cols(st, dq, c->dH.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, c->sB.z()));
+    CK(zgemm(st, OP_N, OP_N, g.ne, M, g.mi, ONE, c->sB.z(), g.ne, (ll)g.ne * g.mi, c->du0.z(), g.mi,
+             (ll)g.mi * M, ZERO, Hc, g.ne, (ll)g.ne * M, nl));
+  }
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
     const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;
@@ -980,11 +989,19 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
     down_level(c, l, OP_C, c->dU[l].z(), Hc, Ho, M);
     std::swap(Hc, Ho);
   }
-  // grad = k^2 Re sum_dir conj(u0) (H^H g), summed over the directions first:
-  // Q^T = g u0^H per leaf (ne x mi), then grad_n = k^2 Re sum_e conj(H_en) Q^T_en
-  CK(zgemm(st, OP_N, OP_C, g.ne, g.mi, M, ONE, Hc, g.ne, (ll)g.ne * M, c->du0.z(), g.mi, (ll)g.mi * M, ZERO,
-           c->sB.z(), g.ne, (ll)g.ne * g.mi, nl));
-  CK(grad_leaf(st, c->dH.z(), c->sB.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, grad));
+  // grad = k^2 Re sum_dir conj(u0) (H^H g).  Many directions: summed over the
+  // directions first, Q^T = g u0^H per leaf (ne x mi), then
+  // grad_n = k^2 Re sum_e conj(H_en) Q^T_en.  Fewer than ne directions:
+  // W = H^H g (mi x M per leaf, H read once), then the sum over directions.
+  if (M < g.ne) {
+    CK(zgemm(st, OP_C, OP_N, g.mi, M, g.ne, ONE, c->dH.z(), g.ne, (ll)g.ne * g.mi, Hc, g.ne, (ll)g.ne * M, ZERO,
+             c->sB.z(), g.mi, (ll)g.mi * M, nl));
+    CK(grad_rows(st, c->du0.z(), c->sB.z(), c->dPk.d() + P, g.mi, M, nl, g.nleaf, grad));
+  } else {
+    CK(zgemm(st, OP_N, OP_C, g.ne, g.mi, M, ONE, Hc, g.ne, (ll)g.ne * M, c->du0.z(), g.mi, (ll)g.mi * M, ZERO,
+             c->sB.z(), g.ne, (ll)g.ne * g.mi, nl));
+    CK(grad_leaf(st, c->dH.z(), c->sB.z(), c->dPk.d() + P, g.ne, g.mi, nl, g.nleaf, grad));
+  }
   mark(c, 4, 1);
   profile_set_phase(PH_OTHER);
 }

@@ -62,6 +62,13 @@ hipError_t boundary_st_adj(hipStream_t st, const double2* STb, int nb, int ncol,
 // the outgoing-impedance maps.
 hipError_t scale_leaf_cols(hipStream_t st, const double* dq, const double2* H, const double* k2v, int ne, int mi,
                            ll nleaf, ll lpp, double2* Hs);
+// out = k^2 dq u0 per leaf (mi x M, u0's layout): the Frechet body load for
+// the product H (k^2 dq u0) when few directions make that cheaper.
+hipError_t scale_leaf_rows(hipStream_t st, const double* dq, const double2* u0, const double* k2v, int mi, int M,
+                           ll nleaf, ll lpp, double2* out);
+// grad[z mi + n] = k^2 Re sum_m conj(u0[n][m]) W[n][m] per leaf (W = H^H g).
+hipError_t grad_rows(hipStream_t st, const double2* u0, const double2* W, const double* k2v, int mi, int M,
+                     ll nleaf, ll lpp, double* grad);
 // grad[z mi + n] = k^2 Re sum_e conj(H[e][n]) QT[e][n] per leaf.
 hipError_t grad_leaf(hipStream_t st, const double2* H, const double2* QT, const double* k2v, int ne, int mi,
                      ll nleaf, ll lpp, double* grad);

@@ -568,6 +568,58 @@ hipError_t scale_leaf_cols(hipStream_t st, const double* dq, const double2* H, c
   return hipGetLastError();
 }
 
+// Few directions: the body load k^2 dq u0 itself (mi x M per leaf, the
+// layout of u0), so that H is read once by the product H (k^2 dq u0) instead
+// of being scaled into a copy.
+__global__ void k_scale_leaf_rows(const double* dq, const double2* u0, const double* k2v, int mi, int M, ll nleaf,
+                                  ll lpp, double2* out) {
+  const ll per = (ll)mi * M;
+  const ll total = per * nleaf;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll z = idx / per;
+    const int n = (int)(idx % per) % mi;
+    const double s = k2v[z / lpp] * dq[z * mi + n];
+    const double2 u = u0[idx];
+    out[idx] = make_double2(s * u.x, s * u.y);
+  }
+}
+
+// Few directions: grad[z mi + n] = k^2 Re sum_m conj(u0[n][m]) W[n][m] with
+// W = H^H g formed by a product (mi x M per leaf); one thread per node, the
+// directions summed in order.
+__global__ void k_grad_rows(const double2* u0, const double2* W, const double* k2v, int mi, int M, ll nleaf, ll lpp,
+                            double* grad) {
+  const ll total = (ll)mi * nleaf;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll z = idx / mi;
+    const int n = (int)(idx % mi);
+    const ll base = z * (ll)mi * M + n;
+    double acc = 0.0;
+    for (int m = 0; m < M; ++m) {
+      const double2 u = u0[base + (ll)m * mi], w = W[base + (ll)m * mi];
+      acc += u.x * w.x + u.y * w.y;
+    }
+    grad[idx] = k2v[z / lpp] * acc;
+  }
+}
+
+hipError_t scale_leaf_rows(hipStream_t st, const double* dq, const double2* u0, const double* k2v, int mi, int M,
+                           ll nleaf, ll lpp, double2* out) {
+  const ll total = (ll)mi * M * nleaf;
+  KernelTimer kt(st, K_POINT, 6.0 * (double)total, 40.0 * (double)total);
+  hipLaunchKernelGGL(k_scale_leaf_rows, dim3(blocks_for(total)), dim3(NT), 0, st, dq, u0, k2v, mi, M, nleaf, lpp,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t grad_rows(hipStream_t st, const double2* u0, const double2* W, const double* k2v, int mi, int M,
+                     ll nleaf, ll lpp, double* grad) {
+  KernelTimer kt(st, K_POINT, 4.0 * M * (double)mi * nleaf, (32.0 * M + 8.0) * mi * (double)nleaf);
+  hipLaunchKernelGGL(k_grad_rows, dim3(blocks_for((ll)mi * nleaf)), dim3(NT), 0, st, u0, W, k2v, mi, M, nleaf, lpp,
+                     grad);
+  return hipGetLastError();
+}
+
 hipError_t grad_leaf(hipStream_t st, const double2* H, const double2* QT, const double* k2v, int ne, int mi,
                      ll nleaf, ll lpp, double* grad) {
   KernelTimer kt(st, K_POINT, 4.0 * ne * (double)mi * nleaf, (32.0 * ne + 8.0) * mi * (double)nleaf);

@@ -518,12 +518,17 @@ hipError_t splitk_workspace(hipStream_t st, size_t bytes, void** out) {
 // and a long K: about two workgroups per compute unit, slices of at least
 // 512 (a split costs a reduction pass, so shapes that already fill the chip
 // are left alone).
+// Products with at most 32 columns (sweeps with few right-hand sides) are
+// bound by streaming A, so they take thinner slices (at least 256) and aim at
+// about 2048 workgroups to keep more loads in flight.
 int choose_splits(int M, int N, int K, int batch) {
   const ll tiles = (ll)((M + 63) / 64) * ((N + 31) / 32) * batch;
-  if (tiles >= 256 || K < 1024) return 1;
-  ll s = (512 + tiles - 1) / tiles;
-  if (s > K / 512) s = K / 512;
-  if (s > 16) s = 16;
+  const bool skinny = N <= 32;
+  const ll target = skinny ? 2048 : 512, slice = skinny ? 256 : 512, most = skinny ? 32 : 16;
+  if (tiles >= (skinny ? 1024 : 256) || K < 1024) return 1;
+  ll s = (target + tiles - 1) / tiles;
+  if (s > K / slice) s = K / slice;
+  if (s > most) s = most;
   return s < 2 ? 1 : (int)s;
 }
 template <int WM, int WN, bool M3, int TK, int WAVES, bool DB = false>

@@ -143,3 +143,23 @@ def test_nonfinite_contrast_is_reported():
     assert s.stats()["nonfinite"] == 0
     s.solve(directions(M))
     assert _rel(s.far_field(th, 2.0).cpu().numpy(), prob.far_field()) < 1e-9
+
+
+@pytest.mark.parametrize("M", [4, 55, 56, 64])
+def test_jvp_vjp_leaf_orders_match_oracle(M):
+    """The leaf terms of the derivatives are formed in one of two orders by
+    the direction count (fewer than the 56 edge nodes: scaled fields and
+    H^H g; else scaled H and g u0^H); both against the oracle."""
+    torch = _torch()
+    L, k, P = 2, 5.0, 8
+    print(f"jvp/vjp leaf order M={M}", flush=True)
+    prob, q, th = _case(L, k, M, P, 3)
+    s = _solver(L)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    s.solve(directions(M))
+    s.far_field(th, 2.0)
+    rng = np.random.default_rng(M)
+    dq = synth.gaussian_bumps(prob.grid.pde_coords(), 3, 7) + 0.1 * rng.standard_normal(prob.grid.npde)
+    assert _rel(s.jvp(torch.from_numpy(dq).cuda()).cpu().numpy(), prob.jvp(dq)) < 1e-9
+    r = rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))
+    assert _rel(s.vjp(torch.from_numpy(r).cuda()).cpu().numpy(), prob.vjp(r)) < 1e-9

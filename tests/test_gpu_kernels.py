@@ -379,3 +379,27 @@ def test_zinv_butterfly_singular_falls_back_and_reports():
     with pytest.raises(hps.HpsError) as e:
         hps.zinv(_colmajor(torch, A))
     assert e.value.code == hps.HPS_ESINGULAR
+
+
+@pytest.mark.parametrize("M,N,K,batch", [(2000, 16, 4000, 1), (100, 5, 3000, 3), (28, 16, 84, 50), (1, 1, 2000, 2),
+                                         (130, 9, 17, 4), (700, 3, 1024, 2), (64, 16, 1, 1)])
+def test_zgemm_few_columns_matches_cpu(M, N, K, batch):
+    """Products with at most 16 columns (the sweeps with few right-hand
+    sides; long K is split into thin slices reduced in a fixed order):
+    against complex128 on the CPU, and the same bits on a second call."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    print(f"zgemm few columns M={M} N={N} K={K} batch={batch}", flush=True)
+    rng = np.random.default_rng(M + 7 * N + K)
+    A, B, C0 = _rand(rng, (batch, M, K)), _rand(rng, (batch, K, N)), _rand(rng, (batch, M, N))
+    alpha, beta = 0.7 - 0.3j, -0.5 + 0.25j
+    ref = alpha * (A @ B) + beta * C0
+    outs = []
+    for rep in range(2):
+        C = _colmajor(torch, C0)
+        hps.zgemm(_colmajor(torch, A), _colmajor(torch, B), C, alpha=alpha, beta=beta)
+        torch.cuda.synchronize()
+        outs.append(_back(C))
+    scale = np.abs(A) @ np.abs(B) + np.abs(C0)
+    assert np.max(np.abs(outs[0] - ref) / scale) < 1e-14
+    assert np.array_equal(outs[0], outs[1])
