@@ -654,6 +654,114 @@ __global__ __launch_bounds__(64 * NPW) void np_block(const double2* Aall, ll lda
   }
 }
 
+// Wide pivot-free panel block: IB = D^-1 for the b x b diagonal block
+// D[i][j] = A[c0 + i][c0 + j] (b <= 128) by Gauss-Jordan on the diagonal
+// (the matrix was mixed by the butterfly transform; the probe check and the
+// pivoted fallback guard the result), records sig / pos of the panel, and
+// sets info on an exactly zero pivot.  1024 threads: thread t holds the 4 x 4
+// tile of rows 4 (t & 31) + i and columns 4 (t >> 5) + j.  Per column the
+// pivot row and the column itself are posted to LDS (double-buffered by
+// column parity, one barrier per column); a thread reads 4 values of each and
+// updates its tile with new = a v + b pr (a = 0, b = 1/piv on the pivot row;
+// a = 1, b = -A[r][c]/piv elsewhere).  Columns go in groups of four so that
+// the position inside a tile is a compile-time index.
+constexpr int WPW = 128;  // wide panel width
+__global__ __launch_bounds__(1024) void np_wide_block(const double2* Aall, ll lda, ll sA, int c0, int b,
+                                                      double2* IB_all, int* sig_all, int* pos_all, int n,
+                                                      int* info) {
+  __shared__ double2 prow[2][WPW];
+  __shared__ double2 pcol[2][WPW];
+  const ll bi = blockIdx.x;
+  const int t = threadIdx.x, rb = t & 31, cb = t >> 5;
+  const double2* A = Aall + bi * sA;
+  double2 v[4][4];
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = 4 * rb + ii, j = 4 * cb + jj;
+      v[ii][jj] = (r < b && j < b) ? A[(ll)(c0 + r) + (ll)(c0 + j) * lda] : make_double2(r == j ? 1.0 : 0.0, 0.0);
+    }
+  bool zero_seen = false;
+  for (int c4 = 0; c4 < b; c4 += 4) {
+    const bool rowg = (rb == (c4 >> 2)), colg = (cb == (c4 >> 2));
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const int c = c4 + cc;
+      if (c < b) {  // uniform
+        const int cur = cc & 1;
+        if (rowg) {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) prow[cur][4 * cb + jj] = v[cc][jj];
+        }
+        if (colg) {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) pcol[cur][4 * rb + ii] = v[ii][cc];
+        }
+        __syncthreads();
+        const double2 piv = pcol[cur][c];
+        double2 pr[4], pc[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) pr[jj] = prow[cur][4 * cb + jj];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) pc[ii] = pcol[cur][4 * rb + ii];
+        const bool zero = (piv.x == 0.0 && piv.y == 0.0);
+        zero_seen = zero_seen || zero;
+        const double2 inv = zero ? make_double2(0.0, 0.0) : crecip(piv);
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const bool prowl = (rowg && ii == cc);
+          const double2 g = cmul(pc[ii], inv);
+          const double a = prowl ? 0.0 : 1.0;
+          const double2 bb = prowl ? inv : make_double2(-g.x, -g.y);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            double2 x;
+            x.x = fma(bb.x, pr[jj].x, fma(-bb.y, pr[jj].y, a * v[ii][jj].x));
+            x.y = fma(bb.x, pr[jj].y, fma(bb.y, pr[jj].x, a * v[ii][jj].y));
+            v[ii][jj] = x;
+          }
+          if (colg) v[ii][cc] = bb;
+        }
+      }
+    }
+  }
+  double2* IB = IB_all + bi * (ll)WPW * WPW;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = 4 * rb + ii, j = 4 * cb + jj;
+      if (r < b && j < b) IB[r + (ll)j * b] = v[ii][jj];
+    }
+  if (zero_seen && t == 0) info[bi] = 1;
+  int* sig = sig_all + bi * n;
+  int* pos = pos_all + bi * n;
+  if (t < b) {
+    sig[c0 + t] = c0 + t;
+    pos[c0 + t] = c0 + t;
+  }
+}
+
+// T[i + j n] = A[i][c0 + j] for i < n, j < b (copy of a wide panel's columns).
+__global__ void k_copy_cols(const double2* Aall, ll lda, ll sA, int c0, int n, int b, double2* Tall, ll sT) {
+  const ll bi = blockIdx.y;
+  const ll e = (ll)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (ll)n * b) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  Tall[bi * sT + e] = Aall[bi * sA + (ll)i + (ll)(c0 + j) * lda];
+}
+
+// A[c0 + i][c0 + j] = IB[i + j b] for i, j < b (the pivot rows of a wide
+// panel after the exchange product).
+__global__ void k_put_block(double2* Aall, ll lda, ll sA, int c0, int b, const double2* IB_all) {
+  const ll bi = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b * b) return;
+  const int i = e % b, j = e / b;
+  Aall[bi * sA + (ll)(c0 + i) + (ll)(c0 + j) * lda] = IB_all[bi * (ll)WPW * WPW + e];
+}
+
 // Depth-2 random butterfly transform (Parker 1995; as used for pivot-free
 // LU by Baboulin, Dongarra, Herrmann and Tomov 2013).  A butterfly of order
 // 2h is B = (1/sqrt 2) [R0 R1; R0 -R1] with random diagonal R0, R1 whose
@@ -808,6 +916,8 @@ struct Inv {
   int* candB;
   int* info;
   bool nopiv;  // pivot rows = the panel's own rows (after a butterfly transform)
+  double2* IBw;  // wide pivot-free panels: block inverses (batch x 128 x 128)
+  double2* Tw;   // and copies of the panel columns (batch x n x 128); null: 32-column panels
 };
 
 hipError_t launch_panel(const Inv& v, int c0, int bw) {
@@ -888,6 +998,31 @@ hipError_t np_panel(const Inv& v, int c0, int bw) {
   return hipGetLastError();
 }
 
+// Wide pivot-free panel (b <= 128 columns): block inverse IB of the
+// diagonal block, then the exchange of the panel columns as one product,
+// A[:, panel] = -A_old[:, panel] IB on every row, and the pivot rows (which
+// that gives as -I) set to IB.
+hipError_t np_wide_panel(const Inv& v, int c0, int bw) {
+  {
+    KernelTimer kt(v.st, K_GJ_PANEL, 8.0 * (double)bw * bw * bw * v.batch, 32.0 * (double)bw * bw * v.batch);
+    hipLaunchKernelGGL(np_wide_block, dim3(v.batch), dim3(1024), 0, v.st, v.work, v.lda, v.sA, c0, bw, v.IBw,
+                       v.sig, v.pos, v.n, v.info);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  const ll sTw = (ll)v.n * WPW;
+  {
+    KernelTimer kt(v.st, K_MOVE, 0.0, 32.0 * (double)v.n * bw * v.batch);
+    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)(((ll)v.n * bw + NT - 1) / NT), v.batch), dim3(NT), 0, v.st,
+                       v.work, v.lda, v.sA, c0, v.n, bw, v.Tw, sTw);
+  }
+  HPS_HIP_TRY(hipGetLastError());
+  HPS_HIP_TRY(zgemm(v.st, OP_N, OP_N, v.n, bw, bw, make_double2(-1.0, 0.0), v.Tw, v.n, sTw, v.IBw, bw,
+                    (ll)WPW * WPW, make_double2(0.0, 0.0), v.work + (ll)c0 * v.lda, v.lda, v.sA, v.batch));
+  hipLaunchKernelGGL(k_put_block, dim3((unsigned)((bw * bw + 255) / 256), v.batch), dim3(256), 0, v.st, v.work,
+                     v.lda, v.sA, c0, bw, v.IBw);
+  return hipGetLastError();
+}
+
 hipError_t wide_panel(const Inv& v, int c0, int bw) {
   return v.nopiv ? np_panel(v, c0, bw) : tournament_panel(v, c0, bw);
 }
@@ -954,10 +1089,11 @@ hipError_t side_stream(hipStream_t st, hipStream_t* out) {
 // recursive blocking restricted to its own columns (32-column pivot-free
 // leaves, all rows), with its pivot-row copies in the part of T after the
 // look-ahead's own w x n copies (the side stream still reads those).
-int lookahead_width(int n, bool nopiv) {
-  if (!nopiv) return BMAX;
+int lookahead_width(const Inv& v) {
+  if (!v.nopiv) return BMAX;
+  if (v.IBw && (size_t)WPW * v.n <= t_elems(v.n)) return WPW;  // wide panels: one block inverse each
   for (int w = 4 * BMAX; w > BMAX; w -= BMAX)
-    if ((size_t)w * n + t_elems_block(w) <= t_elems(n)) return w;
+    if ((size_t)w * v.n + t_elems_block(w) <= t_elems(v.n)) return w;
   return BMAX;
 }
 
@@ -965,7 +1101,8 @@ hipError_t process_block(const Inv& v, int c0, int c1);
 
 hipError_t lookahead_inverse(const Inv& v) {
   const int n = v.n;
-  const int PW = lookahead_width(n, v.nopiv);
+  const int PW = lookahead_width(v);
+  const bool wide = v.nopiv && PW == WPW && v.IBw;
   Inv vp = v;  // in-panel elimination: pivot-row copies after the look-ahead's
   vp.T = v.T + (ll)PW * n;
   hipStream_t X = nullptr;
@@ -976,7 +1113,9 @@ hipError_t lookahead_inverse(const Inv& v) {
   bool pending = false;  // an update on X not yet waited for
   for (int c0 = 0; c0 < n && err == hipSuccess; c0 += PW) {
     const int b = n - c0 < PW ? n - c0 : PW;
-    if ((err = (b <= BMAX ? wide_panel(v, c0, b) : process_block(vp, c0, c0 + b))) != hipSuccess) break;
+    if ((err = (wide ? np_wide_panel(v, c0, b) : b <= BMAX ? wide_panel(v, c0, b) : process_block(vp, c0, c0 + b))) !=
+        hipSuccess)
+      break;
     const int c1 = c0 + b;
     const int b1 = n - c1 < PW ? n - c1 : PW;  // next panel (0 after the last)
     // the pivot rows of panel p in every column, once X has applied panel p-1
@@ -1119,6 +1258,8 @@ size_t zinv_workspace(int n, int batch) {
     bytes += align256((size_t)batch * n * n * sizeof(double2));            // transformed matrix
     bytes += 3 * align256((size_t)batch * n * NPROBE * sizeof(double2));   // probes X0, Y, X1
     bytes += align256((size_t)batch * sizeof(double));                     // probe errors
+    bytes += align256((size_t)batch * WPW * WPW * sizeof(double2));        // wide-panel block inverses
+    bytes += align256((size_t)batch * n * WPW * sizeof(double2));          // wide-panel column copies
   }
   return bytes;
 }
@@ -1128,9 +1269,11 @@ namespace {
 // Elimination without the final permutation; v.sig / v.pos left in ws.
 // nopiv: pivot-free panels (sig / pos end as the identity).
 hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int batch, void* ws, int* info, Inv& v,
-                     bool nopiv = false) {
+                     bool nopiv = false, double2* wide_ws = nullptr) {
   char* p = (char*)ws;
   v.nopiv = nopiv;
+  v.IBw = wide_ws;
+  v.Tw = wide_ws ? wide_ws + (ll)batch * WPW * WPW : nullptr;
   v.st = st;
   v.n = n;
   v.batch = batch;
@@ -1191,6 +1334,8 @@ hipError_t rbt_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, doub
   double2* X1 = (double2*)p;
   p += align256((size_t)batch * per * sizeof(double2));
   double* err = (double*)p;
+  p += align256((size_t)batch * sizeof(double));
+  double2* wide_ws = (double2*)p;  // block inverses, then column copies (contiguous: see zinv_workspace)
   const dim3 tg((m + 255) / 256, m, batch);
   {
     KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)nn * batch);
@@ -1198,7 +1343,7 @@ hipError_t rbt_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, doub
   }
   HPS_HIP_TRY(hipGetLastError());
   Inv v{};
-  HPS_HIP_TRY(zinv_core(st, n, T, n, nn, batch, ws, info, v, true));
+  HPS_HIP_TRY(zinv_core(st, n, T, n, nn, batch, ws, info, v, true, wide_ws));
   {
     KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)nn * batch);
     hipLaunchKernelGGL(k_rbt, tg, dim3(256), 0, st, T, (ll)n, nn, out, ldo, sO, m, RBT_SEED_V, 0, RBT_SEED_U, 1);
