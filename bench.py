@@ -610,7 +610,8 @@ def main():
         torch.cuda.empty_cache()
         per_corr = []
         for nref in (0, 1, 2):
-            sm = hps.Solver(nleaf=L, p=16, keep_derivs=False, precision="mixed", max_refine=nref, refine_tol=1e-300)
+            sm = hps.Solver(nleaf=L, p=16, keep_derivs=False, precision="mixed", max_refine=nref, refine_tol=1e-300,
+                            fallback_fp64=False)
             sm.factor(q, k)
             try:
                 sm.solve(dirs)

@@ -101,13 +101,16 @@ typedef struct hps_opts {
   int nprob;             /* independent problems on this grid (1 .. 4096); see Batches */
   int max_refine;        /* HPS_MIXED: most refinement corrections per solve (0 .. 100) */
   double refine_tol;     /* HPS_MIXED: relative residual target (> 0) */
+  int fallback_fp64;     /* HPS_MIXED: non-zero: a solve whose refinement stops above refine_tol
+                            redoes its sweep in complex128 (exact FP64 result, refine_fallback = 1
+                            in hps_stats) instead of returning HPS_ENOCONV */
 } hps_opts;
 
 typedef struct hps_ctx hps_ctx;
 
 /* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
  * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1,
- * max_refine = 8, refine_tol = 1e-10 (the far-field error follows the interface
+ * max_refine = 8, fallback_fp64 = 1, refine_tol = 1e-10 (the far-field error follows the interface
  * residual closely, so 1e-10 leaves two orders of margin under a 1e-8 far-field
  * target; one correction reaches it at k = 80). */
 void hps_default_opts(hps_opts* o);
@@ -239,6 +242,7 @@ typedef struct hps_stats {
   int nonfinite;          /* last factorisation: bit 0 non-finite contrast, bit 1 non-finite top inverse */
   int refine_iters;       /* HPS_MIXED: corrections made by the last solve */
   double refine_residual; /* HPS_MIXED: its final relative interface residual */
+  int refine_fallback;    /* HPS_MIXED: 1 if the last solve redid its sweep in complex128 */
 } hps_stats;
 
 /* Timings of the last calls (synchronises the stream) and memory use. */
@@ -306,7 +310,7 @@ hps_status hps_zinv_blocking(int mode);
 /* Pivoting of the explicit inverses of hps_zinv and of the factorisation's
  * W and Z inverses (the merges and the top of the Section 2 direct solver
  * only use the products with W^{-1} and Z^{-1}), process-wide:
- *   mode -1 (default): orders above 512 that are multiples of 4 are first
+ *   mode -1 (default): orders of at least 224 that are multiples of 4 are first
  *           mixed by a depth-2 random butterfly transform (Parker 1995;
  *           Baboulin, Dongarra, Herrmann, Tomov 2013), A~ = U^T A V, then
  *           eliminated without searching the rows for pivots (Gauss-Jordan

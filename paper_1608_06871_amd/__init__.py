@@ -33,7 +33,7 @@ class Opts(ctypes.Structure):
                 ("eta_scale", ctypes.c_double), ("keep_derivs", ctypes.c_int),
                 ("precision", ctypes.c_int), ("host_threads", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("nprob", ctypes.c_int), ("max_refine", ctypes.c_int),
-                ("refine_tol", ctypes.c_double)]
+                ("refine_tol", ctypes.c_double), ("fallback_fp64", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("t_jvp_ms", ctypes.c_double), ("t_vjp_ms", ctypes.c_double),
                 ("t_leaf_ms", ctypes.c_double), ("t_merge_ms", ctypes.c_double), ("t_top_ms", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int),
-                ("nonfinite", ctypes.c_int), ("refine_iters", ctypes.c_int), ("refine_residual", ctypes.c_double)]
+                ("nonfinite", ctypes.c_int), ("refine_iters", ctypes.c_int), ("refine_residual", ctypes.c_double),
+                ("refine_fallback", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
@@ -130,7 +131,7 @@ class Solver:
 
     def __init__(self, nleaf=4, p=16, box=(-1.0, 1.0, -1.0, 1.0), eta_scale=1.0,
                  keep_derivs=True, host_threads=0, stream=None, nprob=1, precision="fp64",
-                 max_refine=None, refine_tol=None):
+                 max_refine=None, refine_tol=None, fallback_fp64=None):
         torch = _torch()
         L = lib()
         o = Opts()
@@ -148,6 +149,8 @@ class Solver:
             o.max_refine = int(max_refine)
         if refine_tol is not None:
             o.refine_tol = float(refine_tol)
+        if fallback_fp64 is not None:
+            o.fallback_fp64 = 1 if fallback_fp64 else 0
         self.precision = precision
         self.max_refine, self.refine_tol = o.max_refine, o.refine_tol
         if stream is None:
@@ -401,7 +404,7 @@ def zinv_blocking(mode=-1):
 
 def zinv_pivoting(mode=-1, tol=-1.0):
     """Pivoting of the large explicit inverses (process-wide): -1 butterfly
-    transform + pivot-free elimination above order 512 (probe-checked, with a
+    transform + pivot-free elimination from order 224 (probe-checked, with a
     pivoted fallback), 0 always pivoted, 1 butterfly for every multiple of 4;
     tol >= 0 sets the probe tolerance (-1 keeps it)."""
     rc = lib().hps_zinv_pivoting(int(mode), float(tol))

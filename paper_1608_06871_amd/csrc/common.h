@@ -56,7 +56,7 @@ int gemm_variant_count();
 void zinv_set_blocking(int mode);
 
 // Pivoting of zinv (process-wide): -1 butterfly transform + pivot-free
-// elimination for orders above 512 (checked on probe vectors, pivoted
+// elimination for orders of at least 224 (checked on probe vectors, pivoted
 // fallback), 0 always pivoted, 1 butterfly for every order that is a multiple
 // of 4; tol >= 0 sets the probe-check tolerance.
 void zinv_set_pivoting(int mode, double tol);

@@ -118,6 +118,7 @@ struct hps_ctx {
   bool mixed = false;
   int refine_iters = 0;
   double refine_res = 0.0;
+  int refine_fallback = 0;  // last solve fell back to the complex128 sweep
   DBuf dRleaf;                              // leaf ItI maps (complex128)
   std::vector<DBuf> dD32, dU32, dE32;       // complex64 sweep operators per level
   DBuf sE;                                  // h-to-f3 maps before conversion
@@ -792,6 +793,24 @@ void solve_mixed(hps_ctx* c, int M, const double2* Fc) {
            (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf * P));
 }
 
+// complex128 sweep from the root data Fc (= Z^-1 rhs): boundary (s, t), the
+// down-sweep through the levels and u0 = Y f at the leaves.  Fo is scratch.
+void solve_fp64(hps_ctx* c, int M, double2* Fc, double2* Fo) {
+  const Geometry& g = c->g;
+  hipStream_t st = c->st;
+  const int P = c->P, nb = c->nb;
+  const ll sF = (ll)nb * M, sbb = (ll)nb * nb;
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, Fc, nb, sF, ZERO, c->dg.z(), nb, sF,
+           P));
+  CK(boundary_st(st, Fc, c->dg.z(), c->dG.z(), nb, M, c->dPk.d() + 2 * P, c->dST.z(), P));
+  for (int l = g.nlev; l >= 1; --l) {
+    down_level(c, l, OP_N, c->dD[l].z(), Fc, Fo, M);
+    std::swap(Fc, Fo);
+  }
+  CK(zgemm(st, OP_N, OP_N, g.mi, M, g.ne, ONE, c->dY.z(), g.mi, (ll)g.mi * g.ne, Fc, g.ne,
+           (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf * P));
+}
+
 // ang: P x M direction angles (problem-major).
 void solve(hps_ctx* c, int M, const double* ang) {
   require(c->factored, HPS_ESTATE, "hps_solve before hps_factor");
@@ -821,24 +840,24 @@ void solve(hps_ctx* c, int M, const double* ang) {
   double2* Fo = c->dF1.z();
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, sbb, c->dRhs.z(), nb, sF, ZERO, Fc, nb, sF,
            P));
+  c->refine_fallback = 0;
   if (c->mixed) {
     solve_mixed(c, M, Fc);
+    if (!(c->refine_res <= c->o.refine_tol) && c->o.fallback_fp64) {
+      // refinement stopped above its target: the complex128 sweep from the
+      // same top solution (Fc is untouched by the mixed sweeps)
+      solve_fp64(c, M, Fc, Fo);
+      c->refine_fallback = 1;
+    }
     mark(c, 1, 1);
+    profile_set_phase(PH_OTHER);
     c->ndir = M;
     c->solved = true;
-    if (!(c->refine_res <= c->o.refine_tol))
+    if (!c->refine_fallback && !(c->refine_res <= c->o.refine_tol))
       throw HpsError{HPS_ENOCONV, "refinement stopped at relative residual " + std::to_string(c->refine_res)};
     return;
   }
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, Fc, nb, sF, ZERO, c->dg.z(), nb, sF,
-           P));
-  CK(boundary_st(st, Fc, c->dg.z(), c->dG.z(), nb, M, etav, c->dST.z(), P));
-  for (int l = g.nlev; l >= 1; --l) {
-    down_level(c, l, OP_N, c->dD[l].z(), Fc, Fo, M);
-    std::swap(Fc, Fo);
-  }
-  CK(zgemm(st, OP_N, OP_N, g.mi, M, g.ne, ONE, c->dY.z(), g.mi, (ll)g.mi * g.ne, Fc, g.ne,
-           (ll)g.ne * M, ZERO, c->du0.z(), g.mi, (ll)g.mi * M, g.nleaf * P));
+  solve_fp64(c, M, Fc, Fo);
   mark(c, 1, 1);
   profile_set_phase(PH_OTHER);
   c->ndir = M;
@@ -1208,6 +1227,7 @@ void hps_default_opts(hps_opts* o) {
   o->nprob = 1;
   o->max_refine = 8;
   o->refine_tol = 1e-10;
+  o->fallback_fp64 = 1;
 }
 
 hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
@@ -1416,6 +1436,7 @@ hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
     out->nonfinite = c->nonfinite;
     out->refine_iters = c->refine_iters;
     out->refine_residual = c->refine_res;
+    out->refine_fallback = c->refine_fallback;
   });
 }
 

@@ -1195,14 +1195,18 @@ bool use_lookahead(int n, int batch) {
 }
 
 // Pivoting of the explicit inverses (process-wide):
-//   -1 (default): for orders above the register-panel limit that are
-//      multiples of 4, a random butterfly transform and pivot-free
-//      elimination, checked on probe vectors, with the pivoted
-//      (tournament) elimination as fallback; partial pivoting otherwise;
+//   -1 (default): for orders of at least 224 that are multiples of 4, a
+//      random butterfly transform and pivot-free elimination, checked on
+//      probe vectors, with the pivoted elimination as fallback; partial
+//      pivoting otherwise;
 //    0: always partial / tournament pivoting;
 //    1: the butterfly path for every order that is a multiple of 4 (>= 8).
 // -2: not read yet (HPS_ZINV_PIVOTING = 0 / 1 in the environment).
 std::atomic<int> g_pivoting{-2};
+// Default rule: the butterfly path from this order up (measured on MI355X:
+// faster than the pivoted register panels at orders 224 and 448, slower at
+// 56, about even at 112).
+constexpr int RBT_MIN_N = 224;
 std::atomic<double> g_rbt_tol{1e-10};
 std::atomic<long> g_rbt_calls{0}, g_rbt_fallbacks{0};
 std::atomic<double> g_rbt_maxerr{0.0};
@@ -1221,7 +1225,7 @@ bool use_rbt(int n, int batch) {
   }
   if (m == 0) return false;
   if (m == 1) return true;
-  return n > NS_MAX_N;
+  return n >= RBT_MIN_N;
 }
 
 size_t std_workspace(int n, int batch, bool wide) {

@@ -95,13 +95,32 @@ def test_mixed_not_converged_reports():
     L, k = 4, 10.0
     xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
     q = synth.gaussian_bumps(xy, 5, 1, amp=(0.1, 0.3), width=0.15)
-    s = hps.Solver(nleaf=L, p=16, precision="mixed", keep_derivs=False, max_refine=0)
+    s = hps.Solver(nleaf=L, p=16, precision="mixed", keep_derivs=False, max_refine=0, fallback_fp64=False)
     s.factor(torch.from_numpy(q).cuda(), k)
     with pytest.raises(hps.HpsError) as e:
         s.solve(synth.equispaced_angles(8))
     assert e.value.code == hps.HPS_ENOCONV
     st = s.stats()
-    assert st["refine_iters"] == 0 and 1e-10 < st["refine_residual"] < 1e-3
+    assert st["refine_iters"] == 0 and 1e-10 < st["refine_residual"] < 1e-3 and st["refine_fallback"] == 0
+
+
+def test_mixed_not_converged_falls_back_to_fp64():
+    """With the fallback (the default) the same unconverged solve redoes its
+    sweep in complex128: no error, the flag is set, and the far field is the
+    complex128 path's, bit for bit (same factorisation, same kernels)."""
+    import paper_1608_06871_amd as hps
+    L, k = 4, 10.0
+    xy = hps.Solver(nleaf=L, p=16, keep_derivs=False).node_coords()
+    q = synth.gaussian_bumps(xy, 5, 1, amp=(0.1, 0.3), width=0.15)
+    th, dirs = synth.equispaced_angles(16), synth.equispaced_angles(8)
+    s = hps.Solver(nleaf=L, p=16, precision="mixed", keep_derivs=False, max_refine=0)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    s.solve(dirs)
+    st = s.stats()
+    assert st["refine_fallback"] == 1 and st["refine_iters"] == 0
+    ff = s.far_field(th, 2.0).cpu()
+    _, ref = _run(hps, "fp64", L, k, q, dirs, th, 2.0, keep_derivs=False)
+    assert torch.equal(ff, torch.from_numpy(ref))
 
 
 def test_mixed_fullsize_k80():
