@@ -172,6 +172,108 @@ def potential_matrices(grid, k, targets):
     return PS, PD
 
 
+def kernel_dGx(k, x, y, v):
+    """Derivative of G(x, y) in x along the unit vector v (the target's normal
+    or tangent): -(ik/4) H1(k r) ((x - y) . v) / r; x [2], y [n, 2]."""
+    dx = x[0] - y[:, 0]
+    dy = x[1] - y[:, 1]
+    r = np.hypot(dx, dy)
+    return -0.25j * k * hankel1(1, k * r) * (dx * v[0] + dy * v[1]) / r
+
+
+def _dlagrange_rows(nodes, w, tau):
+    """d ell_j / dt at points tau (none equal to a node): ell_j(t) times
+    sum_{m != j} 1 / (t - t_m)."""
+    lag = _lagrange_rows(nodes, w, tau)
+    d = tau[:, None] - nodes[None, :]
+    tot = np.sum(1.0 / d, axis=1)
+    return lag * (tot[:, None] - 1.0 / d)
+
+
+def _piece_points(x, A, B, k):
+    """Gauss points (parameter t, weight in t) of the adaptive pieces of
+    panel A -> B for target x (the refinement rule of _pieces)."""
+    pieces, _ = _pieces(x, A, B, k)
+    a = np.array([p[0] for p in pieces])
+    b = np.array([p[1] for p in pieces])
+    t = ((0.5 * (a + b))[:, None] + (0.5 * (b - a))[:, None] * _GX[None, :]).ravel()
+    wt = ((0.5 * (b - a))[:, None] * _GW[None, :]).ravel()
+    return t, wt
+
+
+def bm_matrices(grid, k):
+    """The two further operators of the combined-field (Burton-Miller) form of
+    the exterior relation, on the outer-boundary nodes (ordering of
+    boundary_matrices): the adjoint double layer
+        K'_ij = int d/dn_x G(x_i, y) ell_j(y) ds_y
+    and the hypersingular operator T = d/dn_x of the double layer, written by
+    Maue's identity for the panel-wise density s = sum_j s_j ell_j:
+        T s (x) = d/dsigma_x int G(x, y) (ds/dsigma)(y) dsigma_y
+                  + k^2 int G(x, y) (n_x . n_y) s(y) ds_y,
+    sigma the arclength along the boundary in the counter-clockwise sense
+    (tangent tau = (-n_y, n_x)).  ds/dsigma of a panel's interpolant includes
+    point masses at the panel ends (the interpolant's jumps), so a panel P
+    from A to B with orientation o = +1 (A -> B counter-clockwise) or -1
+    contributes
+        o [ int d/dtau_x G(x, y(t)) ell_j'(t) dt + ell_j(-1) d/dtau_x G(x, A)
+            - ell_j(1) d/dtau_x G(x, B) ]
+    (t the panel parameter).  On the target's own (straight) panel
+    d/dtau_x G = -1 / (pi h (t_x - t)) + a bounded remainder, so the
+    principal value is
+        -1/(pi h) [int (ell'(t) - ell'(t_x)) / (t_x - t) dt
+                   + ell'(t_x) log((1 + t_x) / (1 - t_x))]
+    and the remainder takes the adaptive rule.  The second term of Maue's
+    identity is k^2 (n_x . n_y) S_ij (straight panels)."""
+    nodes = grid.t[1:-1]
+    w = bary_weights(nodes)
+    nloc = nodes.size
+    A, B, N = _panel_arrays(grid)
+    nP = len(A)
+    orient = np.array([1.0 if side in (0, 1) else -1.0 for side in range(4) for _ in range(grid.L)])
+    S, _ = boundary_matrices(grid, k)
+    nb = grid.nb
+    Kp = np.zeros((nb, nb), dtype=np.complex128)
+    T1 = np.zeros((nb, nb), dtype=np.complex128)
+    lag_end = _lagrange_rows(nodes, w, np.array([-1.0, 1.0]))  # [2, nloc]
+    # ell_j'(t_i) on the panel's own nodes: the differentiation matrix
+    Dn = np.zeros((nloc, nloc))
+    for i in range(nloc):
+        for j in range(nloc):
+            if i != j:
+                Dn[i, j] = (w[j] / w[i]) / (nodes[i] - nodes[j])
+        Dn[i, i] = -np.sum(Dn[i])
+    gdl = _dlagrange_rows(nodes, w, _GX)  # ell'(t) at the plain Gauss points
+    for i in range(nb):
+        x = grid.bxy[i]
+        nx = grid.bnormal[i]
+        tx = np.array([-nx[1], nx[0]])
+        Pi = int(grid.bnodes[i, 2]) * grid.L + int(grid.bnodes[i, 3])
+        li = int(grid.bnodes[i, 4])
+        for P in range(nP):
+            cols = slice(P * nloc, (P + 1) * nloc)
+            h = float(np.hypot(*(B[P] - A[P])))
+            t, wt = _piece_points(x, A[P], B[P], k)
+            y = A[P][None, :] + (B[P] - A[P])[None, :] * ((1 + t) / 2)[:, None]
+            lag = _lagrange_rows(nodes, w, t)
+            Kp[i, cols] = (kernel_dGx(k, x, y, nx) * wt * 0.5 * h) @ lag
+            dl = _dlagrange_rows(nodes, w, t)
+            jumps = lag_end[0] * kernel_dGx(k, x, A[P][None, :], tx)[0] - lag_end[1] * kernel_dGx(k, x, B[P][None, :], tx)[0]
+            if P != Pi:
+                T1[i, cols] = orient[P] * ((kernel_dGx(k, x, y, tx) * wt) @ dl + jumps)
+                continue
+            # own panel: principal value + remainder + the end terms
+            t0 = nodes[li]
+            dlx = Dn[li]  # ell_j'(t_x)
+            dd = (gdl - dlx[None, :]) / (t0 - _GX)[:, None]
+            pv = -(1.0 / (np.pi * h)) * (_GW @ dd + dlx * np.log((1 + t0) / (1 - t0)))
+            delta = t0 - t
+            rem = -0.25j * k * hankel1(1, k * 0.5 * h * np.abs(delta)) * np.sign(delta) + 1.0 / (np.pi * h * delta)
+            T1[i, cols] = pv + (rem * wt) @ dl + orient[P] * jumps
+    nn = grid.bnormal @ grid.bnormal.T
+    T = T1 + k * k * nn * S
+    return Kp, T
+
+
 def circle_points(R, P):
     """Measurement points x_p = R (cos theta_p, sin theta_p), theta_p = 2 pi p / P
     (Section 4 uses equispaced angles on the circle of radius R)."""

@@ -20,13 +20,18 @@ Discrete system (rows):
       from the two leaves = 0 (u is single valued there);
   E3  each outer-boundary node: d_nu u (leaf spectral) - t = d_nu u_inc;
   E4  outer boundary: S t - (K - I/2) (u - u_inc) = 0.
+With exterior="burton_miller" the E4 rows are instead the combined-field
+relation (S + i beta (K' + I/2)) t - ((K - I/2) + i beta T) (u - u_inc) = 0,
+beta = 1/k: the Green relation plus i beta times its normal derivative, which
+stays uniquely solvable at the Dirichlet eigenvalues of the box where the plain
+relation does not (the Remark of Section 2 assumes k is not one of them).
 Unknowns: u at all non-corner grid nodes, then t at the boundary nodes.
 """
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .bie import boundary_matrices, circle_points, potential_matrices
+from .bie import bm_matrices, boundary_matrices, circle_points, potential_matrices
 from .cheb import diff_matrix
 from .grid import Grid
 
@@ -41,13 +46,25 @@ def plane_wave(k, d_angle, xy):
 class Problem:
     """Discrete forward problem for one (grid, k)."""
 
-    def __init__(self, L, k, p=16, box=(-1.0, 1.0, -1.0, 1.0)):
+    def __init__(self, L, k, p=16, box=(-1.0, 1.0, -1.0, 1.0), exterior="calderon"):
+        if exterior not in ("calderon", "burton_miller"):
+            raise ValueError("exterior must be 'calderon' or 'burton_miller'")
         self.grid = Grid(L, p, box)
         self.k = float(k)
+        self.exterior = exterior
         D = diff_matrix(self.grid.t) * (2.0 / self.grid.h)
         self.D1 = D
         self.D2 = D @ D
         self.S, self.K = boundary_matrices(self.grid, self.k)
+        # E4 coefficients: Mt t - Ms (u - u_inc) = 0
+        nb = self.grid.nb
+        self.Mt = self.S.copy()
+        self.Ms = self.K - 0.5 * np.eye(nb)
+        if exterior == "burton_miller":
+            Kp, T = bm_matrices(self.grid, self.k)
+            beta = 1.0 / self.k
+            self.Mt = self.Mt + 1j * beta * (Kp + 0.5 * np.eye(nb))
+            self.Ms = self.Ms + 1j * beta * T
         self._base = self._assemble_q_independent()
         self.nrow = self._base[3]
         self.ncol = self.grid.nu + self.grid.nb
@@ -107,11 +124,10 @@ class Problem:
         self.e4_row0 = nrow
         bu = U[g.bnodes[:, 0], g.bnodes[:, 1]]
         self.bu = bu
-        KmI = self.K - 0.5 * np.eye(g.nb)
         rr = nrow + np.repeat(np.arange(g.nb), g.nb)
         rows += [rr, rr]
         cols += [np.tile(g.nu + np.arange(g.nb), g.nb), np.tile(bu, g.nb)]
-        vals += [self.S.ravel(), -KmI.ravel()]
+        vals += [self.Mt.ravel(), -self.Ms.ravel()]
         nrow += g.nb
         rows = np.concatenate(rows)
         cols = np.concatenate(cols)
@@ -134,11 +150,10 @@ class Problem:
         """Right-hand sides (one column per incident direction)."""
         g = self.grid
         B = np.zeros((self.nrow, len(dir_angles)), dtype=np.complex128)
-        KmI = self.K - 0.5 * np.eye(g.nb)
         for m, th in enumerate(dir_angles):
             u, grad = plane_wave(self.k, th, g.bxy)
             B[self.e3_row0:self.e3_row0 + g.nb, m] = np.sum(grad * g.bnormal, axis=1)
-            B[self.e4_row0:self.e4_row0 + g.nb, m] = -KmI @ u
+            B[self.e4_row0:self.e4_row0 + g.nb, m] = -self.Ms @ u
         return B
 
     # ------------------------------------------------------------------ solves
