@@ -89,6 +89,20 @@ typedef enum {
  * operators. */
 typedef enum { HPS_FP64 = 0, HPS_MIXED = 1 } hps_precision;
 
+/* Exterior relation on the outer boundary (the E4 rows of the discrete
+ * system), with t = d_nu u_s and s = u_s the scattered traces:
+ * HPS_EXT_GREEN: S t = (K - I/2) s, the Green relation of the Remark in
+ *   Section 2.  It is singular when k^2 is a Dirichlet eigenvalue of the
+ *   Laplacian on Omega (for [-1, 1]^2: k = (pi/2) sqrt(m^2 + n^2)), which the
+ *   Remark excludes;
+ * HPS_EXT_BURTON_MILLER: (S + i beta (K' + I/2)) t = ((K - I/2) + i beta T) s,
+ *   beta = 1/k: the Green relation plus i beta times its normal derivative
+ *   (K' the adjoint double layer, T the hypersingular operator in Maue's
+ *   form), uniquely solvable at every k > 0.  The extra operators cost host
+ *   quadrature in hps_set_wavenumber only; factor, solves and derivatives
+ *   are unchanged in cost. */
+typedef enum { HPS_EXT_GREEN = 0, HPS_EXT_BURTON_MILLER = 1 } hps_exterior;
+
 typedef struct hps_opts {
   double x0, x1, y0, y1; /* square domain Omega; x1 - x0 must equal y1 - y0 */
   int nleaf;             /* leaves per side, a power of two (1 .. 256) */
@@ -104,13 +118,14 @@ typedef struct hps_opts {
   int fallback_fp64;     /* HPS_MIXED: non-zero: a solve whose refinement stops above refine_tol
                             redoes its sweep in complex128 (exact FP64 result, refine_fallback = 1
                             in hps_stats) instead of returning HPS_ENOCONV */
+  int exterior;          /* hps_exterior */
 } hps_opts;
 
 typedef struct hps_ctx hps_ctx;
 
 /* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
  * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1,
- * max_refine = 8, fallback_fp64 = 1, refine_tol = 1e-10 (the far-field error follows the interface
+ * max_refine = 8, fallback_fp64 = 1, refine_tol = 1e-10, HPS_EXT_GREEN (the far-field error follows the interface
  * residual closely, so 1e-10 leaves two orders of margin under a 1e-8 far-field
  * target; one correction reaches it at k = 80). */
 void hps_default_opts(hps_opts* o);
@@ -257,6 +272,15 @@ hps_status hps_get_stats(hps_ctx* ctx, hps_stats* out);
  * NULL). */
 hps_status hps_boundary_operators(const hps_opts* opts, double k, double* xy_host, double* S_host,
                                   double* K_host);
+
+/* Host-only: the operators HPS_EXT_BURTON_MILLER adds, same layout and order
+ * as hps_boundary_operators: Kp_host = K' (adjoint double layer,
+ * Kp[i][j] = int dG/dn_x(x_i, y) ell_j(y) ds) and T_host = T (hypersingular,
+ * the normal derivative at x_i of the double layer of ell_j, by Maue's
+ * identity: tangential derivative of the single layer of d ell_j / d sigma,
+ * including the interpolant's jumps at panel ends, plus
+ * k^2 (n_i . n_j) S[i][j]).  HPS_EINVAL for bad options or k <= 0. */
+hps_status hps_combined_field_operators(const hps_opts* opts, double k, double* Kp_host, double* T_host);
 
 /* Batched complex GEMM C_b = alpha op(A_b) op(B_b) + beta C_b, b < batch,
  * column-major; op: 0 = none, 1 = transpose, 2 = conjugate transpose.

@@ -33,7 +33,7 @@ class Opts(ctypes.Structure):
                 ("eta_scale", ctypes.c_double), ("keep_derivs", ctypes.c_int),
                 ("precision", ctypes.c_int), ("host_threads", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("nprob", ctypes.c_int), ("max_refine", ctypes.c_int),
-                ("refine_tol", ctypes.c_double), ("fallback_fp64", ctypes.c_int)]
+                ("refine_tol", ctypes.c_double), ("fallback_fp64", ctypes.c_int), ("exterior", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -76,6 +76,7 @@ SIGNATURES = [
     ("hps_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
     ("hps_gn_step", _I, [_P, _D, _I, _P, _I, _P, _D, _I, _I, _P, _P, _I, _D, _P, _P, _P, _P]),
     ("hps_boundary_operators", _I, [ctypes.POINTER(Opts), _D, _P, _P, _P]),
+    ("hps_combined_field_operators", _I, [ctypes.POINTER(Opts), _D, _P, _P]),
     ("hps_zgemm", _I, [_P, _I, _I, _I, _I, _I, _P, _P, _L, _L, _P, _L, _L, _P, _P, _L, _L, _I]),
     ("hps_zinv", _I, [_P, _I, _I, _P, _P]),
     ("hps_zinv_noalloc", _I, [_P, _I, _I, _P, _P, _P]),
@@ -123,6 +124,10 @@ def _dev(t, dtype, numel=None, name="array"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# exterior relations of hps_opts.exterior
+EXTERIORS = {"green": 0, "burton_miller": 1}
+
+
 class Solver:
     """One HPS context: geometry fixed at construction; factor/solve/... as in
     the C ABI (include/hps.h).  With nprob > 1 the context holds a batch of
@@ -131,7 +136,7 @@ class Solver:
 
     def __init__(self, nleaf=4, p=16, box=(-1.0, 1.0, -1.0, 1.0), eta_scale=1.0,
                  keep_derivs=True, host_threads=0, stream=None, nprob=1, precision="fp64",
-                 max_refine=None, refine_tol=None, fallback_fp64=None):
+                 max_refine=None, refine_tol=None, fallback_fp64=None, exterior="green"):
         torch = _torch()
         L = lib()
         o = Opts()
@@ -151,6 +156,10 @@ class Solver:
             o.refine_tol = float(refine_tol)
         if fallback_fp64 is not None:
             o.fallback_fp64 = 1 if fallback_fp64 else 0
+        if exterior not in EXTERIORS:
+            raise ValueError(f"exterior must be one of {sorted(EXTERIORS)}")
+        o.exterior = EXTERIORS[exterior]
+        self.exterior = exterior
         self.precision = precision
         self.max_refine, self.refine_tol = o.max_refine, o.refine_tol
         if stream is None:
@@ -328,6 +337,24 @@ def boundary_operators(nleaf, p, k, box=(-1.0, 1.0, -1.0, 1.0)):
     if rc != HPS_OK:
         raise HpsError(rc, "hps_boundary_operators")
     return xy, S, K
+
+
+def combined_field_operators(nleaf, p, k, box=(-1.0, 1.0, -1.0, 1.0)):
+    """Host-side K' (adjoint double layer) and T (hypersingular) [nb, nb]
+    complex128 numpy, in the order of boundary_operators (no GPU needed)."""
+    L = lib()
+    o = Opts()
+    L.hps_default_opts(ctypes.byref(o))
+    o.x0, o.x1, o.y0, o.y1 = map(float, box)
+    o.nleaf, o.p = int(nleaf), int(p)
+    nb = 4 * o.nleaf * (o.p - 2)
+    Kp = np.zeros((nb, nb), dtype=np.complex128)
+    T = np.zeros((nb, nb), dtype=np.complex128)
+    rc = L.hps_combined_field_operators(ctypes.byref(o), float(k), Kp.ctypes.data_as(ctypes.c_void_p),
+                                        T.ctypes.data_as(ctypes.c_void_p))
+    if rc != HPS_OK:
+        raise HpsError(rc, "hps_combined_field_operators")
+    return Kp, T
 
 
 def zgemm(A, B, C=None, opA=0, opB=0, alpha=1.0, beta=0.0, stream=None):

@@ -389,13 +389,14 @@ void leaf_operators(const Geometry& g, double k, double eta, std::vector<cplx>& 
   }
 }
 
-void layer_moments(const Geometry& g, double k, const std::vector<double>& tx,
-                   const std::vector<double>& ty, std::vector<cplx>& S, std::vector<cplx>& K,
-                   int nthreads) {
-  const int L = g.L, m1 = g.p - 2;
-  const int npan = 4 * L;
+namespace {
+
+// The 4 L outer-boundary panels (leaf edges), side * L + index, each from A
+// to B in increasing x (sides 0, 2) or y (sides 1, 3), with outward normal.
+std::vector<Panel> outer_panels(const Geometry& g) {
+  const int L = g.L;
   const double X1 = g.x0 + g.h * L, Y1 = g.y0 + g.h * L;
-  std::vector<Panel> pan(npan);
+  std::vector<Panel> pan(4 * L);
   for (int side = 0; side < 4; ++side)
     for (int i = 0; i < L; ++i) {
       Panel P;
@@ -406,9 +407,12 @@ void layer_moments(const Geometry& g, double k, const std::vector<double>& tx,
       if (side == 3) P = {g.x0, g.y0 + lo, g.x0, g.y0 + hi, -1.0, 0.0};
       pan[side * L + i] = P;
     }
-  const int nb = (int)g.root.size();
-  std::vector<int> col((size_t)npan * m1, -1);
-  for (int q = 0; q < nb; ++q) col[(size_t)g.root[q].panel * m1 + g.root[q].local] = q;
+  return pan;
+}
+
+// Interpolation on a panel's p - 2 interior Lobatto nodes, 16-point Gauss rule.
+Quad panel_quad(const Geometry& g, double k) {
+  const int m1 = g.p - 2;
   Quad Q;
   Q.nloc = m1;
   Q.k = k;
@@ -421,6 +425,123 @@ void layer_moments(const Geometry& g, double k, const std::vector<double>& tx,
     Q.bw[j] = 1.0 / prod;
   }
   gauss_legendre(16, Q.gx, Q.gw);
+  return Q;
+}
+
+// Runs work(lo, hi) over [0, n) on up to nthreads threads.
+template <class F>
+void parallel_rows(size_t n, int nthreads, F work) {
+  if (nthreads < 1) nthreads = 1;
+  if ((size_t)nthreads > n) nthreads = (int)std::max<size_t>(1, n);
+  std::vector<std::thread> th;
+  const size_t chunk = (n + nthreads - 1) / nthreads;
+  for (int w = 0; w < nthreads; ++w) {
+    const size_t lo = w * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back(work, lo, hi);
+  }
+  for (auto& x : th) x.join();
+}
+
+// Derivatives ell_j'(tau) of the Lagrange basis (tau not a node), from the
+// barycentric form ell_j = u_j / sum_m u_m, u_j = bw_j / (tau - t_j):
+// ell_j' = ell_j (sum_m ell_m / (tau - t_m) - 1 / (tau - t_j)).
+void dlagrange(const Quad& Q, double tau, const double* lag, double* out) {
+  double s = 0.0;
+  for (int m = 0; m < Q.nloc; ++m) s += lag[m] / (tau - Q.nodes[m]);
+  for (int j = 0; j < Q.nloc; ++j) out[j] = lag[j] * (s - 1.0 / (tau - Q.nodes[j]));
+}
+
+// Target data of the combined-field moments: boundary node (x, y) with
+// outward normal (nx, ny), counter-clockwise tangent (-ny, nx); on its own
+// panel (own = true) at parameter t0.
+struct BmTarget {
+  double x, y, nx, ny;
+  bool own;
+  double t0;
+};
+
+// Accumulates, over the parameter piece [a, b] of panel P (orientation o =
+// +1 when A -> B runs counter-clockwise), with the refinement rule of piece():
+//   mKp[j] += int dG/dn_x ell_j ds,
+//   mT[j]  += int o dG/dtau_x ell_j'(t) dt  (plus, on the target's own panel,
+//             1 / (pi h (t0 - t)): the kernel minus its Cauchy part).
+void piece_bm(const Quad& Q, const Panel& P, const BmTarget& X, double o, double a, double b, int depth,
+              cplx* mKp, cplx* mT) {
+  const double vx = P.bx - P.ax, vy = P.by - P.ay;
+  const double len_full = std::sqrt(vx * vx + vy * vy);
+  const double len = 0.5 * (b - a) * len_full;
+  // On the target's own panel everything is taken in the panel parameter:
+  // the kernel's Cauchy part is subtracted at t0, so the kernel must be
+  // singular at exactly t0 (coordinates would move it by rounding, and near
+  // the target that mismatch grows like 1 / (t0 - t)).
+  double tp, d;
+  if (X.own) {
+    tp = X.t0;
+    d = 0.5 * len_full * std::max(0.0, std::max(a - tp, tp - b));
+  } else {
+    const double px = X.x - P.ax, py = X.y - P.ay;
+    tp = 2.0 * (px * vx + py * vy) / (len_full * len_full) - 1.0;
+    const double tc = std::min(std::max(tp, a), b);
+    const double cx = P.ax + vx * 0.5 * (1.0 + tc), cy = P.ay + vy * 0.5 * (1.0 + tc);
+    d = std::hypot(X.x - cx, X.y - cy);
+  }
+  if ((d >= 0.75 * len && Q.k * len <= 4.0) || depth > 200) {
+    const double half = 0.5 * (b - a), mid = 0.5 * (a + b);
+    const double tx = -X.ny, ty = X.nx;
+    double lag[64], dl[64];
+    for (size_t g = 0; g < Q.gx.size(); ++g) {
+      const double tau = mid + half * Q.gx[g];
+      const double wt = half * Q.gw[g];
+      cplx gK, gT;
+      if (X.own) {
+        // x - y = (t0 - t) (B - A) / 2: normal component 0, o times the
+        // tangential one (t0 - t) h / 2
+        const double dt = X.t0 - tau;
+        const double r = 0.5 * len_full * std::fabs(dt);
+        cplx h0, h1;
+        hankel01(Q.k * r, h0, h1);
+        gK = 0.0;
+        gT = cplx(0.0, -0.25 * Q.k) * h1 * (dt > 0.0 ? 1.0 : -1.0) + 1.0 / (PI * len_full * dt);
+      } else {
+        const double yx = P.ax + vx * 0.5 * (1.0 + tau), yy = P.ay + vy * 0.5 * (1.0 + tau);
+        const double dx = X.x - yx, dy = X.y - yy;
+        const double r = std::hypot(dx, dy);
+        cplx h0, h1;
+        hankel01(Q.k * r, h0, h1);
+        const cplx c1 = cplx(0.0, -0.25 * Q.k) * h1 / r;  // grad_x G = c1 (x - y)
+        gK = c1 * (dx * X.nx + dy * X.ny) * (wt * 0.5 * len_full);
+        gT = o * c1 * (dx * tx + dy * ty);
+      }
+      gT *= wt;
+      lagrange(Q, tau, lag);
+      dlagrange(Q, tau, lag, dl);
+      for (int j = 0; j < Q.nloc; ++j) {
+        mKp[j] += gK * lag[j];
+        mT[j] += gT * dl[j];
+      }
+    }
+    return;
+  }
+  if (d == 0.0 && len < 1e-15) return;
+  double split = 0.5 * (a + b);
+  if (tp > a + 0.05 * (b - a) && tp < b - 0.05 * (b - a)) split = tp;
+  piece_bm(Q, P, X, o, a, split, depth + 1, mKp, mT);
+  piece_bm(Q, P, X, o, split, b, depth + 1, mKp, mT);
+}
+
+}  // namespace
+
+void layer_moments(const Geometry& g, double k, const std::vector<double>& tx,
+                   const std::vector<double>& ty, std::vector<cplx>& S, std::vector<cplx>& K,
+                   int nthreads) {
+  const int L = g.L, m1 = g.p - 2;
+  const int npan = 4 * L;
+  const std::vector<Panel> pan = outer_panels(g);
+  const int nb = (int)g.root.size();
+  std::vector<int> col((size_t)npan * m1, -1);
+  for (int q = 0; q < nb; ++q) col[(size_t)g.root[q].panel * m1 + g.root[q].local] = q;
+  const Quad Q = panel_quad(g, k);
   const size_t nt = tx.size();
   S.assign(nt * nb, cplx(0.0, 0.0));
   K.assign(nt * nb, cplx(0.0, 0.0));
@@ -438,16 +559,86 @@ void layer_moments(const Geometry& g, double k, const std::vector<double>& tx,
         }
       }
   };
-  if (nthreads < 1) nthreads = 1;
-  if ((size_t)nthreads > nt) nthreads = (int)std::max<size_t>(1, nt);
-  std::vector<std::thread> th;
-  const size_t chunk = (nt + nthreads - 1) / nthreads;
-  for (int w = 0; w < nthreads; ++w) {
-    const size_t lo = w * chunk, hi = std::min(nt, lo + chunk);
-    if (lo >= hi) break;
-    th.emplace_back(work, lo, hi);
-  }
-  for (auto& x : th) x.join();
+  parallel_rows(nt, nthreads, work);
+}
+
+void combined_field_moments(const Geometry& g, double k, std::vector<cplx>& Kp, std::vector<cplx>& T1,
+                            int nthreads) {
+  const int L = g.L, m1 = g.p - 2;
+  const int npan = 4 * L;
+  const std::vector<Panel> pan = outer_panels(g);
+  const int nb = (int)g.root.size();
+  std::vector<int> col((size_t)npan * m1, -1);
+  for (int q = 0; q < nb; ++q) col[(size_t)g.root[q].panel * m1 + g.root[q].local] = q;
+  const Quad Q = panel_quad(g, k);
+  // ell_j'(t_i) on the nodes: off the diagonal (bw_j / bw_i) / (t_i - t_j),
+  // on it sum_{m != i} 1 / (t_i - t_m) (log-derivative of the node polynomial)
+  std::vector<double> Dn((size_t)m1 * m1);
+  for (int i = 0; i < m1; ++i)
+    for (int j = 0; j < m1; ++j) {
+      double v = 0.0;
+      if (i != j) {
+        v = (Q.bw[j] / Q.bw[i]) / (Q.nodes[i] - Q.nodes[j]);
+      } else {
+        for (int m = 0; m < m1; ++m)
+          if (m != i) v += 1.0 / (Q.nodes[i] - Q.nodes[m]);
+      }
+      Dn[(size_t)i * m1 + j] = v;
+    }
+  // ell_j at the panel ends t = -1, +1
+  std::vector<double> lA(m1), lB(m1);
+  lagrange(Q, -1.0, lA.data());
+  lagrange(Q, 1.0, lB.data());
+  Kp.assign((size_t)nb * nb, cplx(0.0, 0.0));
+  T1.assign((size_t)nb * nb, cplx(0.0, 0.0));
+  auto dGdtau = [&](const BmTarget& X, double yx, double yy) {
+    const double dx = X.x - yx, dy = X.y - yy;
+    const double r = std::hypot(dx, dy);
+    cplx h0, h1;
+    hankel01(k * r, h0, h1);
+    return cplx(0.0, -0.25 * k) * h1 * ((dx * -X.ny + dy * X.nx) / r);
+  };
+  auto work = [&](size_t lo, size_t hi) {
+    std::vector<cplx> mK(m1), mT(m1);
+    std::vector<double> lag(m1), dl(m1);
+    for (size_t i = lo; i < hi; ++i) {
+      const BoundaryNode& bn = g.root[i];
+      for (int pp = 0; pp < npan; ++pp) {
+        const Panel& P = pan[pp];
+        const double o = (pp / L) < 2 ? 1.0 : -1.0;  // sides 0, 1 run counter-clockwise
+        BmTarget X{bn.x, bn.y, bn.nx, bn.ny, pp == bn.panel, Q.nodes[bn.local]};
+        std::fill(mK.begin(), mK.end(), cplx(0.0, 0.0));
+        std::fill(mT.begin(), mT.end(), cplx(0.0, 0.0));
+        piece_bm(Q, P, X, o, -1.0, 1.0, 0, mK.data(), mT.data());
+        // point masses of d s / d sigma at the panel ends (jumps of the
+        // panel-wise interpolant): o [ell_j(-1) dG/dtau(x, A) - ell_j(1) dG/dtau(x, B)]
+        const cplx gA = o * dGdtau(X, P.ax, P.ay), gB = o * dGdtau(X, P.bx, P.by);
+        for (int j = 0; j < m1; ++j) mT[j] += gA * lA[j] - gB * lB[j];
+        if (X.own) {
+          // principal value of -1/(pi h) int ell_j'(t) / (t0 - t) dt: the
+          // divided difference is a polynomial (Gauss rule exact) plus the
+          // closed-form p.v. integral of 1 / (t0 - t)
+          const double t0 = X.t0;
+          const double hl = std::hypot(P.bx - P.ax, P.by - P.ay);
+          const double lg = std::log((1.0 + t0) / (1.0 - t0));
+          const double* d0 = &Dn[(size_t)bn.local * m1];
+          std::vector<double> acc(m1, 0.0);
+          for (size_t q = 0; q < Q.gx.size(); ++q) {
+            lagrange(Q, Q.gx[q], lag.data());
+            dlagrange(Q, Q.gx[q], lag.data(), dl.data());
+            for (int j = 0; j < m1; ++j) acc[j] += Q.gw[q] * (dl[j] - d0[j]) / (t0 - Q.gx[q]);
+          }
+          for (int j = 0; j < m1; ++j) mT[j] += -(acc[j] + d0[j] * lg) / (PI * hl);
+        }
+        for (int j = 0; j < m1; ++j) {
+          const int c = col[(size_t)pp * m1 + j];
+          Kp[i * nb + c] = mK[j];
+          T1[i * nb + c] = mT[j];
+        }
+      }
+    }
+  };
+  parallel_rows((size_t)nb, nthreads, work);
 }
 
 }  // namespace hps

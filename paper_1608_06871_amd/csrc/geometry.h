@@ -57,4 +57,15 @@ void layer_moments(const Geometry& g, double k, const std::vector<double>& tx,
                    const std::vector<double>& ty, std::vector<cplx>& S, std::vector<cplx>& K,
                    int nthreads);
 
+// Moments of the combined-field (Burton-Miller) exterior relation on the
+// outer-boundary nodes (row-major [nb x nb], root order):
+//   Kp[i][j] = int dG/dn_x(x_i, y) ell_j(y) ds (adjoint double layer),
+//   T1[i][j] = d/dsigma_x int G(x_i, y) d(ell_j)/dsigma ds (the tangential
+//              part of the hypersingular operator in Maue's form, including
+//              the interpolant's jumps at the panel ends; principal value on
+//              the target's own panel).
+// The full hypersingular operator is T1 + k^2 (n_i . n_j) S.
+void combined_field_moments(const Geometry& g, double k, std::vector<cplx>& Kp, std::vector<cplx>& T1,
+                            int nthreads);
+
 }  // namespace hps

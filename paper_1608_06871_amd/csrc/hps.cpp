@@ -18,9 +18,11 @@
 //                U = [A13 V; -B23 (A33 V + [I, 0])], V = W^-1 [B33, -I],
 //                for the upward propagation of body-load data (derivatives);
 //   top          the outer-boundary system Z = A1 + A2 R_root with
-//                A1 = S/2 - (K - I/2)/(2 i eta), A2 = S/2 + (K - I/2)/(2 i eta)
-//                from the Calderon relation, inverted.
-// Solve: f_root = Z^-1 [S, -(K - I/2)] [d_nu u_inc; u_inc], then the
+//                A1 = Mt/2 - Ms/(2 i eta), A2 = Mt/2 + Ms/(2 i eta)
+//                from the exterior relation Mt t = Ms s (Mt = S, Ms = K - I/2
+//                for the Green relation; S + i beta (K' + I/2) and
+//                K - I/2 + i beta T for the combined field), inverted.
+// Solve: f_root = Z^-1 [Mt, -Ms] [d_nu u_inc; u_inc], then the
 // down-sweep f3 = D f through the levels and u = Y f at the leaves.
 #include "../../include/hps.h"
 
@@ -209,7 +211,7 @@ void upload(DBuf& b, const void* src, size_t bytes, hipStream_t st) {
 }
 
 // Host-side operators of one wavenumber: the leaf base matrix and outgoing
-// map (column-major), the boundary right-hand-side operator [S, -(K - I/2)]
+// map (column-major), the boundary right-hand-side operator [Mt, -Ms]
 // and the top blocks A1, A2.
 struct WaveOps {
   std::vector<cplx> A0, Mout, Bop, A1, A2;
@@ -233,14 +235,32 @@ void wave_ops(const hps_ctx* c, double k, double eta, WaveOps& w) {
   }
   std::vector<cplx> S, K;
   layer_moments(g, k, tx, ty, S, K, c->nthreads);
+  // exterior relation Mt t = Ms s: (S, K - I/2), or the combined field
+  // (S + i beta (K' + I/2), K - I/2 + i beta T), beta = 1/k
+  std::vector<cplx>& Mt = S;
+  std::vector<cplx>& Ms = K;
+  for (int i = 0; i < nb; ++i) Ms[(size_t)i * nb + i] -= 0.5;
+  if (c->o.exterior == HPS_EXT_BURTON_MILLER) {
+    std::vector<cplx> Kp, T1;
+    combined_field_moments(g, k, Kp, T1, c->nthreads);
+    const cplx ib = cplx(0.0, 1.0 / k);
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j) {
+        const size_t ij = (size_t)i * nb + j;
+        const double nn = g.root[i].nx * g.root[j].nx + g.root[i].ny * g.root[j].ny;
+        const cplx Tij = T1[ij] + k * k * nn * S[ij];
+        Ms[ij] += ib * Tij;
+        Mt[ij] += ib * (Kp[ij] + (i == j ? 0.5 : 0.0));
+      }
+  }
   const cplx cinv = cplx(0.0, -1.0 / (2.0 * eta));  // 1 / (2 i eta)
   w.Bop.assign((size_t)nb * 2 * nb, cplx());
   w.A1.assign((size_t)nb * nb, cplx());
   w.A2.assign((size_t)nb * nb, cplx());
   for (int i = 0; i < nb; ++i)
     for (int j = 0; j < nb; ++j) {
-      const cplx sv = S[(size_t)i * nb + j];
-      const cplx kmi = K[(size_t)i * nb + j] - (i == j ? 0.5 : 0.0);
+      const cplx sv = Mt[(size_t)i * nb + j];
+      const cplx kmi = Ms[(size_t)i * nb + j];
       w.Bop[i + (size_t)j * nb] = sv;
       w.Bop[i + (size_t)(nb + j) * nb] = -kmi;
       w.A1[i + (size_t)j * nb] = 0.5 * sv - cinv * kmi;
@@ -1228,6 +1248,7 @@ void hps_default_opts(hps_opts* o) {
   o->max_refine = 8;
   o->refine_tol = 1e-10;
   o->fallback_fp64 = 1;
+  o->exterior = HPS_EXT_GREEN;
 }
 
 hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
@@ -1239,6 +1260,7 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
   if (o.nleaf < 1 || o.nleaf > 256 || (o.nleaf & (o.nleaf - 1))) return HPS_EINVAL;
   if (o.p < 4 || o.p > 20) return HPS_EINVAL;
   if (o.precision != HPS_FP64 && o.precision != HPS_MIXED) return HPS_EINVAL;
+  if (o.exterior != HPS_EXT_GREEN && o.exterior != HPS_EXT_BURTON_MILLER) return HPS_EINVAL;
   if (o.nprob < 1 || o.nprob > 4096) return HPS_EINVAL;
   if (o.precision == HPS_MIXED && (o.max_refine < 0 || o.max_refine > 100 || !(o.refine_tol > 0.0)))
     return HPS_EINVAL;
@@ -1462,6 +1484,35 @@ hps_status hps_boundary_operators(const hps_opts* opts, double k, double* xy_hos
     layer_moments(g, k, tx, ty, S, K, nth);
     std::memcpy(S_host, S.data(), S.size() * sizeof(cplx));
     std::memcpy(K_host, K.data(), K.size() * sizeof(cplx));
+  } catch (...) {
+    return HPS_EINVAL;
+  }
+  return HPS_OK;
+}
+
+hps_status hps_combined_field_operators(const hps_opts* opts, double k, double* Kp_host, double* T_host) {
+  if (!opts || !(k > 0.0) || !std::isfinite(k) || !Kp_host || !T_host) return HPS_EINVAL;
+  try {
+    Geometry g;
+    g.build(opts->x0, opts->x1, opts->y0, opts->nleaf, opts->p);
+    const int nb = (int)g.root.size();
+    std::vector<double> tx(nb), ty(nb);
+    for (int i = 0; i < nb; ++i) {
+      tx[i] = g.root[i].x;
+      ty[i] = g.root[i].y;
+    }
+    unsigned hw = std::thread::hardware_concurrency();
+    const int nth = opts->host_threads > 0 ? opts->host_threads : (int)std::min(16u, std::max(1u, hw));
+    std::vector<cplx> S, K, Kp, T1;
+    layer_moments(g, k, tx, ty, S, K, nth);
+    combined_field_moments(g, k, Kp, T1, nth);
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j) {
+        const size_t ij = (size_t)i * nb + j;
+        T1[ij] += k * k * (g.root[i].nx * g.root[j].nx + g.root[i].ny * g.root[j].ny) * S[ij];
+      }
+    std::memcpy(Kp_host, Kp.data(), Kp.size() * sizeof(cplx));
+    std::memcpy(T_host, T1.data(), T1.size() * sizeof(cplx));
   } catch (...) {
     return HPS_EINVAL;
   }

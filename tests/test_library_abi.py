@@ -50,6 +50,9 @@ def test_default_opts_and_invalid_create_on_cpu():
     assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
     bad.p, bad.x1 = 16, 3.0  # not square
     assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
+    bad.x1, bad.exterior = 1.0, 2  # no such exterior relation
+    assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
+    assert o.exterior == 0
 
 
 def test_status_codes_match_the_header():
