@@ -154,10 +154,10 @@ def algorithmic_work(L, M, p=16):
     bytes one sweep must read (16 bytes per complex entry)."""
     e = p - 2
     mi, ne = e * e, 4 * e
-    n = mi + ne
     nl = L * L
     nb = 4 * L * e
-    inv = {"leaf": nl * 8.0 * n ** 3, "merge": 0.0, "top": 8.0 * nb ** 3}
+    # leaves: the interior impedance problem (order mi) is inverted explicitly
+    inv = {"leaf": nl * 8.0 * mi ** 3, "merge": 0.0, "top": 8.0 * nb ** 3}
     D_bytes = 0.0
     for l, (cnt, s) in enumerate(level_table(L, p), start=1):
         nc = child_boundary(l, e)

@@ -1,11 +1,20 @@
 // libhps: the C ABI of include/hps.h on top of the HIP kernels.
 //
 // Factorisation (per contrast q, wavenumber k):
-//   leaf stage   every leaf's collocation matrix (PDE rows + incoming
-//                impedance rows) is inverted in one batched call; from the
-//                inverse come Y (interior field from incoming impedance),
-//                R (leaf impedance-to-impedance map) and H (outgoing
-//                impedance from an interior body load);
+//   leaf stage   the leaf collocation matrix A = [A_ii A_ie; A_ei A_ee]
+//                (PDE rows at the interior nodes, incoming-impedance rows at
+//                the edge nodes; unknowns interior then edge) changes with q
+//                only on the diagonal of A_ii.  The edge unknowns are folded
+//                in per wavenumber (A_ee is diagonally dominant), leaving the
+//                leaf's impedance problem on the interior,
+//                  S = A_ii - A_ie A_ee^-1 A_ei - k^2 diag(q),
+//                uniquely solvable for real k like A itself (det A =
+//                det A_ee det S), which one batched call inverts.  With the
+//                per-k blocks P1 = A_ie A_ee^-1, V = Mout_i - Mout_e A_ee^-1 A_ei,
+//                R0 = Mout_e A_ee^-1 (Mout the outgoing impedance rows):
+//                  Y = -S^-1 P1        interior field from incoming impedance,
+//                  R = R0 + V Y        leaf impedance-to-impedance map,
+//                  H = V S^-1          outgoing impedance from a body load;
 //   merge tree   per level, all merges are batched: with child maps
 //                Ra = [A11 A13; A31 A33], Rb = [B22 B23; B32 B33] on
 //                (exterior, shared) nodes and the matching f3a = -g3b,
@@ -107,7 +116,11 @@ struct hps_ctx {
   // per wavenumber (one slot per problem)
   bool have_k = false;
   std::vector<double> kv, etav;
-  DBuf dA0, dMout, dBop, dA1, dA2, dbnode;
+  // per problem, n^2 entries: the leaf blocks S0 = A_ii - A_ie A_ee^-1 A_ei
+  // at q = 0 [mi x mi], P1 [mi x ne], V [ne x mi], R0 [ne x ne] (column-major,
+  // consecutive)
+  DBuf dLeaf;
+  DBuf dBop, dA1, dA2, dbnode;
   DBuf dPk;  // device [k (P) | k^2 (P) | eta (P)]
   std::vector<DBuf> didx;  // 4 index arrays per level
   // leaf-edge slots: [1 .. nlev] the shared nodes of a merge ([alpha; beta]
@@ -210,24 +223,100 @@ void upload(DBuf& b, const void* src, size_t bytes, hipStream_t st) {
   CK(hipStreamSynchronize(st));
 }
 
-// Host-side operators of one wavenumber: the leaf base matrix and outgoing
-// map (column-major), the boundary right-hand-side operator [Mt, -Ms]
-// and the top blocks A1, A2.
+// Host-side operators of one wavenumber: the leaf blocks (layout of
+// hps_ctx::dLeaf), the boundary right-hand-side operator [Mt, -Ms] and the
+// top blocks A1, A2.
 struct WaveOps {
-  std::vector<cplx> A0, Mout, Bop, A1, A2;
+  std::vector<cplx> Leaf, Bop, A1, A2;
 };
+
+// In-place inverse of the row-major n x n matrix a (Gauss-Jordan with
+// partial pivoting; host, small orders).
+void host_inverse(int n, std::vector<cplx>& a) {
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int c = 0; c < n; ++c) {
+    int pr = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(a[(size_t)r * n + c]) > std::abs(a[(size_t)pr * n + c])) pr = r;
+    require(std::abs(a[(size_t)pr * n + c]) > 0.0, HPS_ESINGULAR, "singular leaf edge block");
+    if (pr != c) {
+      for (int j = 0; j < n; ++j) std::swap(a[(size_t)pr * n + j], a[(size_t)c * n + j]);
+      std::swap(perm[pr], perm[c]);
+    }
+    const cplx piv = 1.0 / a[(size_t)c * n + c];
+    a[(size_t)c * n + c] = 1.0;
+    for (int j = 0; j < n; ++j) a[(size_t)c * n + j] *= piv;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const cplx f = a[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      a[(size_t)r * n + c] = 0.0;
+      for (int j = 0; j < n; ++j) a[(size_t)r * n + j] -= f * a[(size_t)c * n + j];
+    }
+  }
+  // columns come out in the pivot order: undo the row exchanges
+  std::vector<cplx> t(n);
+  for (int r = 0; r < n; ++r) {
+    for (int j = 0; j < n; ++j) t[perm[j]] = a[(size_t)r * n + j];
+    for (int j = 0; j < n; ++j) a[(size_t)r * n + j] = t[j];
+  }
+}
+
+// The per-wavenumber leaf blocks from the collocation matrix A0 (q = 0) and
+// the outgoing rows Mout (both row-major, unknowns interior then edge).
+void leaf_blocks(const Geometry& g, const std::vector<cplx>& A0, const std::vector<cplx>& Mout,
+                 std::vector<cplx>& out) {
+  const int mi = g.mi, ne = g.ne, n = mi + ne;
+  auto a = [&](int r, int j) { return A0[(size_t)r * n + j]; };
+  auto mo = [&](int e, int j) { return Mout[(size_t)e * n + j]; };
+  std::vector<cplx> E((size_t)ne * ne);
+  for (int i = 0; i < ne; ++i)
+    for (int j = 0; j < ne; ++j) E[(size_t)i * ne + j] = a(mi + i, mi + j);
+  host_inverse(ne, E);  // A_ee^-1
+  std::vector<cplx> P2((size_t)ne * mi);  // A_ee^-1 A_ei
+  for (int i = 0; i < ne; ++i)
+    for (int b = 0; b < ne; ++b) {
+      const cplx e = E[(size_t)i * ne + b];
+      for (int j = 0; j < mi; ++j) P2[(size_t)i * mi + j] += e * a(mi + b, j);
+    }
+  out.assign((size_t)n * n, cplx());
+  cplx* S0 = out.data();
+  cplx* P1 = S0 + (size_t)mi * mi;
+  cplx* V = P1 + (size_t)mi * ne;
+  cplx* R0 = V + (size_t)ne * mi;
+  for (int r = 0; r < mi; ++r)
+    for (int j = 0; j < mi; ++j) {
+      cplx v = a(r, j);
+      for (int b = 0; b < ne; ++b) v -= a(r, mi + b) * P2[(size_t)b * mi + j];
+      S0[r + (size_t)j * mi] = v;
+    }
+  for (int r = 0; r < mi; ++r)
+    for (int j = 0; j < ne; ++j) {
+      cplx v = 0.0;
+      for (int b = 0; b < ne; ++b) v += a(r, mi + b) * E[(size_t)b * ne + j];
+      P1[r + (size_t)j * mi] = v;
+    }
+  for (int e = 0; e < ne; ++e) {
+    for (int j = 0; j < mi; ++j) {
+      cplx v = mo(e, j);
+      for (int b = 0; b < ne; ++b) v -= mo(e, mi + b) * P2[(size_t)b * mi + j];
+      V[e + (size_t)j * ne] = v;
+    }
+    for (int j = 0; j < ne; ++j) {
+      cplx v = 0.0;
+      for (int b = 0; b < ne; ++b) v += mo(e, mi + b) * E[(size_t)b * ne + j];
+      R0[e + (size_t)j * ne] = v;
+    }
+  }
+}
 
 void wave_ops(const hps_ctx* c, double k, double eta, WaveOps& w) {
   const Geometry& g = c->g;
-  const int n = c->n, ne = g.ne, nb = c->nb;
+  const int nb = c->nb;
   std::vector<cplx> A0, Mout;
   leaf_operators(g, k, eta, A0, Mout);
-  w.A0.assign((size_t)n * n, cplx());
-  w.Mout.assign((size_t)ne * n, cplx());
-  for (int r = 0; r < n; ++r)
-    for (int j = 0; j < n; ++j) w.A0[r + (size_t)j * n] = A0[(size_t)r * n + j];
-  for (int e = 0; e < ne; ++e)
-    for (int j = 0; j < n; ++j) w.Mout[e + (size_t)j * ne] = Mout[(size_t)e * n + j];
+  leaf_blocks(g, A0, Mout, w.Leaf);
   std::vector<double> tx(nb), ty(nb);
   for (int i = 0; i < nb; ++i) {
     tx[i] = g.root[i].x;
@@ -281,10 +370,9 @@ void set_wavenumbers(hps_ctx* c, const double* k) {
   const Geometry& g = c->g;
   const int n = c->n, ne = g.ne, nb = c->nb;
   const double es = c->o.eta_scale > 0.0 ? c->o.eta_scale : 1.0;
-  const size_t sA0 = (size_t)n * n, sMo = (size_t)ne * n, sBo = (size_t)nb * 2 * nb, sA = (size_t)nb * nb;
+  const size_t sA0 = (size_t)n * n, sBo = (size_t)nb * 2 * nb, sA = (size_t)nb * nb;
   if (!c->have_k) {
-    c->dA0.ensure(zb(sA0 * P));
-    c->dMout.ensure(zb(sMo * P));
+    c->dLeaf.ensure(zb(sA0 * P));
     c->dBop.ensure(zb(sBo * P));
     c->dA1.ensure(zb(sA * P));
     c->dA2.ensure(zb(sA * P));
@@ -311,8 +399,7 @@ void set_wavenumbers(hps_ctx* c, const double* k) {
     for (int a = 0; a < b && src < 0; ++a)
       if (k[a] == k[b]) src = a;
     if (src >= 0) {
-      CK(hipMemcpyAsync(c->dA0.z() + sA0 * b, c->dA0.z() + sA0 * src, zb(sA0), hipMemcpyDeviceToDevice, c->st));
-      CK(hipMemcpyAsync(c->dMout.z() + sMo * b, c->dMout.z() + sMo * src, zb(sMo), hipMemcpyDeviceToDevice,
+      CK(hipMemcpyAsync(c->dLeaf.z() + sA0 * b, c->dLeaf.z() + sA0 * src, zb(sA0), hipMemcpyDeviceToDevice,
                         c->st));
       CK(hipMemcpyAsync(c->dBop.z() + sBo * b, c->dBop.z() + sBo * src, zb(sBo), hipMemcpyDeviceToDevice,
                         c->st));
@@ -321,8 +408,7 @@ void set_wavenumbers(hps_ctx* c, const double* k) {
     } else {
       WaveOps w;
       wave_ops(c, k[b], es * k[b], w);
-      upload_at(c->dA0, zb(sA0 * b), w.A0.data(), zb(sA0), c->st);
-      upload_at(c->dMout, zb(sMo * b), w.Mout.data(), zb(sMo), c->st);
+      upload_at(c->dLeaf, zb(sA0 * b), w.Leaf.data(), zb(sA0), c->st);
       upload_at(c->dBop, zb(sBo * b), w.Bop.data(), zb(sBo), c->st);
       upload_at(c->dA1, zb(sA * b), w.A1.data(), zb(sA), c->st);
       upload_at(c->dA2, zb(sA * b), w.A2.data(), zb(sA), c->st);
@@ -362,7 +448,7 @@ void plan_factor_buffers(hps_ctx* c) {
   const Geometry& g = c->g;
   const size_t P = c->P;
   const size_t nl = (size_t)g.nleaf * P, n = c->n, ne = g.ne, mi = g.mi, nb = c->nb;
-  size_t zws = zinv_perm_workspace((int)n, (int)nl);
+  size_t zws = zinv_workspace((int)mi, (int)nl);
   size_t rmax = nl * ne * ne, blk = 0, w = 0, q = 0, v = 0;
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
@@ -376,7 +462,7 @@ void plan_factor_buffers(hps_ctx* c) {
   }
   zws = std::max(zws, zinv_workspace((int)nb, (int)P));
   c->sA.ensure(zb(std::max(nl * n * n, P * nb * nb)));
-  c->sInv.ensure(zb(2 * nl * (size_t)g.ne * n));  // leaf stage: Mout column-gathered, then Mout inv
+  c->sInv.ensure(zb(nl * mi * mi));  // leaf stage: S^-1
   c->sZws.ensure(zws);
   c->sR0.ensure(zb(rmax));
   c->sR1.ensure(zb(rmax));
@@ -447,29 +533,27 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   CK(flag_nonfinite(st, q, (ll)P * g.nleaf * mi, 1, nonfinite));
 
   // leaf stage (all leaves of all problems)
-  CK(leaf_assemble(st, c->dA0.z(), nn, q, k2v, n, mi, c->sA.z(), nl, lpp));
-  // Leaf inverses without their final permutation: M = sA with
-  // inv[c][k] = M[sig[c]][pos[k]] per leaf; the products below read M
-  // through the maps instead of an unpermuted copy.
-  const int* sig = nullptr;
-  const int* pos = nullptr;
-  CK(zinv_perm(st, n, c->sA.z(), n, nn, nl, c->sZws.p, c->sInfo.i(), &sig, &pos));
-  const double2* M = c->sA.z();
-  // Y = inv[0:mi, mi:n] (interior values of the edge-data solutions)
-  CK(gather_perm(st, mi, ne, M, n, nn, 1, sig, n, n, pos + mi, n, n, c->dY.z(), mi, (ll)mi * ne, nl));
-  // Mout inv = (Mout[:, pos] M)[:, pos]: with r = sig[c],
-  // sum_c Mout[o][c] M[sig[c]][pos[k]] = sum_r Mout[o][pos[r]] M[r][pos[k]].
-  // The outgoing map is one per problem (leaf z of problem z / lpp).
-  double2* Mp = c->sInv.z();
-  double2* T = Mp + (ll)nl * ne * n;
-  const ll smo = (ll)ne * n;
-  CK(gather_perm(st, ne, n, c->dMout.z(), ne, P == 1 ? 0 : smo, lpp, nullptr, 0, ne, pos, n, n, Mp, ne, smo, nl));
-  CK(zgemm(st, OP_N, OP_N, ne, n, n, ONE, Mp, ne, smo, M, n, nn, ZERO, T, ne, smo, nl));
+  // S = S0 - k^2 diag(q) per leaf, inverted (the blocks of problem z / lpp)
+  const double2* S0 = c->dLeaf.z();
+  const double2* P1 = S0 + (ll)mi * mi;
+  const double2* V = P1 + (ll)mi * ne;
+  const double2* R0 = V + (ll)ne * mi;
+  const ll smm = (ll)mi * mi;
+  CK(leaf_assemble(st, S0, nn, q, k2v, mi, mi, c->sA.z(), nl, lpp));
+  double2* Si = c->sInv.z();
+  CK(zinv(st, mi, c->sA.z(), mi, smm, Si, mi, smm, nl, c->sZws.p, c->sInfo.i()));
+  // Y = -S^-1 P1
+  CK(zgemm_div(st, OP_N, OP_N, mi, ne, mi, MONE, Si, mi, smm, 1, P1, mi, nn, lpp, ZERO, c->dY.z(), mi,
+               (ll)mi * ne, nl));
+  // R = R0 + V Y
   double2* Rc = c->sR0.z();
-  // R = Mout inv[:, mi:n] (leaf ItI maps), H = Mout inv[:, 0:mi]
-  CK(gather_perm(st, ne, ne, T, ne, smo, 1, nullptr, 0, ne, pos + mi, n, n, Rc, ne, (ll)ne * ne, nl));
+  CK(gather_perm(st, ne, ne, R0, ne, nn, lpp, nullptr, 0, ne, nullptr, 0, ne, Rc, ne, (ll)ne * ne, nl));
+  CK(zgemm_div(st, OP_N, OP_N, ne, ne, mi, ONE, V, ne, nn, lpp, c->dY.z(), mi, (ll)mi * ne, 1, ONE, Rc, ne,
+               (ll)ne * ne, nl));
+  // H = V S^-1
   if (c->o.keep_derivs)
-    CK(gather_perm(st, ne, mi, T, ne, smo, 1, nullptr, 0, ne, pos, n, n, c->dH.z(), ne, (ll)ne * mi, nl));
+    CK(zgemm_div(st, OP_N, OP_N, ne, mi, mi, ONE, V, ne, nn, lpp, Si, mi, smm, 1, ZERO, c->dH.z(), ne,
+                 (ll)ne * mi, nl));
   if (c->mixed) CK(hipMemcpyAsync(c->dRleaf.p, Rc, zb((size_t)nl * ne * ne), hipMemcpyDeviceToDevice, st));
   mark(c, 5, 1);
 
@@ -1208,7 +1292,7 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
 
 int64_t device_bytes(const hps_ctx* c) {
   int64_t s = 0;
-  const DBuf* bufs[] = {&c->dA0, &c->dMout, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dPk, &c->dY, &c->dH,
+  const DBuf* bufs[] = {&c->dLeaf, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dPk, &c->dY, &c->dH,
                         &c->dRroot, &c->dZinv, &c->dRrootH, &c->dZinvH, &c->dA2H, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
                         &c->sBlk, &c->sW, &c->sWinv, &c->sQ, &c->sVin, &c->sV, &c->sTmp, &c->sInfo,
                         &c->d_dirs, &c->dG, &c->dRhs, &c->dF0, &c->dF1, &c->dF3, &c->du0, &c->dST,
