@@ -250,7 +250,7 @@ typedef struct hps_stats {
   double t_vjp_ms;        /* last hps_vjp */
   double t_leaf_ms;       /* last hps_factor: leaf stage (collocation, inverses, leaf maps) */
   double t_merge_ms;      /* last hps_factor: merge tree (all levels) */
-  double t_top_ms;        /* last hps_factor: top system Z = A1 + A2 R and its inverse */
+  double t_top_ms;        /* last hps_factor: top system A2^-1 A1 + R and its inverse */
   int64_t device_bytes;   /* device memory held by the context */
   int ndir;               /* directions of the last solve */
   int singular;           /* 1 if the last factorisation met a zero pivot */

@@ -120,7 +120,9 @@ struct hps_ctx {
   // at q = 0 [mi x mi], P1 [mi x ne], V [ne x mi], R0 [ne x ne] (column-major,
   // consecutive)
   DBuf dLeaf;
-  DBuf dBop, dA1, dA2, dbnode;
+  // top blocks scaled by A2^-1 (per problem): C1 = A2^-1 A1 and, in dBop,
+  // A2^-1 [Mt, -Ms]; the outer-boundary system is then Z' = C1 + R_root
+  DBuf dBop, dC1, dbnode;
   DBuf dPk;  // device [k (P) | k^2 (P) | eta (P)]
   std::vector<DBuf> didx;  // 4 index arrays per level
   // leaf-edge slots: [1 .. nlev] the shared nodes of a merge ([alpha; beta]
@@ -149,7 +151,7 @@ struct hps_ctx {
   DBuf dY, dH, dRroot, dZinv;
   // conjugate transposes of the top operators for the adjoint (read as plain
   // column-major operands, which the matrix cores stream faster)
-  DBuf dRrootH, dZinvH, dA2H;
+  DBuf dRrootH, dZinvH;
   std::vector<DBuf> dD, dU;
   DBuf sA, sInv, sZws, sR0, sR1, sBlk, sW, sWinv, sQ, sVin, sV, sTmp, sInfo;
 
@@ -166,7 +168,7 @@ struct hps_ctx {
   DBuf dPhi;
 
   // derivative scratch
-  DBuf sB, sST2, sW2;
+  DBuf sB, sST2;
   // Gauss-Newton scratch
   DBuf sGn, sGnZ;
 
@@ -374,8 +376,7 @@ void set_wavenumbers(hps_ctx* c, const double* k) {
   if (!c->have_k) {
     c->dLeaf.ensure(zb(sA0 * P));
     c->dBop.ensure(zb(sBo * P));
-    c->dA1.ensure(zb(sA * P));
-    c->dA2.ensure(zb(sA * P));
+    c->dC1.ensure(zb(sA * P));
     c->kv.assign(P, 0.0);
     c->etav.assign(P, 0.0);
     std::vector<double> bn(4 * (size_t)nb);
@@ -389,6 +390,7 @@ void set_wavenumbers(hps_ctx* c, const double* k) {
     upload(c->dbnode, bn.data(), bn.size() * sizeof(double), c->st);
   }
   bool changed = false;
+  DBuf tA2, tInv, tRaw, tWs, tInfo;  // device temporaries of the A2^-1 scaling
   for (int b = 0; b < P; ++b) {
     if (c->have_k && k[b] == c->kv[b]) continue;
     changed = true;
@@ -403,22 +405,33 @@ void set_wavenumbers(hps_ctx* c, const double* k) {
                         c->st));
       CK(hipMemcpyAsync(c->dBop.z() + sBo * b, c->dBop.z() + sBo * src, zb(sBo), hipMemcpyDeviceToDevice,
                         c->st));
-      CK(hipMemcpyAsync(c->dA1.z() + sA * b, c->dA1.z() + sA * src, zb(sA), hipMemcpyDeviceToDevice, c->st));
-      CK(hipMemcpyAsync(c->dA2.z() + sA * b, c->dA2.z() + sA * src, zb(sA), hipMemcpyDeviceToDevice, c->st));
+      CK(hipMemcpyAsync(c->dC1.z() + sA * b, c->dC1.z() + sA * src, zb(sA), hipMemcpyDeviceToDevice, c->st));
     } else {
       WaveOps w;
       wave_ops(c, k[b], es * k[b], w);
       upload_at(c->dLeaf, zb(sA0 * b), w.Leaf.data(), zb(sA0), c->st);
-      upload_at(c->dBop, zb(sBo * b), w.Bop.data(), zb(sBo), c->st);
-      upload_at(c->dA1, zb(sA * b), w.A1.data(), zb(sA), c->st);
-      upload_at(c->dA2, zb(sA * b), w.A2.data(), zb(sA), c->st);
+      // C1 = A2^-1 A1 and A2^-1 [Mt, -Ms] on the device
+      tA2.ensure(zb(sA));
+      tInv.ensure(zb(sA));
+      tRaw.ensure(zb(sBo));
+      tWs.ensure(zinv_workspace(nb, 1));
+      tInfo.ensure(sizeof(int));
+      upload(tA2, w.A2.data(), zb(sA), c->st);
+      CK(hipMemsetAsync(tInfo.p, 0, sizeof(int), c->st));
+      CK(zinv(c->st, nb, tA2.z(), nb, (ll)sA, tInv.z(), nb, (ll)sA, 1, tWs.p, tInfo.i()));
+      upload(tRaw, w.A1.data(), zb(sA), c->st);
+      CK(zgemm(c->st, OP_N, OP_N, nb, nb, nb, ONE, tInv.z(), nb, 0, tRaw.z(), nb, 0, ZERO, c->dC1.z() + sA * b, nb,
+               0, 1));
+      upload(tRaw, w.Bop.data(), zb(sBo), c->st);
+      CK(zgemm(c->st, OP_N, OP_N, nb, 2 * nb, nb, ONE, tInv.z(), nb, 0, tRaw.z(), nb, 0, ZERO,
+               c->dBop.z() + sBo * b, nb, 0, 1));
+      int info = 0;
+      CK(hipMemcpyAsync(&info, tInfo.p, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      CK(hipStreamSynchronize(c->st));
+      require(info == 0, HPS_ESINGULAR, "the exterior impedance block A2 is singular at this wavenumber");
     }
     c->kv[b] = k[b];
     c->etav[b] = es * k[b];
-  }
-  if (changed && c->o.keep_derivs) {
-    c->dA2H.ensure(zb(sA * P));
-    CK(conj_transpose(c->st, nb, c->dA2.z(), nb, (ll)sA, c->dA2H.z(), nb, (ll)sA, P));
   }
   std::vector<double> pk(3 * (size_t)P);
   for (int b = 0; b < P; ++b) {
@@ -637,15 +650,13 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   }
   mark(c, 6, 1);
 
-  // top: Z = A1 + A2 R_root per problem, inverted
+  // top: Z' = A2^-1 (A1 + A2 R_root) = C1 + R_root per problem, inverted
   mark(c, 7, 0);
   profile_set_phase(PH_TOP);
   const ll sbb = (ll)nb * nb;
   CK(hipMemcpyAsync(c->dRroot.p, Rc, zb((size_t)P * sbb), hipMemcpyDeviceToDevice, st));
   double2* Z = c->sA.z();
-  CK(hipMemcpyAsync(Z, c->dA1.p, zb((size_t)P * sbb), hipMemcpyDeviceToDevice, st));
-  CK(zgemm(st, OP_N, OP_N, nb, nb, nb, ONE, c->dA2.z(), nb, sbb, c->dRroot.z(), nb, sbb, ONE, Z, nb, sbb,
-           P));
+  CK(zadd(st, c->dC1.z(), Rc, Z, (ll)P * sbb));
   CK(zinv(st, nb, Z, nb, sbb, c->dZinv.z(), nb, sbb, P, c->sZws.p, c->sInfo.i()));
   if (c->o.keep_derivs) {
     CK(conj_transpose(st, nb, c->dRroot.z(), nb, sbb, c->dRrootH.z(), nb, sbb, P));
@@ -805,8 +816,9 @@ double mixed_residual(hps_ctx* c, int M, const double2*& froot, const double2*& 
   groot = gc;
   const ll sF = (ll)nb * M, sbb = (ll)nb * nb, ntop = (ll)P * sF;
   CK(hipMemcpyAsync(c->dRb.p, c->dRhs.p, zb((size_t)ntop), hipMemcpyDeviceToDevice, st));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA1.z(), nb, sbb, froot, nb, sF, MONE, c->dRb.z(), nb, sF, P));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA2.z(), nb, sbb, groot, nb, sF, ONE, c->dRb.z(), nb, sF, P));
+  // outer-boundary residual in the scaled form C1 f + g - A2^-1 rhs
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dC1.z(), nb, sbb, froot, nb, sF, MONE, c->dRb.z(), nb, sF, P));
+  CK(zadd(st, c->dRb.z(), groot, c->dRb.z(), ntop));
   const ll nleaf = (ll)nl * ne * M;
   CK(dot(st, (const double*)c->dFl.p, (const double*)c->dFl.p, 2 * nleaf, partial, nrm));
   CK(dot(st, (const double*)c->dRhs.p, (const double*)c->dRhs.p, 2 * ntop, partial, nrm + 1));
@@ -855,13 +867,13 @@ void mixed_correct(hps_ctx* c, int M) {
     hc = hp;
     pp ^= 1;
   }
-  // top: delta f = Z^-1 (-r_b - A2 h)
+  // top: delta f = Z'^-1 (-r_b - h)
   const ll sF = (ll)nb * M, sbb = (ll)nb * nb, ntop = (ll)P * sF;
   double2* hr = c->rT0.z();
   double2* w = c->rT1.z();
   CK(to_f64(st, hc, ntop, hr));
   CK(gather2d(st, (int)ntop, 1, c->dRb.z(), ntop, 0, nullptr, nullptr, w, ntop, 0, -1.0, 1));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dA2.z(), nb, sbb, hr, nb, sF, ONE, w, nb, sF, P));
+  CK(zsub(st, w, hr, w, ntop));
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinv.z(), nb, sbb, w, nb, sF, ZERO, hr, nb, sF, P));
   float2* dr = (hc == (float2*)c->mF0.p) ? (float2*)c->mF1.p : (float2*)c->mF0.p;
   CK(to_f32(st, hr, ntop, dr));
@@ -1036,7 +1048,6 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
   const ll sF = (ll)nb * M, sbb = (ll)nb * nb;
   c->sB.ensure(zb((size_t)nl * g.ne * g.mi));
   c->sST2.ensure(zb((size_t)2 * P * nb * M));
-  c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 3, 0);
   profile_set_phase(PH_JVP);
   // leaf outgoing data of the body load k^2 dq u0: H (k^2 dq u0).  With many
@@ -1069,10 +1080,8 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
              Ho, np, sp, cnt));
     std::swap(Hc, Ho);
   }
-  // root: Z f = -A2 h,  g = R f + h
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dA2.z(), nb, sbb, Hc, nb, sF, ZERO, c->sW2.z(), nb, sF, P));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dZinv.z(), nb, sbb, c->sW2.z(), nb, sF, ZERO, Ho, nb, sF,
-           P));
+  // root: f = -Z'^-1 h (Z' = A2^-1 Z),  g = R f + h
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dZinv.z(), nb, sbb, Hc, nb, sF, ZERO, Ho, nb, sF, P));
   CK(hipMemcpyAsync(c->dg.p, Hc, zb((size_t)P * nb * M), hipMemcpyDeviceToDevice, st));
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRroot.z(), nb, sbb, Ho, nb, sF, ONE, c->dg.z(), nb, sF,
            P));
@@ -1094,7 +1103,6 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
   const ll sF = (ll)nb * M, sbb = (ll)nb * nb;
   c->sB.ensure(zb((size_t)nl * g.ne * g.mi));
   c->sST2.ensure(zb((size_t)2 * P * nb * M));
-  c->sW2.ensure(zb((size_t)P * nb * M));
   mark(c, 4, 0);
   profile_set_phase(PH_VJP);
   // [sbar; tbar] = Phi^H r
@@ -1106,8 +1114,7 @@ void vjp(hps_ctx* c, const double* r, double* grad) {
   double2* gb = Hc;
   CK(boundary_st_adj(st, c->sST2.z(), nb, M, c->dPk.d() + 2 * P, fb, gb, P));
   CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dRrootH.z(), nb, sbb, gb, nb, sF, ONE, fb, nb, sF, P));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, ONE, c->dZinvH.z(), nb, sbb, fb, nb, sF, ZERO, c->sW2.z(), nb, sF, P));
-  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dA2H.z(), nb, sbb, c->sW2.z(), nb, sF, ONE, gb, nb, sF, P));
+  CK(zgemm(st, OP_N, OP_N, nb, M, nb, MONE, c->dZinvH.z(), nb, sbb, fb, nb, sF, ONE, gb, nb, sF, P));
   for (int l = g.nlev; l >= 1; --l) {
     down_level(c, l, OP_C, c->dU[l].z(), Hc, Ho, M);
     std::swap(Hc, Ho);
@@ -1292,11 +1299,11 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
 
 int64_t device_bytes(const hps_ctx* c) {
   int64_t s = 0;
-  const DBuf* bufs[] = {&c->dLeaf, &c->dBop, &c->dA1, &c->dA2, &c->dbnode, &c->dPk, &c->dY, &c->dH,
-                        &c->dRroot, &c->dZinv, &c->dRrootH, &c->dZinvH, &c->dA2H, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
+  const DBuf* bufs[] = {&c->dLeaf, &c->dBop, &c->dC1, &c->dbnode, &c->dPk, &c->dY, &c->dH,
+                        &c->dRroot, &c->dZinv, &c->dRrootH, &c->dZinvH, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
                         &c->sBlk, &c->sW, &c->sWinv, &c->sQ, &c->sVin, &c->sV, &c->sTmp, &c->sInfo,
                         &c->d_dirs, &c->dG, &c->dRhs, &c->dF0, &c->dF1, &c->dF3, &c->du0, &c->dST,
-                        &c->dg, &c->dPhi, &c->sB, &c->sST2, &c->sW2, &c->dSx, &c->dSy,
+                        &c->dg, &c->dPhi, &c->sB, &c->sST2, &c->dSx, &c->dSy,
                         &c->dNodeGrid, &c->sS1, &c->sS2, &c->sS3, &c->sGn, &c->sGnZ};
   for (const DBuf* b : bufs) s += (int64_t)b->bytes;
   for (const auto& b : c->didx) s += (int64_t)b.bytes;
