@@ -1,7 +1,7 @@
 """Python binding of libhps, the MI355X HPS/ItI Helmholtz scattering library.
 
 Argument marshalling only: every computation runs in the HIP kernels behind
-the C ABI of include/hps.h.  Device arrays are torch tensors on the GPU
+the C ABI of include/hps.h and include/hps_blocks.h.  Device arrays are torch tensors on the GPU
 (float64 / complex128, contiguous); the library enqueues on the stream given
 at construction (default: torch's current stream).  If libhps.so is missing
 the first call raises: there is no CPU fallback.

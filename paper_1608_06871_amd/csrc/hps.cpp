@@ -1,4 +1,4 @@
-// libhps: the C ABI of include/hps.h on top of the HIP kernels.
+// libhps: the C ABI of include/hps.h and include/hps_blocks.h on top of the HIP kernels.
 //
 // Factorisation (per contrast q, wavenumber k):
 //   leaf stage   the leaf collocation matrix A = [A_ii A_ie; A_ei A_ee]
@@ -33,7 +33,7 @@
 //                K - I/2 + i beta T for the combined field), inverted.
 // Solve: f_root = Z^-1 [Mt, -Ms] [d_nu u_inc; u_inc], then the
 // down-sweep f3 = D f through the levels and u = Y f at the leaves.
-#include "../../include/hps.h"
+#include "../../include/hps_blocks.h"
 
 #include <chrono>
 #include <cmath>

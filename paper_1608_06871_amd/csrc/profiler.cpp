@@ -6,7 +6,7 @@
 #include <mutex>
 #include <vector>
 
-#include "../../include/hps.h"
+#include "../../include/hps_blocks.h"
 #include "common.h"
 
 namespace hps {

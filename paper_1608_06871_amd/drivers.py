@@ -48,6 +48,29 @@ def leaves_for(k, ppw, p=16, width=2.0, min_leaves=1, max_leaves=256):
     return L
 
 
+def grid_for(k, ppw, width=2.0, p_range=(12, 20), min_leaves=1, max_leaves=256):
+    """(L, p) for a wavenumber: L leaves per side (a power of two) of p x p
+    points, with at least ppw points per wavelength over the width (Section 4)
+    and as few points as that allows: the fewest intervals (p - 1) L per side
+    with (p - 1) L >= ppw k width / (2 pi), p in p_range, ties to the higher
+    order.  The leaf order supplies the granularity that a power-of-two leaf
+    count alone lacks (doubling L can double the points per side)."""
+    need = ppw * k * width / (2.0 * math.pi)
+    best = None
+    L = 1
+    while L <= max_leaves:
+        if L >= min_leaves:
+            p = max(p_range[0], int(math.ceil(need / L - 1e-9)) + 1)
+            if p <= p_range[1]:
+                key = ((p - 1) * L, -p)
+                if best is None or key < best[0]:
+                    best = (key, L, p)
+        L *= 2
+    if best is None:
+        raise ValueError(f"k = {k} needs more than {max_leaves} leaves per side at {ppw} points per wavelength")
+    return best[1], best[2]
+
+
 def paper_schedule(k_max, k0=1.0, dk=0.25, ppw=10.0, p=16, width=2.0, angles_per_k=4, R=20.0, min_leaves=1,
                    leaves=None):
     """The frequency schedule of Section 4: k_j = k0 + j dk up to k_max,
@@ -55,8 +78,9 @@ def paper_schedule(k_max, k0=1.0, dk=0.25, ppw=10.0, p=16, width=2.0, angles_per
     floor(angles_per_k k_j) receivers at 2 pi p / P_j on the circle of radius
     R, band S(k_j) = floor(2 k_j) (eq. sineseries: modes m + n <= S), and the
     leaf grid per k from the points-per-wavelength rule (or `leaves` for a
-    fixed grid).  The text gives P_j = floor(4 k_j); Tables 2-3 list
-    M P = 16 k^2, i.e. P = 8 k (angles_per_k = 8)."""
+    fixed grid; p = "auto" picks leaf count and order per k with grid_for,
+    each step then carrying its own "p").  The text gives P_j = floor(4 k_j);
+    Tables 2-3 list M P = 16 k^2, i.e. P = 8 k (angles_per_k = 8)."""
     out = []
     j = 0
     while True:
@@ -66,8 +90,12 @@ def paper_schedule(k_max, k0=1.0, dk=0.25, ppw=10.0, p=16, width=2.0, angles_per
         M = max(1, int(math.floor(2.0 * k + 1e-12)))
         P = max(1, int(math.floor(angles_per_k * k + 1e-12)))
         S = int(math.floor(2.0 * k + 1e-12))
-        L = leaves if leaves is not None else leaves_for(k, ppw, p, width, min_leaves)
-        out.append({"j": j, "k": k, "M": M, "P": P, "band": S, "modes": S * (S - 1) // 2, "L": L, "R": R})
+        if p == "auto":
+            L, pk = grid_for(k, ppw, width, min_leaves=min_leaves) if leaves is None else (leaves, 16)
+        else:
+            L, pk = (leaves if leaves is not None else leaves_for(k, ppw, p, width, min_leaves)), p
+        out.append({"j": j, "k": k, "M": M, "P": P, "band": S, "modes": S * (S - 1) // 2, "L": L, "p": pk,
+                    "R": R})
         j += 1
     return out
 
@@ -169,11 +197,12 @@ class RecursiveLinearization:
         self.checkpoint = checkpoint
         self._ctx = {}
 
-    def solver(self, L):
+    def solver(self, L, p=None):
         from . import Solver
-        if L not in self._ctx:
-            self._ctx[L] = Solver(nleaf=L, p=self.p, box=self.box, keep_derivs=True)
-        return self._ctx[L]
+        p = self.p if p is None else p
+        if (L, p) not in self._ctx:
+            self._ctx[(L, p)] = Solver(nleaf=L, p=p, box=self.box, keep_derivs=True)
+        return self._ctx[(L, p)]
 
     def _save(self, j, coef, S, log):
         tmp = self.checkpoint + ".tmp"
@@ -211,12 +240,12 @@ class RecursiveLinearization:
             S_new = max(S, band - 1)  # largest mode number in the band m + n <= S(k)
             coef = extend(coef, S, S_new)
             S = S_new
-            s = self.solver(step["L"])
+            s = self.solver(step["L"], step.get("p"))
             d = self.data(step)
             dnorm = float(d.abs().pow(2).sum().sqrt())
             dirs = synth.equispaced_angles(step["M"])
             th = synth.equispaced_angles(step["P"])
-            entry = {k_: step[k_] for k_ in ("j", "k", "M", "P", "band", "modes", "L")}
+            entry = {k_: step[k_] for k_ in ("j", "k", "M", "P", "band", "modes", "L", "p") if k_ in step}
             entry["newton"] = []
             prev_mis = None
             for it in range(self.newton_max):

@@ -163,3 +163,33 @@ def test_jvp_vjp_leaf_orders_match_oracle(M):
     assert _rel(s.jvp(torch.from_numpy(dq).cuda()).cpu().numpy(), prob.jvp(dq)) < 1e-9
     r = rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))
     assert _rel(s.vjp(torch.from_numpy(r).cuda()).cpu().numpy(), prob.vjp(r)) < 1e-9
+
+
+@pytest.mark.parametrize("p,L,k", [(12, 2, 6.0), (13, 2, 8.0), (17, 4, 12.0), (20, 2, 9.0)])
+def test_leaf_orders_of_the_grid_rule_match_oracle(p, L, k):
+    """Leaf orders other than 16 (the grid rule picks p in [12, 20] per k):
+    far field, total field, J dq and Re J^H r element by element against
+    the oracle on the same grid."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    M, P, R = 4, 16, 2.0
+    print(f"leaf order p={p} L={L} k={k}", flush=True)
+    s = hps.Solver(nleaf=L, p=p)
+    inp = synth.parity_inputs(s.node_coords(), M, P, seed=p)
+    prob = Problem(L, k, p)
+    assert np.max(np.abs(s.node_coords() - prob.grid.pde_coords())) < 1e-15
+    _, th = circle_points(R, P)
+    prob.set_measurement(th, R)
+    prob.factor(inp["q"])
+    prob.solve(directions(M))
+    s.factor(torch.from_numpy(inp["q"]).cuda(), k)
+    s.solve(synth.equispaced_angles(M))
+    ff = s.far_field(synth.equispaced_angles(P), R).cpu().numpy()
+    u = s.total_field().cpu().numpy()
+    jv = s.jvp(torch.from_numpy(inp["dq"]).cuda()).cpu().numpy()
+    g = s.vjp(torch.from_numpy(inp["r"]).cuda()).cpu().numpy()
+    errs = {"far": _rel(ff, prob.far_field()), "u": _rel(u, prob.u_pde().T), "jvp": _rel(jv, prob.jvp(inp["dq"])),
+            "vjp": _rel(g, prob.vjp(inp["r"]))}
+    print("  " + ", ".join(f"{n} {e:.1e}" for n, e in errs.items()), flush=True)
+    for n, e in errs.items():
+        assert e <= 1e-9, (n, e)

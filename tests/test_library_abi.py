@@ -1,5 +1,5 @@
 """CPU checks of the C-ABI library: it builds, loads, and exports every entry
-point that include/hps.h declares (no compute calls without a GPU)."""
+point that include/*.h declare (no compute calls without a GPU)."""
 import ctypes
 import os
 import re
@@ -11,7 +11,8 @@ HEADER = os.path.join(ROOT, "include", "hps.h")
 
 
 def _declared():
-    text = open(HEADER).read()
+    text = "".join(open(os.path.join(ROOT, "include", f)).read()
+                   for f in sorted(os.listdir(os.path.join(ROOT, "include"))) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(hps_[a-z0-9_]+)\s*\(", text)))
 
