@@ -655,24 +655,32 @@ __global__ __launch_bounds__(64 * NPW) void np_block(const double2* Aall, ll lda
 }
 
 // Wide pivot-free panel block: IB = D^-1 for the b x b diagonal block
-// D[i][j] = A[c0 + i][c0 + j] (b <= 128) by Gauss-Jordan on the diagonal
+// D[i][j] = A[c0 + i][c0 + j] (b <= W) by Gauss-Jordan on the diagonal
 // (the matrix was mixed by the butterfly transform; the probe check and the
 // pivoted fallback guard the result), records sig / pos of the panel, and
-// sets info on an exactly zero pivot.  1024 threads: thread t holds the 4 x 4
-// tile of rows 4 (t & 31) + i and columns 4 (t >> 5) + j.  Per column the
+// sets info on an exactly zero pivot.  (W/4)^2 threads: thread t holds the
+// 4 x 4 tile of rows 4 (t % (W/4)) + i and columns 4 (t / (W/4)) + j.  Per column the
 // pivot row and the column itself are posted to LDS (double-buffered by
 // column parity, one barrier per column); a thread reads 4 values of each and
 // updates its tile with new = a v + b pr (a = 0, b = 1/piv on the pivot row;
 // a = 1, b = -A[r][c]/piv elsewhere).  Columns go in groups of four so that
 // the position inside a tile is a compile-time index.
-constexpr int WPW = 128;  // wide panel width
-__global__ __launch_bounds__(1024) void np_wide_block(const double2* Aall, ll lda, ll sA, int c0, int b,
-                                                      double2* IB_all, int* sig_all, int* pos_all, int n,
-                                                      int* info) {
-  __shared__ double2 prow[2][WPW];
-  __shared__ double2 pcol[2][WPW];
+// Panel widths: the panel chain (one workgroup per block inverse, its cost
+// growing with W^3 / (W/4)^2) against the rank-W updates on the side stream
+// (fewer, larger products for larger W).  Measured on MI355X (order-3584
+// inverse 10.0 / 9.7 / 9.5 / 9.7 / 10.3 ms for W = 128 / 96 / 80 / 64 / 56;
+// order 1792: 4.0 / 3.6 / 3.1 / 2.7 / 2.8 ms): W = 80 from order 2560, else 64.
+constexpr int WPW = 80;  // largest width: the workspace strides
+inline int wide_width(int n) { return n >= 2560 ? 80 : 64; }
+template <int W>
+__global__ __launch_bounds__((W / 4) * (W / 4)) void np_wide_block(const double2* Aall, ll lda, ll sA, int c0,
+                                                                   int b, double2* IB_all, int* sig_all,
+                                                                   int* pos_all, int n, int* info) {
+  constexpr int WPG = W / 4;
+  __shared__ double2 prow[2][W];
+  __shared__ double2 pcol[2][W];
   const ll bi = blockIdx.x;
-  const int t = threadIdx.x, rb = t & 31, cb = t >> 5;
+  const int t = threadIdx.x, rb = t % WPG, cb = t / WPG;
   const double2* A = Aall + bi * sA;
   double2 v[4][4];
 #pragma unroll
@@ -998,15 +1006,19 @@ hipError_t np_panel(const Inv& v, int c0, int bw) {
   return hipGetLastError();
 }
 
-// Wide pivot-free panel (b <= 128 columns): block inverse IB of the
+// Wide pivot-free panel (b <= wide_width(n) columns): block inverse IB of the
 // diagonal block, then the exchange of the panel columns as one product,
 // A[:, panel] = -A_old[:, panel] IB on every row, and the pivot rows (which
 // that gives as -I) set to IB.
 hipError_t np_wide_panel(const Inv& v, int c0, int bw) {
   {
     KernelTimer kt(v.st, K_GJ_PANEL, 8.0 * (double)bw * bw * bw * v.batch, 32.0 * (double)bw * bw * v.batch);
-    hipLaunchKernelGGL(np_wide_block, dim3(v.batch), dim3(1024), 0, v.st, v.work, v.lda, v.sA, c0, bw, v.IBw,
-                       v.sig, v.pos, v.n, v.info);
+    if (wide_width(v.n) == 80)
+      hipLaunchKernelGGL(np_wide_block<80>, dim3(v.batch), dim3(20 * 20), 0, v.st, v.work, v.lda, v.sA, c0, bw,
+                         v.IBw, v.sig, v.pos, v.n, v.info);
+    else
+      hipLaunchKernelGGL(np_wide_block<64>, dim3(v.batch), dim3(16 * 16), 0, v.st, v.work, v.lda, v.sA, c0, bw,
+                         v.IBw, v.sig, v.pos, v.n, v.info);
   }
   HPS_HIP_TRY(hipGetLastError());
   const ll sTw = (ll)v.n * WPW;
@@ -1084,14 +1096,15 @@ hipError_t side_stream(hipStream_t st, hipStream_t* out) {
 // or the next panel's columns; its row mask (pivot positions of panel p)
 // is unaffected by the positions the next panel assigns meanwhile.
 // Panel width of the look-ahead.  Pivoted: 32 (one tournament per panel).
-// Pivot-free: up to 128, so that each pass over the matrix is a rank-128
-// update instead of four rank-32 ones; a wide panel is eliminated by the
+// Pivot-free with the wide workspace: wide_width(n) columns, each panel's
+// diagonal block inverted by one workgroup (np_wide_block) and exchanged by
+// one product.  Without it: up to 128 columns, a panel eliminated by the
 // recursive blocking restricted to its own columns (32-column pivot-free
 // leaves, all rows), with its pivot-row copies in the part of T after the
 // look-ahead's own w x n copies (the side stream still reads those).
 int lookahead_width(const Inv& v) {
   if (!v.nopiv) return BMAX;
-  if (v.IBw && (size_t)WPW * v.n <= t_elems(v.n)) return WPW;  // wide panels: one block inverse each
+  if (v.IBw && (size_t)WPW * v.n <= t_elems(v.n)) return wide_width(v.n);  // wide panels: one block inverse each
   for (int w = 4 * BMAX; w > BMAX; w -= BMAX)
     if ((size_t)w * v.n + t_elems_block(w) <= t_elems(v.n)) return w;
   return BMAX;
@@ -1102,7 +1115,7 @@ hipError_t process_block(const Inv& v, int c0, int c1);
 hipError_t lookahead_inverse(const Inv& v) {
   const int n = v.n;
   const int PW = lookahead_width(v);
-  const bool wide = v.nopiv && PW == WPW && v.IBw;
+  const bool wide = v.nopiv && PW == wide_width(n) && v.IBw;
   Inv vp = v;  // in-panel elimination: pivot-row copies after the look-ahead's
   vp.T = v.T + (ll)PW * n;
   hipStream_t X = nullptr;
