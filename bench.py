@@ -374,6 +374,70 @@ def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_b
     print(json.dumps(res), flush=True)
 
 
+def trace_summary(trace_csv, out_path, skip_steps=1):
+    """Per-step kernel table from a rocprofv3 kernel trace (--kernel-trace
+    --output-format csv) of a benchmark run: the trace is cut into steps at
+    every k_leaf_assemble (the first kernel of a step), the first skip_steps
+    (warm-up, with the GEMM tile-tuning trials) are left out, and each kernel
+    name's calls and time are averaged over the remaining steps.  Also: the
+    GEMM family per call (compare roofline.avg_launch_ms of the bench line),
+    kernel time, window (first start to last end) and GPU-busy time (union of
+    the kernel intervals) per step."""
+    import csv
+    import re
+    with open(trace_csv) as f:
+        rows = list(csv.DictReader(f))
+    key = lambda r, *names: next(r[n] for n in names if n in r)
+    ev = sorted((int(key(r, "Start_Timestamp", "start")), int(key(r, "End_Timestamp", "end")),
+                 key(r, "Kernel_Name", "kernel_name", "name")) for r in rows)
+    marks = [i for i, e in enumerate(ev) if re.search(STEP_MARK, e[2])]
+    if len(marks) <= skip_steps:
+        raise SystemExit("trace holds no step after the skipped ones")
+    sel = ev[marks[skip_steps]:]
+    nsteps = len(marks) - skip_steps
+
+    def short(n):
+        n = re.sub(r"^void ", "", n)
+        n = n.replace("hps::(anonymous namespace)::", "").replace("hps::", "")
+        n = re.sub(r"\(.*$", "", n)
+        return n.replace("HIP_vector_type<double, 2u>", "double2").replace("HIP_vector_type<float, 2u>", "float2")
+
+    tot = {}
+    for s0, e0, n in sel:
+        k = short(n)
+        c, t = tot.get(k, (0, 0.0))
+        tot[k] = (c + 1, t + (e0 - s0) * 1e-6)
+    ktime = sum(t for _, t in tot.values())
+    busy, cur_s, cur_e = 0.0, None, None
+    for s0, e0, _ in sel:
+        if cur_e is None or s0 > cur_e:
+            if cur_e is not None:
+                busy += (cur_e - cur_s) * 1e-6
+            cur_s, cur_e = s0, e0
+        else:
+            cur_e = max(cur_e, e0)
+    busy += (cur_e - cur_s) * 1e-6
+    window = (max(e for _, e, _ in sel) - sel[0][0]) * 1e-6
+    gemm = [(c, t) for k, (c, t) in tot.items() if re.search(r"zgemm_kernel|gemm_kernel<double|k_splitk_reduce", k)]
+    main_calls = sum(c for k, (c, _) in tot.items() if re.search(r"zgemm_kernel|gemm_kernel<double", k))
+    gt = sum(t for _, t in gemm)
+    lines = [f"Steps summarised: {nsteps} (after {skip_steps} warm-up step(s) left out).", "",
+             f"Per step: kernel time {ktime / nsteps:.2f} ms, window {window / nsteps:.2f} ms, GPU busy "
+             f"{busy / nsteps:.2f} ms (kernel time above the window: kernels overlapping on a second stream).", "",
+             f"Complex FP64 GEMM family (`zgemm_kernel`, FP64 `gemm_kernel`, `k_splitk_reduce`): "
+             f"{main_calls / nsteps:.0f} calls per step, {gt / nsteps:.2f} ms per step, "
+             f"{gt / max(main_calls, 1) * 1e3:.1f} us per call.", "",
+             "| kernel | calls per step | ms per step | avg us | % of kernel time |", "|---|---|---|---|---|"]
+    for k, (c, t) in sorted(tot.items(), key=lambda x: -x[1][1]):
+        if t / ktime < 0.001:
+            continue
+        lines.append(f"| `{k}` | {c / nsteps:.1f} | {t / nsteps:.2f} | {t / c * 1e3:.1f} | {100 * t / ktime:.1f} |")
+    text = "\n".join(lines) + "\n"
+    with open(out_path, "w") as f:
+        f.write(text)
+    print(text, flush=True)
+
+
 def batch_problems(n=32, seed0=100):
     """32 independent problems: k ~ U[10, 60], leaf grids 8, 16 or 32 per
     side, 16 to 256 directions, contrasts from the 5-bump generator."""
@@ -484,6 +548,8 @@ def main():
                          "there is a warm-up step")
     ap.add_argument("--copy-probe", type=int, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "OUT"),
+                    help="per-step kernel table of a rocprofv3 kernel trace of a benchmark run")
     ap.add_argument("--traffic-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                            "COPY_WRITE_CSV", "COPY_BYTES"),
                     help="write the GEMM traffic summary from four rocprofv3 --pmc runs and exit")
@@ -493,6 +559,8 @@ def main():
         return traffic_summary(a[0], a[1], a[2], a[3], int(a[4]), TRAFFIC_FILE)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.trace_summary:
+        return trace_summary(args.trace_summary[0], args.trace_summary[1])
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (--gpus {args.gpus} "
               "requested). Run with --gpus 1.", file=sys.stderr)
