@@ -193,3 +193,29 @@ def test_leaf_orders_of_the_grid_rule_match_oracle(p, L, k):
     print("  " + ", ".join(f"{n} {e:.1e}" for n, e in errs.items()), flush=True)
     for n, e in errs.items():
         assert e <= 1e-9, (n, e)
+
+
+def test_degenerate_and_empty_inputs():
+    """One direction and one angle against the oracle; a zero perturbation and
+    a zero residual give exactly zero; empty direction or angle lists, R <= 0
+    and non-finite angles are rejected with HPS_EINVAL."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    L, k = 2, 5.0
+    prob, q, _ = _case(L, k, 1, 1, 3)
+    s = _solver(L)
+    s.factor(torch.from_numpy(q).cuda(), k)
+    s.solve(directions(1))
+    _, th = circle_points(2.0, 1)
+    ff = s.far_field(th, 2.0).cpu().numpy()
+    assert ff.shape == (1, 1)
+    assert _rel(ff, prob.far_field()) <= 1e-9
+    jv = s.jvp(torch.zeros(s.npde, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert np.all(jv == 0.0)
+    g = s.vjp(torch.zeros((1, 1), dtype=torch.complex128, device="cuda")).cpu().numpy()
+    assert np.all(g == 0.0)
+    for bad in (lambda: s.solve([]), lambda: s.far_field([], 2.0), lambda: s.far_field(th, 0.0),
+                lambda: s.far_field(th, -1.0), lambda: s.solve([np.nan])):
+        with pytest.raises(hps.HpsError) as e:
+            bad()
+        assert e.value.code == hps.HPS_EINVAL
