@@ -767,6 +767,16 @@ hipError_t zgemm_full(hipStream_t st, int opA, int opB, int M, int N, int K, dou
                       int batch, const int* rmap, int rsplit, ll rpart) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535 || adiv < 1 || bdiv < 1) return hipErrorInvalidValue;
+  // an operand shared by the whole batch is a stride-0 broadcast: the default
+  // kernel (tuned, faster than the shared-operand template) serves it
+  if (adiv >= batch) {
+    adiv = 1;
+    sA = 0;
+  }
+  if (bdiv >= batch) {
+    bdiv = 1;
+    sB = 0;
+  }
   if (rmap && (adiv != 1 || bdiv != 1)) return hipErrorInvalidValue;
   Args a{M, N, K < 0 ? 0 : K, opA, opB, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, rpos, srp, plo, phi,
          adiv, bdiv, K < 0 ? 0 : K, 0, rmap, rsplit, rpart};
