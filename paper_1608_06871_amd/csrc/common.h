@@ -62,6 +62,37 @@ void zinv_set_blocking(int mode);
 void zinv_set_pivoting(int mode, double tol);
 void zinv_pivoting_info(long* calls, long* fallbacks, double* max_err);
 
+// While an RbtDeferScope lives on a thread, butterfly inverses (zinv) do not
+// synchronise for their probe check: each folds its verdict into *flag_dev
+// (|= 1 on a failed check; the failed matrices' zero-pivot flags in info are
+// cleared) and its largest probe error into *maxerr_dev (bit pattern of a
+// non-negative double, updated by atomicMax); both must start at zero.  The
+// caller reads them after its own synchronisation, reports them with
+// zinv_note_deferred, and redoes its work inside an RbtOffScope (pivoted
+// path only) when the flag is set.
+class RbtDeferScope {
+ public:
+  RbtDeferScope(int* flag_dev, unsigned long long* maxerr_dev);
+  ~RbtDeferScope();
+  RbtDeferScope(const RbtDeferScope&) = delete;
+  RbtDeferScope& operator=(const RbtDeferScope&) = delete;
+
+ private:
+  int* prev_flag_;
+  unsigned long long* prev_err_;
+};
+class RbtOffScope {
+ public:
+  RbtOffScope();
+  ~RbtOffScope();
+  RbtOffScope(const RbtOffScope&) = delete;
+  RbtOffScope& operator=(const RbtOffScope&) = delete;
+
+ private:
+  bool prev_;
+};
+void zinv_note_deferred(double max_err, bool fallback);
+
 // Workspace sizes (bytes) for zinv with matrices of order n in batches of `batch`.
 size_t zinv_workspace(int n, int batch);
 size_t zinv_perm_workspace(int n, int batch);

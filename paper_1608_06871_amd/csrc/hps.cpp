@@ -36,6 +36,7 @@
 #include "../../include/hps_blocks.h"
 
 #include <chrono>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -153,7 +154,7 @@ struct hps_ctx {
   // column-major operands, which the matrix cores stream faster)
   DBuf dRrootH, dZinvH;
   std::vector<DBuf> dD, dU;
-  DBuf sA, sInv, sZws, sR0, sR1, sBlk, sW, sWinv, sQ, sVin, sV, sTmp, sInfo;
+  DBuf sA, sInv, sZws, sR0, sR1, sBlk, sW, sWinv, sQ, sVin, sV, sTmp, sInfo, sRbt;
 
   // solve
   bool solved = false;
@@ -521,12 +522,13 @@ void plan_factor_buffers(hps_ctx* c) {
   }
 }
 
-void factor(hps_ctx* c, const double* q, const double* kv) {
-  require(q != nullptr, HPS_EINVAL, "q_nodes is NULL");
-  bool same = c->have_k;
-  for (int b = 0; b < c->P && same; ++b) same = (kv[b] == c->kv[b]);
-  if (!same) set_wavenumbers(c, kv);
+// One factorisation pass.  With defer, the butterfly inverses report their
+// probe checks through the device flag read at this pass's single
+// synchronisation; returns false (nothing reported) when a check failed, so
+// that the caller redoes the pass on the pivoted path.
+bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   plan_factor_buffers(c);
+  c->sRbt.ensure(16);  // [int verdict flag | pad | u64 largest probe error]
   const Geometry& g = c->g;
   hipStream_t st = c->st;
   const int P = c->P;
@@ -543,7 +545,10 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   // (1: the contrast, 2: the top inverse)
   int* nonfinite = c->sInfo.i() + ninfo;
   CK(hipMemsetAsync(c->sInfo.p, 0, sizeof(int) * (ninfo + 1), st));
+  CK(hipMemsetAsync(c->sRbt.p, 0, 16, st));
   CK(flag_nonfinite(st, q, (ll)P * g.nleaf * mi, 1, nonfinite));
+  std::unique_ptr<RbtDeferScope> defer_scope;
+  if (defer) defer_scope.reset(new RbtDeferScope(c->sRbt.i(), (unsigned long long*)((char*)c->sRbt.p + 8)));
 
   // leaf stage (all leaves of all problems)
   // S = S0 - k^2 diag(q) per leaf, inverted (the blocks of problem z / lpp)
@@ -667,15 +672,39 @@ void factor(hps_ctx* c, const double* q, const double* kv) {
   mark(c, 0, 1);
   profile_set_phase(PH_OTHER);
   std::vector<int> info(ninfo + 1);
+  unsigned long long rbt[2] = {0, 0};
   CK(hipMemcpyAsync(info.data(), c->sInfo.p, sizeof(int) * (ninfo + 1), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(rbt, c->sRbt.p, 16, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  c->singular = 0;
-  for (int i = 0; i < ninfo; ++i) c->singular |= (info[i] != 0);
+  defer_scope.reset();
   c->nonfinite = info[ninfo];
   if (c->nonfinite & 1) throw HpsError{HPS_ENONFINITE, "the contrast q holds a NaN or infinite value"};
+  if (defer) {
+    int flag = 0;
+    double max_err = 0.0;
+    std::memcpy(&flag, &rbt[0], sizeof(int));
+    std::memcpy(&max_err, &rbt[1], sizeof(double));
+    zinv_note_deferred(max_err, flag != 0);
+    if (flag) return false;
+  }
+  c->singular = 0;
+  for (int i = 0; i < ninfo; ++i) c->singular |= (info[i] != 0);
   if (c->singular) throw HpsError{HPS_ESINGULAR, "zero pivot in the factorisation"};
   if (c->nonfinite) throw HpsError{HPS_ENONFINITE, "the factorisation produced a NaN or infinite value"};
   c->factored = true;
+  return true;
+}
+
+void factor(hps_ctx* c, const double* q, const double* kv) {
+  require(q != nullptr, HPS_EINVAL, "q_nodes is NULL");
+  bool same = c->have_k;
+  for (int b = 0; b < c->P && same; ++b) same = (kv[b] == c->kv[b]);
+  if (!same) set_wavenumbers(c, kv);
+  // the butterfly inverses' checks are read once per pass; a failed check
+  // (not met so far on any workload) redoes the pass with pivoting
+  if (factor_pass(c, q, true)) return;
+  RbtOffScope pivoted;
+  factor_pass(c, q, false);
 }
 
 void plan_sweep_buffers(hps_ctx* c, int M) {

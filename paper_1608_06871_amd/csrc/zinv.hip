@@ -888,6 +888,25 @@ __global__ __launch_bounds__(256) void k_probe_err(const double2* X0, const doub
   if (threadIdx.x == 0) err[bi] = sqrt(sn[0] / sd[0]);
 }
 
+// Deferred verdict of a butterfly inverse: flag |= 1 when a matrix's probe
+// error exceeds tol (or is NaN) or its pivot-free elimination met a zero
+// pivot; that zero-pivot flag is cleared (the pivoted redo decides real
+// singularity).  maxerr keeps the largest probe error as the bit pattern of a
+// non-negative double (ordered like the value; NaN stores +inf).
+__global__ __launch_bounds__(256) void k_probe_verdict(const double* err, int* info, int batch, double tol,
+                                                       int* flag, unsigned long long* maxerr) {
+  for (int b = threadIdx.x; b < batch; b += 256) {
+    const double e = err[b];
+    const bool bad = !(e <= tol) || info[b] != 0;
+    if (bad) {
+      atomicOr(flag, 1);
+      info[b] = 0;
+    }
+    const double em = e == e ? e : INFINITY;
+    atomicMax(maxerr, (unsigned long long)__double_as_longlong(em));
+  }
+}
+
 size_t cand_ints(int n, int batch) { return (size_t)batch * ((n + TR - 1) / TR) * BMAX; }
 
 // Split point of a block of w > BMAX columns: half of its panels, rounded up.
@@ -1226,9 +1245,13 @@ std::atomic<double> g_rbt_maxerr{0.0};
 constexpr int NPROBE = 2;
 constexpr unsigned RBT_SEED_U = 0x5a17u, RBT_SEED_V = 0x3c6du;
 
+thread_local bool g_rbt_off = false;               // RbtOffScope active on this thread
+thread_local int* g_defer_flag = nullptr;           // RbtDeferScope: verdict flag
+thread_local unsigned long long* g_defer_err = nullptr;  // RbtDeferScope: largest probe error
+
 bool use_rbt(int n, int batch) {
   (void)batch;
-  if (no_alloc_active() || n % 4 != 0 || n < 8) return false;
+  if (no_alloc_active() || g_rbt_off || n % 4 != 0 || n < 8) return false;
   int m = g_pivoting.load();
   if (m == -2) {
     const char* e = std::getenv("HPS_ZINV_PIVOTING");
@@ -1254,6 +1277,25 @@ size_t std_workspace(int n, int batch, bool wide) {
 }  // namespace
 
 void zinv_set_blocking(int mode) { g_blocking.store(mode); }
+
+RbtDeferScope::RbtDeferScope(int* flag_dev, unsigned long long* maxerr_dev)
+    : prev_flag_(g_defer_flag), prev_err_(g_defer_err) {
+  g_defer_flag = flag_dev;
+  g_defer_err = maxerr_dev;
+}
+RbtDeferScope::~RbtDeferScope() {
+  g_defer_flag = prev_flag_;
+  g_defer_err = prev_err_;
+}
+RbtOffScope::RbtOffScope() : prev_(g_rbt_off) { g_rbt_off = true; }
+RbtOffScope::~RbtOffScope() { g_rbt_off = prev_; }
+
+void zinv_note_deferred(double max_err, bool fallback) {
+  if (fallback) g_rbt_fallbacks.fetch_add(1);
+  double prev = g_rbt_maxerr.load();
+  while ((std::isnan(max_err) || max_err > prev) && !g_rbt_maxerr.compare_exchange_weak(prev, max_err)) {
+  }
+}
 
 void zinv_set_pivoting(int mode, double tol) {
   g_pivoting.store(mode);
@@ -1378,6 +1420,15 @@ hipError_t rbt_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, doub
   HPS_HIP_TRY(zgemm(st, OP_N, OP_N, n, NPROBE, n, one, out, ldo, sO, Y, n, per, zero, X1, n, per, batch));
   hipLaunchKernelGGL(k_probe_err, dim3(batch), dim3(256), 0, st, X0, X1, per, err);
   HPS_HIP_TRY(hipGetLastError());
+  if (g_defer_flag) {
+    // the caller reads the verdict at its own synchronisation and redoes its
+    // work on the pivoted path if any check failed
+    hipLaunchKernelGGL(k_probe_verdict, dim3(1), dim3(256), 0, st, err, info, batch, g_rbt_tol.load(),
+                       g_defer_flag, g_defer_err);
+    HPS_HIP_TRY(hipGetLastError());
+    g_rbt_calls.fetch_add(1);
+    return hipSuccess;
+  }
   std::vector<double> he(batch);
   std::vector<int> hi(batch);
   HPS_HIP_TRY(hipMemcpyAsync(he.data(), err, sizeof(double) * batch, hipMemcpyDeviceToHost, st));

@@ -219,3 +219,40 @@ def test_degenerate_and_empty_inputs():
         with pytest.raises(hps.HpsError) as e:
             bad()
         assert e.value.code == hps.HPS_EINVAL
+
+
+def test_deferred_butterfly_check_redoes_factorisation_pivoted():
+    """The factorisation reads its butterfly inverses' probe checks once, at
+    its own synchronisation.  Forced from the host (probe tolerance 0, so
+    every check fails), it must count one fallback per factorisation, redo
+    the pass on the pivoted path and give exactly the always-pivoted result;
+    with the default tolerance it matches the oracle golden path to 1e-9."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    L, k, M, P = 16, 40.0, 4, 16
+    s = hps.Solver(nleaf=L, p=16)
+    inp = synth.parity_inputs(s.node_coords(), M, P, seed=7)
+    q = torch.from_numpy(inp["q"]).cuda()
+    th = synth.equispaced_angles(P)
+
+    def run():
+        s.factor(q, k)
+        s.solve(synth.equispaced_angles(M))
+        return s.far_field(th, 2.0).cpu(), s.vjp(torch.from_numpy(inp["r"]).cuda()).cpu()
+
+    try:
+        hps.zinv_pivoting(0)
+        ref = run()
+        hps.zinv_pivoting(-1, 0.0)
+        before = hps.zinv_pivoting_info()
+        got = run()
+        after = hps.zinv_pivoting_info()
+        print(f"fallbacks {after['fallbacks'] - before['fallbacks']}, calls {after['calls'] - before['calls']}",
+              flush=True)
+        assert after["fallbacks"] == before["fallbacks"] + 1
+        assert after["calls"] > before["calls"]
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    finally:
+        hps.zinv_pivoting(-1, 1e-10)
+    ok = run()
+    assert _rel(ok[0].numpy(), ref[0].numpy()) <= 1e-9
