@@ -155,6 +155,11 @@ struct hps_ctx {
   DBuf dRrootH, dZinvH;
   std::vector<DBuf> dD, dU;
   DBuf sA, sInv, sZws, sR0, sR1, sBlk, sW, sWinv, sQ, sVin, sV, sTmp, sInfo, sRbt;
+  // per merge level, the block moves that depend only on the children's maps
+  // (one launch per level; built and uploaded once per factorisation)
+  std::vector<MoveDesc> hMoves;
+  std::vector<int> moveOff;
+  DBuf dMoves;
 
   // solve
   bool solved = false;
@@ -522,6 +527,73 @@ void plan_factor_buffers(hps_ctx* c) {
   }
 }
 
+// The block moves of every merge level that depend only on the children's
+// maps (gathers of the child blocks, the identity of W, the -B32 part of Q,
+// the -A31 and zero parts of D's lower half, the parent map's diagonal and
+// zero blocks, and V's and Tm's fixed parts), as one list per level, uploaded
+// to the device.  The moves of a level write disjoint elements; they run at
+// the start of the level, before the products that read or complete them.
+void build_merge_moves(hps_ctx* c) {
+  const Geometry& g = c->g;
+  const int P = c->P;
+  const bool derivs = c->o.keep_derivs || c->mixed;
+  c->hMoves.clear();
+  c->moveOff.assign(g.nlev + 2, 0);
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0), mone = make_double2(-1.0, 0.0);
+  const double2* Rc = c->sR0.z();
+  for (int l = 1; l <= g.nlev; ++l) {
+    c->moveOff[l] = (int)c->hMoves.size();
+    const LevelPattern& L = g.lev[l];
+    const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;
+    (void)cnt;
+    const int* i1a = c->didx[4 * l].i();
+    const int* i3a = c->didx[4 * l + 1].i();
+    const int* i2b = c->didx[4 * l + 2].i();
+    const int* i3b = c->didx[4 * l + 3].i();
+    const ll sc = 2LL * nc * nc;
+    const double2* Ra = Rc;
+    const double2* Rb = Rc + (ll)nc * nc;
+    double2* Rn = (Rc == c->sR0.z()) ? c->sR1.z() : c->sR0.z();
+    const ll ms = (ll)m * s, ss = (ll)s * s, sp = (ll)np * np, sd = 4 * ms, sq = 2 * ms, sv = 2 * ss;
+    double2* A13 = c->sBlk.z();
+    double2* A31 = A13 + (ll)cnt * ms;
+    double2* A33 = A31 + (ll)cnt * ms;
+    double2* B23 = A33 + (ll)cnt * ss;
+    double2* B33 = B23 + (ll)cnt * ms;
+    double2* D = c->dD[l].z();
+    auto gather = [&](int M, int N, const double2* in, const int* ri, const int* ci, double2* out, ll ldo,
+                      ll so, double scale) {
+      c->hMoves.push_back(MoveDesc{in, nc, sc, ri, ci, out, ldo, so, M, N, 0, 0, scale, zero, zero});
+    };
+    auto fill = [&](int M, int N, double2* out, ll ldo, ll so, double2 diag, double2 off) {
+      c->hMoves.push_back(MoveDesc{nullptr, 0, 0, nullptr, nullptr, out, ldo, so, M, N, 1, 0, 0.0, diag, off});
+    };
+    gather(m, s, Ra, i1a, i3a, A13, m, ms, 1.0);
+    gather(s, m, Ra, i3a, i1a, A31, s, ms, 1.0);
+    gather(s, s, Ra, i3a, i3a, A33, s, ss, 1.0);
+    gather(m, s, Rb, i2b, i3b, B23, m, ms, 1.0);
+    gather(s, s, Rb, i3b, i3b, B33, s, ss, 1.0);
+    fill(s, s, c->sW.z(), s, ss, one, zero);                                   // W = I (- B33 A33 below)
+    gather(s, m, Rb, i3b, i2b, c->sQ.z() + ms, s, sq, -1.0);                   // Q = [., -B32]
+    gather(s, m, Ra, i3a, i1a, D + s, 2 * s, sd, -1.0);                        // Yb = [-A31, 0] (- A33 X)
+    fill(s, m, D + s + (ll)m * 2 * s, 2 * s, sd, zero, zero);
+    gather(m, m, Ra, i1a, i1a, Rn, np, sp, 1.0);                               // R = blkdiag(A11, B22) + ...
+    gather(m, m, Rb, i2b, i2b, Rn + m + (ll)m * np, np, sp, 1.0);
+    fill(m, m, Rn + (ll)m * np, np, sp, zero, zero);
+    fill(m, m, Rn + m, np, sp, zero, zero);
+    if (derivs) {
+      gather(s, s, Rb, i3b, i3b, c->sVin.z(), s, sv, 1.0);                     // V_in = [B33, -I]
+      fill(s, s, c->sVin.z() + ss, s, sv, mone, zero);
+      fill(s, 2 * s, c->sTmp.z(), s, sv, one, zero);                           // Tm = [I, 0] (+ A33 V)
+    }
+    Rc = Rn;
+  }
+  c->moveOff[g.nlev + 1] = (int)c->hMoves.size();
+  c->dMoves.ensure(std::max<size_t>(1, c->hMoves.size()) * sizeof(MoveDesc));
+  CK(hipMemcpyAsync(c->dMoves.p, c->hMoves.data(), c->hMoves.size() * sizeof(MoveDesc), hipMemcpyHostToDevice,
+                    c->st));
+}
+
 // One factorisation pass.  With defer, the butterfly inverses report their
 // probe checks through the device flag read at this pass's single
 // synchronisation; returns false (nothing reported) when a check failed, so
@@ -578,51 +650,44 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   // merge tree
   mark(c, 6, 0);
   profile_set_phase(PH_MERGE);
+  build_merge_moves(c);
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
-    const int cnt = L.count * P, m = L.m, s = L.s, nc = L.nc, np = L.np;    const int* i1a = c->didx[4 * l].i();
-    const int* i3a = c->didx[4 * l + 1].i();
-    const int* i2b = c->didx[4 * l + 2].i();
-    const int* i3b = c->didx[4 * l + 3].i();
-    const ll sc = 2LL * nc * nc;
-    const double2* Ra = Rc;
-    const double2* Rb = Rc + (ll)nc * nc;
+    const int cnt = L.count * P, m = L.m, s = L.s, np = L.np;
     double2* A13 = c->sBlk.z();
     double2* A31 = A13 + (ll)cnt * m * s;
     double2* A33 = A31 + (ll)cnt * s * m;
     double2* B23 = A33 + (ll)cnt * s * s;
     double2* B33 = B23 + (ll)cnt * m * s;
     const ll ms = (ll)m * s, ss = (ll)s * s;
-    CK(gather2d(st, m, s, Ra, nc, sc, i1a, i3a, A13, m, ms, 1.0, cnt));
-    CK(gather2d(st, s, m, Ra, nc, sc, i3a, i1a, A31, s, ms, 1.0, cnt));
-    CK(gather2d(st, s, s, Ra, nc, sc, i3a, i3a, A33, s, ss, 1.0, cnt));
-    CK(gather2d(st, m, s, Rb, nc, sc, i2b, i3b, B23, m, ms, 1.0, cnt));
-    CK(gather2d(st, s, s, Rb, nc, sc, i3b, i3b, B33, s, ss, 1.0, cnt));
+    // the child blocks, the identity of W, the -B32 and -A31 parts of Q and D,
+    // the parent map's diagonal blocks and zero blocks (and V's and Tm's fixed
+    // parts): one launch of independent moves
+    {
+      const int o0 = c->moveOff[l], o1 = c->moveOff[l + 1];
+      ll mx = 0;
+      for (int t = o0; t < o1; ++t)
+        mx = std::max(mx, (ll)c->hMoves[t].M * c->hMoves[t].N * cnt);
+      CK(multi_move(st, (const MoveDesc*)c->dMoves.p + o0, o1 - o0, mx, cnt));
+    }
     // W = I - B33 A33, inverted
     double2* W = c->sW.z();
     double2* Wi = c->sWinv.z();
-    CK(set2d(st, s, s, W, s, ss, ONE, ZERO, cnt));
     CK(zgemm(st, OP_N, OP_N, s, s, s, MONE, B33, s, ss, A33, s, ss, ONE, W, s, ss, cnt));
     CK(zinv(st, s, W, s, ss, Wi, s, ss, cnt, c->sZws.p, c->sInfo.i()));
     // Q = [B33 A31, -B32]
     double2* Q = c->sQ.z();
     const ll sq = 2 * ms;
     CK(zgemm(st, OP_N, OP_N, s, m, s, ONE, B33, s, ss, A31, s, ms, ZERO, Q, s, sq, cnt));
-    CK(gather2d(st, s, m, Rb, nc, sc, i3b, i2b, Q + ms, s, sq, -1.0, cnt));
     // D = [X; Yb]
     double2* D = c->dD[l].z();
     const ll sd = 4 * ms;
     CK(zgemm(st, OP_N, OP_N, s, 2 * m, s, ONE, Wi, s, ss, Q, s, sq, ZERO, D, 2 * s, sd, cnt));
-    CK(gather2d(st, s, m, Ra, nc, sc, i3a, i1a, D + s, 2 * s, sd, -1.0, cnt));
-    CK(set2d(st, s, m, D + s + (ll)m * 2 * s, 2 * s, sd, ZERO, ZERO, cnt));
     CK(zgemm(st, OP_N, OP_N, s, 2 * m, s, MONE, A33, s, ss, D, 2 * s, sd, ONE, D + s, 2 * s, sd,
              cnt));
     // parent map
     double2* Rn = (Rc == c->sR0.z()) ? c->sR1.z() : c->sR0.z();
     const ll sp = (ll)np * np;
-    CK(set2d(st, np, np, Rn, np, sp, ZERO, ZERO, cnt));
-    CK(gather2d(st, m, m, Ra, nc, sc, i1a, i1a, Rn, np, sp, 1.0, cnt));
-    CK(gather2d(st, m, m, Rb, nc, sc, i2b, i2b, Rn + m + (ll)m * np, np, sp, 1.0, cnt));
     CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, A13, m, ms, D, 2 * s, sd, ONE, Rn, np, sp, cnt));
     CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, B23, m, ms, D + s, 2 * s, sd, ONE, Rn + m, np, sp,
              cnt));
@@ -631,12 +696,9 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
       double2* V = c->sV.z();
       double2* Tm = c->sTmp.z();
       const ll sv = 2 * ss;
-      CK(gather2d(st, s, s, B33, s, ss, nullptr, nullptr, Vin, s, sv, 1.0, cnt));
-      CK(set2d(st, s, s, Vin + ss, s, sv, MONE, ZERO, cnt));
       CK(zgemm(st, OP_N, OP_N, s, 2 * s, s, ONE, Wi, s, ss, Vin, s, sv, ZERO, V, s, sv, cnt));
       double2* U = c->dU[l].z();
       CK(zgemm(st, OP_N, OP_N, m, 2 * s, s, ONE, A13, m, ms, V, s, sv, ZERO, U, 2 * m, sd, cnt));
-      CK(set2d(st, s, 2 * s, Tm, s, sv, ONE, ZERO, cnt));
       CK(zgemm(st, OP_N, OP_N, s, 2 * s, s, ONE, A33, s, ss, V, s, sv, ONE, Tm, s, sv, cnt));
       CK(zgemm(st, OP_N, OP_N, m, 2 * s, s, MONE, B23, m, ms, Tm, s, sv, ZERO, U + m, 2 * m, sd,
                cnt));

@@ -48,6 +48,25 @@ hipError_t skel_residual(hipStream_t st, int s, int M, int ne, int lpm, const in
 // per box).
 hipError_t skel_gather(hipStream_t st, int n, int M, int ne, int lpb, const int* slot, const double2* X,
                        double2* out, int nbox);
+// One batched block move: out_b(i, j) = sc * in_b(ridx[i], cidx[j]) (null
+// index arrays = identity), or, when set != 0, out_b(i, j) = diag on the
+// diagonal and off elsewhere (in unused).  Batch strides si, so.
+struct MoveDesc {
+  const double2* in;
+  ll ldi, si;
+  const int* ridx;
+  const int* cidx;
+  double2* out;
+  ll ldo, so;
+  int M, N, set, pad;
+  double sc;
+  double2 diag, off;
+};
+// Applies ndesc independent moves (device array `desc`, over `batch` matrices
+// each) in one launch; the moves must write disjoint elements.  max_elems:
+// the largest M * N * batch among them.
+hipError_t multi_move(hipStream_t st, const MoveDesc* desc, int ndesc, ll max_elems, int batch);
+
 // out = off everywhere, diag on the diagonal.
 hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
                  double2 off, int batch);

@@ -92,6 +92,29 @@ __global__ void k_set2d(int M, int N, double2* out, ll ldo, ll so, double2 diag,
   }
 }
 
+// Row y of the grid applies move desc[y]; its elements are covered by a
+// grid-stride loop over x.
+__global__ void k_multi_move(const MoveDesc* desc, int batch) {
+  const MoveDesc d = desc[blockIdx.y];
+  const ll per = (ll)d.M * d.N;
+  const ll total = per * batch;
+  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
+    const ll b = idx / per;
+    const int e = (int)(idx % per);
+    const int i = e % d.M, j = e / d.M;
+    double2 v;
+    if (d.set) {
+      v = (i == j) ? d.diag : d.off;
+    } else {
+      const int ri = d.ridx ? d.ridx[i] : i;
+      const int cj = d.cidx ? d.cidx[j] : j;
+      const double2 x = d.in[b * d.si + (ll)ri + (ll)cj * d.ldi];
+      v = make_double2(d.sc * x.x, d.sc * x.y);
+    }
+    d.out[b * d.so + (ll)i + (ll)j * d.ldo] = v;
+  }
+}
+
 // Rows [0, nb): d_nu u_inc; rows [nb, 2 nb): u_inc, one column per direction;
 // column m belongs to problem m / ndir (wavenumber kv[m / ndir]).
 __global__ void k_incident(const double4* bnode, int nb, const double2* dirs, int ndir, const double* kv,
@@ -416,6 +439,16 @@ hipError_t leaf_assemble(hipStream_t st, const double2* A0, ll sA0, const double
   KernelTimer kt(st, K_LEAF, 0.0, 16.0 * (double)n * n * nleaf + 8.0 * mi * (double)nleaf);
   hipLaunchKernelGGL(k_leaf_assemble, dim3(blocks_for((ll)n * n * nleaf)), dim3(NT), 0, st, A0, sA0, q,
                      k2v, n, mi, out, nleaf, lpp);
+  return hipGetLastError();
+}
+
+hipError_t multi_move(hipStream_t st, const MoveDesc* desc, int ndesc, ll max_elems, int batch) {
+  if (ndesc <= 0 || max_elems <= 0 || batch <= 0) return hipSuccess;
+  if (ndesc > 65535) return hipErrorInvalidValue;
+  KernelTimer kt(st, K_MOVE, 0.0, 0.0);
+  unsigned bx = blocks_for(max_elems);
+  if (bx > 4096) bx = 4096;  // grid-stride beyond: most rows of the grid hold small moves
+  hipLaunchKernelGGL(k_multi_move, dim3(bx, ndesc), dim3(NT), 0, st, desc, batch);
   return hipGetLastError();
 }
 
