@@ -466,7 +466,7 @@ void set_wavenumber(hps_ctx* c, double k) {
 void plan_factor_buffers(hps_ctx* c) {
   const Geometry& g = c->g;
   const size_t P = c->P;
-  const size_t nl = (size_t)g.nleaf * P, n = c->n, ne = g.ne, mi = g.mi, nb = c->nb;
+  const size_t nl = (size_t)g.nleaf * P, ne = g.ne, mi = g.mi, nb = c->nb;
   size_t zws = zinv_workspace((int)mi, (int)nl);
   size_t rmax = nl * ne * ne, blk = 0, w = 0, q = 0, v = 0;
   for (int l = 1; l <= g.nlev; ++l) {
@@ -480,7 +480,7 @@ void plan_factor_buffers(hps_ctx* c) {
     v = std::max(v, cnt * 2 * s * s);
   }
   zws = std::max(zws, zinv_workspace((int)nb, (int)P));
-  c->sA.ensure(zb(std::max(nl * n * n, P * nb * nb)));
+  c->sA.ensure(zb(std::max(nl * mi * mi, P * nb * nb)));  // leaf impedance problems, then Z
   c->sInv.ensure(zb(nl * mi * mi));  // leaf stage: S^-1
   c->sZws.ensure(zws);
   c->sR0.ensure(zb(rmax));

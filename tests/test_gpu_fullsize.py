@@ -57,3 +57,35 @@ def test_zero_contrast_k80_full_size(solver):
     solver.solve(synth.equispaced_angles(16))
     uf = solver.far_field(synth.equispaced_angles(P), R).cpu().numpy()
     assert np.max(np.abs(uf)) < 1e-8
+
+
+def test_radial_contrast_k160_largest_grid():
+    """The largest grid tested: 128 x 128 leaves of 16 x 16 (4.0M unknowns,
+    outer boundary 7168 nodes, a 14-level tree, the 7168-order top inverse),
+    k = 160 (38 points per wavelength), against the oracle's separation-of-
+    variables reference (tests/golden/radial_k160.txt, written by
+    tests/golden/make_radial_k160.py from oracle/radial.py only); then zero
+    contrast on the same factorised grid."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    K2, L2, M2, P2 = 160.0, 128, 16, 64
+    print("largest grid: k=160, 128x128 leaves, 16 x 64", flush=True)
+    s = hps.Solver(nleaf=L2, p=16, keep_derivs=False)
+    amp, sig = 0.4, 0.2
+    q = synth.radial_gaussian(s.node_coords(), amp, sig)
+    s.factor(torch.from_numpy(q).cuda(), K2)
+    dirs = synth.equispaced_angles(M2)
+    th = synth.equispaced_angles(P2)
+    s.solve(dirs)
+    uf = s.far_field(th, R).cpu().numpy()
+    tab = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "radial_k160.txt"))
+    coef = tab[:, 1] + 1j * tab[:, 2]
+    ref = scattered_from_modes(coef, th[None, :] - dirs[:, None])
+    err = np.max(np.abs(uf - ref)) / np.max(np.abs(ref))
+    print(f"max relative error {err:.2e}", flush=True)
+    assert err < 1e-8
+    s.factor(torch.zeros(s.npde, dtype=torch.float64, device="cuda"), K2)
+    s.solve(dirs)
+    assert np.max(np.abs(s.far_field(th, R).cpu().numpy())) < 1e-8
+    del s
+    torch.cuda.empty_cache()
