@@ -71,8 +71,9 @@ hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
 #define HPS_NOALLOC_SCRATCH_BYTES (64LL << 20)
 hps_status hps_zinv_noalloc(void* stream, int n, int batch, double* A, double* inv, int* status_dev);
 
-/* Column blocking of the inverses of order above 512 (hps_zinv and the
- * factorisation's W and Z inverses), process-wide; a performance choice, both
+/* Column blocking of the inverses of order above 512, and of the
+ * butterfly-transformed ones (pivot-free panels) from order 320 (hps_zinv and
+ * the factorisation's W and Z inverses), process-wide; a performance choice, both
  * give the inverse to rounding (the merges and the top of the Section 2
  * direct solver only use the products with W^{-1} and Z^{-1}):
  *   mode 1: right-looking with one panel of look-ahead (the next panel's

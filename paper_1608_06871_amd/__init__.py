@@ -421,7 +421,8 @@ def gemm_tuning(mode=1, force=-1):
 
 
 def zinv_blocking(mode=-1):
-    """Column blocking of the inverses of order above 512 (process-wide):
+    """Column blocking of the inverses of order above 512 and of the
+    butterfly-transformed ones from order 320 (process-wide):
     1 right-looking with look-ahead, 0 recursive, -1 by size (look-ahead while
     the batch fits the last-level cache)."""
     rc = lib().hps_zinv_blocking(int(mode))

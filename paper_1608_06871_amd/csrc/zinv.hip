@@ -909,10 +909,15 @@ __global__ __launch_bounds__(256) void k_probe_verdict(const double* err, int* i
 
 size_t cand_ints(int n, int batch) { return (size_t)batch * ((n + TR - 1) / TR) * BMAX; }
 
-// Split point of a block of w > BMAX columns: half of its panels, rounded up.
+// Split point of a block of w > BMAX columns: its np = ceil(w / BMAX) panels
+// are spread evenly and the left part takes ceil(np / 2) of them, rounded to
+// a multiple of 4 columns.  Even panels keep every product's width close to a
+// multiple of the GEMM tile (order 196: seven panels of 28 columns, products
+// 84 and 112 wide, where halves of whole 32-column panels gave 128 + 68 and a
+// 4-column panel with products of width 4 and 68).
 int split_at(int c0, int w) {
-  const int np = (w + BMAX - 1) / BMAX;
-  return c0 + BMAX * ((np + 1) / 2);
+  const int np = (w + BMAX - 1) / BMAX, n1 = (np + 1) / 2;
+  return c0 + 4 * ((w * n1 + 2 * np) / (4 * np));
 }
 
 // Largest w x nd product over the recursion on a block of w columns.
@@ -1205,8 +1210,8 @@ hipError_t process_block(const Inv& v, int c0, int c1) {
   return block_update(v, m, c1, c0, m);
 }
 
-// Orders above the register-panel limit: right-looking with look-ahead, or
-// the recursive column blocking.  The right-looking scheme reads and writes
+// Orders above the register-panel limit, and pivot-free (butterfly) ones from
+// order 320: right-looking with look-ahead, or the recursive column blocking.  The right-looking scheme reads and writes
 // every matrix of the batch once per 32-column panel, which pays while the
 // batch stays resident in the 256 MB last-level cache; larger batches take
 // the recursive blocking, whose fewer, larger products need less traffic.
@@ -1358,9 +1363,12 @@ hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int ba
     hipLaunchKernelGGL(gj_init, dim3((n + 255) / 256, batch), dim3(256), 0, st, v.pos, n);
   }
   HPS_HIP_TRY(hipGetLastError());
-  // (the look-ahead's pivot-row copies, b x n, fit the T buffer only above
-  // the register-panel limit)
-  return n > NS_MAX_N && use_lookahead(n, batch) ? lookahead_inverse(v) : process_block(v, 0, n);
+  // (the look-ahead's pivot-row copies, b x n, fit the T buffer above the
+  // register-panel limit, and below it for the pivot-free wide panels once
+  // WPW x n <= t_elems(n), i.e. from order 320: the order-448
+  // merge matrices take 7 wide panels instead of 14 recursive 32-column ones)
+  const bool la_fits = n > NS_MAX_N || (nopiv && wide_ws && (size_t)WPW * n <= t_elems(n));
+  return la_fits && use_lookahead(n, batch) ? lookahead_inverse(v) : process_block(v, 0, n);
 }
 
 hipError_t pivoted_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO,

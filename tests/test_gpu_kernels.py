@@ -156,6 +156,35 @@ def test_zinv_blockings_agree(n, batch, mode):
         assert err < 1e-11, (b, err)
 
 
+@pytest.mark.parametrize("n", [320, 448, 452])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_zinv_butterfly_blockings_agree(n, mode):
+    """Butterfly-transformed orders from 320 up to the register-panel limit
+    take the look-ahead with wide pivot-free panels under blocking 1 (and the
+    default rule) and the recursive 32-column panels under 0: both give
+    inv A = I to rounding with no fallback to the pivoted path; 452 ends with
+    a 4-column panel."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    batch = 2
+    print(f"zinv butterfly n={n} blocking={mode}", flush=True)
+    rng = np.random.default_rng(n + 11 * mode)
+    A = _rand(rng, (batch, n, n)) + 2.0 * np.sqrt(n) * np.eye(n)[None]
+    Ag = _colmajor(torch, A)
+    before = hps.zinv_pivoting_info()
+    hps.zinv_blocking(mode)
+    try:
+        inv = hps.zinv(Ag.clone())
+    finally:
+        hps.zinv_blocking(-1)
+    after = hps.zinv_pivoting_info()
+    assert after["calls"] == before["calls"] + 1 and after["fallbacks"] == before["fallbacks"]
+    prod = _back(hps.zgemm(inv, Ag))
+    for b in range(batch):
+        err = np.max(np.abs(prod[b] - np.eye(n)))
+        assert err < 1e-11, (b, err)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_zinv_reports_singular_tournament(mode):
     """A zero column in an order-700 matrix (tournament path; the zero pivot is
