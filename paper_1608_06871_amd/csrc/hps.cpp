@@ -589,6 +589,7 @@ void build_merge_moves(hps_ctx* c) {
     Rc = Rn;
   }
   c->moveOff[g.nlev + 1] = (int)c->hMoves.size();
+  multi_move_prepare(c->hMoves.data(), (int)c->hMoves.size());
   c->dMoves.ensure(std::max<size_t>(1, c->hMoves.size()) * sizeof(MoveDesc));
   CK(hipMemcpyAsync(c->dMoves.p, c->hMoves.data(), c->hMoves.size() * sizeof(MoveDesc), hipMemcpyHostToDevice,
                     c->st));

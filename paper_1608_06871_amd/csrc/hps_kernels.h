@@ -51,6 +51,16 @@ hipError_t skel_gather(hipStream_t st, int n, int M, int ne, int lpb, const int*
 // One batched block move: out_b(i, j) = sc * in_b(ridx[i], cidx[j]) (null
 // index arrays = identity), or, when set != 0, out_b(i, j) = diag on the
 // diagonal and off elsewhere (in unused).  Batch strides si, so.
+// Exact unsigned division by a fixed d >= 1 for numerators below 2^31
+// (Granlund and Montgomery, PLDI 1994): q = umulhi(n, mul) >> shift with
+// mul = ceil(2^(31 + l) / d), l = ceil(log2 d), shift = l - 1; mul = 0 encodes
+// d = 1 (q = n).
+struct FastDiv {
+  unsigned mul;
+  int shift;
+};
+FastDiv make_fastdiv(int d);
+
 struct MoveDesc {
   const double2* in;
   ll ldi, si;
@@ -61,7 +71,12 @@ struct MoveDesc {
   int M, N, set, pad;
   double sc;
   double2 diag, off;
+  unsigned fdm;  // division by M (make_fastdiv; set by multi_move_prepare)
+  int fds;
 };
+// Fills the division parameters of host-side descriptors before their copy
+// to the device.
+void multi_move_prepare(MoveDesc* desc, int ndesc);
 // Applies ndesc independent moves (device array `desc`, over `batch` matrices
 // each) in one launch; the moves must write disjoint elements.  max_elems:
 // the largest M * N * batch among them.

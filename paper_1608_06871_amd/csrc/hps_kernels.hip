@@ -16,102 +16,130 @@ inline unsigned blocks_for(ll n) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+// Quotient of n < 2^31 by the divisor that (mul, shift) encode (make_fastdiv).
+__device__ __forceinline__ unsigned fdiv(unsigned n, unsigned mul, int shift) {
+  return mul ? (__umulhi(n, mul) >> shift) : n;
+}
+
+// Grid of a batched move: x covers the per (< 2^31) elements of one batch
+// entry, y the entries (the kernels loop over y with stride gridDim.y).
+dim3 move_grid(ll per, int batch) {
+  ll gx = (per + NT - 1) / NT;
+  ll gy = batch < 65535 ? batch : 65535;
+  if (gx < 1) gx = 1;
+  if (gy < 1) gy = 1;
+  while (gx * gy > 1048576 && gy > 1) gy = (gy + 1) / 2;
+  if (gx * gy > 1048576) gx = 1048576 / gy;
+  return dim3((unsigned)gx, (unsigned)gy);
+}
+
 // Leaf z belongs to problem z / lpp, whose base matrix is A0 + problem sA0 and
 // whose k^2 is k2v[problem].
 __global__ void k_leaf_assemble(const double2* A0, ll sA0, const double* q, const double* k2v, int n,
-                                int mi, double2* out, ll nleaf, ll lpp) {
-  const ll per = (ll)n * n;
-  const ll total = per * nleaf;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const ll z = idx / per;
-    const ll pb = z / lpp;
-    const int e = (int)(idx % per);
-    double2 v = A0[pb * sA0 + e];
-    const int r = e % n, c = e / n;
-    if (r == c && r < mi) v.x -= k2v[pb] * q[z * mi + r];
-    out[idx] = v;
+                                unsigned fdm, int fds, int mi, double2* out, int nleaf, int lpp) {
+  const unsigned per = (unsigned)n * (unsigned)n;
+  for (int z = blockIdx.y; z < nleaf; z += gridDim.y) {
+    const int pb = z / lpp;
+    const double2* a = A0 + (ll)pb * sA0;
+    double2* o = out + (ll)z * per;
+    const double* qz = q + (ll)z * mi;
+    const double k2 = k2v[pb];
+    for (unsigned e = blockIdx.x * NT + threadIdx.x; e < per; e += gridDim.x * NT) {
+      double2 v = a[e];
+      const unsigned c = fdiv(e, fdm, fds), r = e - c * (unsigned)n;
+      if (r == c && (int)r < mi) v.x -= k2 * qz[r];
+      o[e] = v;
+    }
   }
 }
 
 template <typename T2, typename T>
-__global__ void k_gather2d(int M, int N, const T2* in, ll ldi, ll si, const int* ridx, const int* cidx,
-                           T2* out, ll ldo, ll so, T sc, int batch) {
-  const ll per = (ll)M * N;
-  const ll total = per * batch;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const ll b = idx / per;
-    const int e = (int)(idx % per);
-    const int i = e % M, j = e / M;
-    const int ri = ridx ? ridx[i] : i;
-    const int cj = cidx ? cidx[j] : j;
-    const T2 v = in[b * si + (ll)ri + (ll)cj * ldi];
-    T2 o;
-    o.x = sc * v.x;
-    o.y = sc * v.y;
-    out[b * so + (ll)i + (ll)j * ldo] = o;
+__global__ void k_gather2d(int M, int N, unsigned fdm, int fds, const T2* in, ll ldi, ll si, const int* ridx,
+                           const int* cidx, T2* out, ll ldo, ll so, T sc, int batch) {
+  const unsigned per = (unsigned)M * (unsigned)N;
+  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
+    const T2* ib = in + (ll)b * si;
+    T2* ob = out + (ll)b * so;
+    for (unsigned e = blockIdx.x * NT + threadIdx.x; e < per; e += gridDim.x * NT) {
+      const unsigned j = fdiv(e, fdm, fds), i = e - j * (unsigned)M;
+      const int ri = ridx ? ridx[i] : (int)i;
+      const int cj = cidx ? cidx[j] : (int)j;
+      const T2 v = ib[(ll)ri + (ll)cj * ldi];
+      T2 o;
+      o.x = sc * v.x;
+      o.y = sc * v.y;
+      ob[(ll)i + (ll)j * ldo] = o;
+    }
   }
 }
 
-__global__ void k_gather_perm(int M, int N, const double2* in, ll ldi, ll si, int idiv, const int* ridx, ll sri,
-                              int rlim, const int* cidx, ll sci, int clim, double2* out, ll ldo, ll so, int batch) {
-  const ll per = (ll)M * N;
-  const ll total = per * batch;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const ll b = idx / per;
-    const int e = (int)(idx % per);
-    const int i = e % M, j = e / M;
-    const int ri = ridx ? ridx[b * sri + i] : i;
-    const int cj = cidx ? cidx[b * sci + j] : j;
-    const bool ok = (unsigned)ri < (unsigned)rlim && (unsigned)cj < (unsigned)clim;
-    out[b * so + (ll)i + (ll)j * ldo] = ok ? in[(b / idiv) * si + (ll)ri + (ll)cj * ldi] : make_double2(0.0, 0.0);
+__global__ void k_gather_perm(int M, int N, unsigned fdm, int fds, const double2* in, ll ldi, ll si, int idiv,
+                              const int* ridx, ll sri, int rlim, const int* cidx, ll sci, int clim, double2* out,
+                              ll ldo, ll so, int batch) {
+  const unsigned per = (unsigned)M * (unsigned)N;
+  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
+    const double2* ib = in + (ll)(b / idiv) * si;
+    const int* rb = ridx ? ridx + (ll)b * sri : nullptr;
+    const int* cb = cidx ? cidx + (ll)b * sci : nullptr;
+    double2* ob = out + (ll)b * so;
+    for (unsigned e = blockIdx.x * NT + threadIdx.x; e < per; e += gridDim.x * NT) {
+      const unsigned j = fdiv(e, fdm, fds), i = e - j * (unsigned)M;
+      const int ri = rb ? rb[i] : (int)i;
+      const int cj = cb ? cb[j] : (int)j;
+      const bool ok = (unsigned)ri < (unsigned)rlim && (unsigned)cj < (unsigned)clim;
+      ob[(ll)i + (ll)j * ldo] = ok ? ib[(ll)ri + (ll)cj * ldi] : make_double2(0.0, 0.0);
+    }
   }
 }
 
 template <typename T2>
-__global__ void k_scatter_rows(int M, int N, const T2* in, ll ldi, ll si, const int* ridx, T2* out, ll ldo,
-                               ll so, int batch) {
-  const ll per = (ll)M * N;
-  const ll total = per * batch;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const ll b = idx / per;
-    const int e = (int)(idx % per);
-    const int i = e % M, j = e / M;
-    out[b * so + (ll)ridx[i] + (ll)j * ldo] = in[b * si + (ll)i + (ll)j * ldi];
+__global__ void k_scatter_rows(int M, int N, unsigned fdm, int fds, const T2* in, ll ldi, ll si, const int* ridx,
+                               T2* out, ll ldo, ll so, int batch) {
+  const unsigned per = (unsigned)M * (unsigned)N;
+  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
+    const T2* ib = in + (ll)b * si;
+    T2* ob = out + (ll)b * so;
+    for (unsigned e = blockIdx.x * NT + threadIdx.x; e < per; e += gridDim.x * NT) {
+      const unsigned j = fdiv(e, fdm, fds), i = e - j * (unsigned)M;
+      ob[(ll)ridx[i] + (ll)j * ldo] = ib[(ll)i + (ll)j * ldi];
+    }
   }
 }
 
-__global__ void k_set2d(int M, int N, double2* out, ll ldo, ll so, double2 diag, double2 off,
-                        int batch) {
-  const ll per = (ll)M * N;
-  const ll total = per * batch;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const ll b = idx / per;
-    const int e = (int)(idx % per);
-    const int i = e % M, j = e / M;
-    out[b * so + (ll)i + (ll)j * ldo] = (i == j) ? diag : off;
+__global__ void k_set2d(int M, int N, unsigned fdm, int fds, double2* out, ll ldo, ll so, double2 diag,
+                        double2 off, int batch) {
+  const unsigned per = (unsigned)M * (unsigned)N;
+  for (int b = blockIdx.y; b < batch; b += gridDim.y) {
+    double2* ob = out + (ll)b * so;
+    for (unsigned e = blockIdx.x * NT + threadIdx.x; e < per; e += gridDim.x * NT) {
+      const unsigned j = fdiv(e, fdm, fds), i = e - j * (unsigned)M;
+      ob[(ll)i + (ll)j * ldo] = (i == j) ? diag : off;
+    }
   }
 }
 
-// Row y of the grid applies move desc[y]; its elements are covered by a
-// grid-stride loop over x.
+// Move desc[blockIdx.y]: z (stride gridDim.z) runs over the batch, x over the
+// elements of one matrix.
 __global__ void k_multi_move(const MoveDesc* desc, int batch) {
   const MoveDesc d = desc[blockIdx.y];
-  const ll per = (ll)d.M * d.N;
-  const ll total = per * batch;
-  for (ll idx = blockIdx.x * (ll)NT + threadIdx.x; idx < total; idx += (ll)gridDim.x * NT) {
-    const ll b = idx / per;
-    const int e = (int)(idx % per);
-    const int i = e % d.M, j = e / d.M;
-    double2 v;
-    if (d.set) {
-      v = (i == j) ? d.diag : d.off;
-    } else {
-      const int ri = d.ridx ? d.ridx[i] : i;
-      const int cj = d.cidx ? d.cidx[j] : j;
-      const double2 x = d.in[b * d.si + (ll)ri + (ll)cj * d.ldi];
-      v = make_double2(d.sc * x.x, d.sc * x.y);
+  const unsigned per = (unsigned)d.M * (unsigned)d.N;
+  if (blockIdx.x * NT >= per) return;
+  for (int b = blockIdx.z; b < batch; b += gridDim.z) {
+    const double2* ib = d.in + (ll)b * d.si;
+    double2* ob = d.out + (ll)b * d.so;
+    for (unsigned e = blockIdx.x * NT + threadIdx.x; e < per; e += gridDim.x * NT) {
+      const unsigned j = fdiv(e, d.fdm, d.fds), i = e - j * (unsigned)d.M;
+      double2 v;
+      if (d.set) {
+        v = (i == j) ? d.diag : d.off;
+      } else {
+        const int ri = d.ridx ? d.ridx[i] : (int)i;
+        const int cj = d.cidx ? d.cidx[j] : (int)j;
+        const double2 x = ib[(ll)ri + (ll)cj * d.ldi];
+        v = make_double2(d.sc * x.x, d.sc * x.y);
+      }
+      ob[(ll)i + (ll)j * d.ldo] = v;
     }
-    d.out[b * d.so + (ll)i + (ll)j * d.ldo] = v;
   }
 }
 
@@ -436,19 +464,43 @@ hipError_t zsub(hipStream_t st, const double2* x, const double2* y, double2* z, 
 
 hipError_t leaf_assemble(hipStream_t st, const double2* A0, ll sA0, const double* q, const double* k2v,
                          int n, int mi, double2* out, ll nleaf, ll lpp) {
+  if (n <= 0 || nleaf <= 0) return hipSuccess;
+  if ((ll)n * n > 0x7fffffffLL || nleaf > 0x7fffffffLL || lpp < 1 || lpp > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_LEAF, 0.0, 16.0 * (double)n * n * nleaf + 8.0 * mi * (double)nleaf);
-  hipLaunchKernelGGL(k_leaf_assemble, dim3(blocks_for((ll)n * n * nleaf)), dim3(NT), 0, st, A0, sA0, q,
-                     k2v, n, mi, out, nleaf, lpp);
+  const FastDiv f = make_fastdiv(n);
+  hipLaunchKernelGGL(k_leaf_assemble, move_grid((ll)n * n, (int)nleaf), dim3(NT), 0, st, A0, sA0, q, k2v, n, f.mul,
+                     f.shift, mi, out, (int)nleaf, (int)lpp);
   return hipGetLastError();
+}
+
+FastDiv make_fastdiv(int d) {
+  if (d <= 1) return FastDiv{0u, 0};
+  const int l = 32 - __builtin_clz((unsigned)(d - 1));  // ceil(log2 d), d >= 2
+  const unsigned long long p = 1ULL << (31 + l);
+  return FastDiv{(unsigned)((p + (unsigned long long)d - 1) / (unsigned long long)d), l - 1};
+}
+
+void multi_move_prepare(MoveDesc* desc, int ndesc) {
+  for (int i = 0; i < ndesc; ++i) {
+    const FastDiv f = make_fastdiv(desc[i].M);
+    desc[i].fdm = f.mul;
+    desc[i].fds = f.shift;
+  }
 }
 
 hipError_t multi_move(hipStream_t st, const MoveDesc* desc, int ndesc, ll max_elems, int batch) {
   if (ndesc <= 0 || max_elems <= 0 || batch <= 0) return hipSuccess;
   if (ndesc > 65535) return hipErrorInvalidValue;
+  const ll per = (max_elems + batch - 1) / batch;  // largest M * N
+  if (per > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_MOVE, 0.0, 0.0);
-  unsigned bx = blocks_for(max_elems);
-  if (bx > 4096) bx = 4096;  // grid-stride beyond: most rows of the grid hold small moves
-  hipLaunchKernelGGL(k_multi_move, dim3(bx, ndesc), dim3(NT), 0, st, desc, batch);
+  // x covers the largest move (blocks beyond a smaller move's elements exit
+  // at once), z the batch (stride loop beyond)
+  ll gx = (per + NT - 1) / NT, gz = batch;
+  if (gx > 4096) gx = 4096;
+  while (gx * ndesc * gz > 1048576 && gz > 1) gz = (gz + 1) / 2;
+  if (gz > 65535) gz = 65535;
+  hipLaunchKernelGGL(k_multi_move, dim3((unsigned)gx, ndesc, (unsigned)gz), dim3(NT), 0, st, desc, batch);
   return hipGetLastError();
 }
 
@@ -456,18 +508,22 @@ hipError_t gather2d(hipStream_t st, int M, int N, const double2* in, ll ldi, ll 
                     const int* ridx, const int* cidx, double2* out, ll ldo, ll so, double sc,
                     int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if ((ll)M * N > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
-  hipLaunchKernelGGL((k_gather2d<double2, double>), dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M,
-                     N, in, ldi, si, ridx, cidx, out, ldo, so, sc, batch);
+  const FastDiv f = make_fastdiv(M);
+  hipLaunchKernelGGL((k_gather2d<double2, double>), move_grid((ll)M * N, batch), dim3(NT), 0, st, M, N, f.mul,
+                     f.shift, in, ldi, si, ridx, cidx, out, ldo, so, sc, batch);
   return hipGetLastError();
 }
 
 hipError_t gather2d(hipStream_t st, int M, int N, const float2* in, ll ldi, ll si, const int* ridx,
                     const int* cidx, float2* out, ll ldo, ll so, float sc, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if ((ll)M * N > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_MOVE, 0.0, 16.0 * (double)M * N * batch);
-  hipLaunchKernelGGL((k_gather2d<float2, float>), dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
-                     in, ldi, si, ridx, cidx, out, ldo, so, sc, batch);
+  const FastDiv f = make_fastdiv(M);
+  hipLaunchKernelGGL((k_gather2d<float2, float>), move_grid((ll)M * N, batch), dim3(NT), 0, st, M, N, f.mul,
+                     f.shift, in, ldi, si, ridx, cidx, out, ldo, so, sc, batch);
   return hipGetLastError();
 }
 
@@ -475,18 +531,21 @@ hipError_t gather_perm(hipStream_t st, int M, int N, const double2* in, ll ldi, 
                        const int* ridx, ll sri, int rlim, const int* cidx, ll sci, int clim, double2* out, ll ldo,
                        ll so, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  if (idiv < 1) return hipErrorInvalidValue;
+  if (idiv < 1 || (ll)M * N > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
-  hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, in, ldi, si, idiv,
-                     ridx, sri, rlim, cidx, sci, clim, out, ldo, so, batch);
+  const FastDiv f = make_fastdiv(M);
+  hipLaunchKernelGGL(k_gather_perm, move_grid((ll)M * N, batch), dim3(NT), 0, st, M, N, f.mul, f.shift, in, ldi,
+                     si, idiv, ridx, sri, rlim, cidx, sci, clim, out, ldo, so, batch);
   return hipGetLastError();
 }
 
 hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi, ll si,
                         const int* ridx, double2* out, ll ldo, ll so, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if ((ll)M * N > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_MOVE, 0.0, 32.0 * (double)M * N * batch);
-  hipLaunchKernelGGL(k_scatter_rows<double2>, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N,
+  const FastDiv f = make_fastdiv(M);
+  hipLaunchKernelGGL(k_scatter_rows<double2>, move_grid((ll)M * N, batch), dim3(NT), 0, st, M, N, f.mul, f.shift,
                      in, ldi, si, ridx, out, ldo, so, batch);
   return hipGetLastError();
 }
@@ -494,9 +553,11 @@ hipError_t scatter_rows(hipStream_t st, int M, int N, const double2* in, ll ldi,
 hipError_t scatter_rows(hipStream_t st, int M, int N, const float2* in, ll ldi, ll si, const int* ridx,
                         float2* out, ll ldo, ll so, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if ((ll)M * N > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_MOVE, 0.0, 16.0 * (double)M * N * batch);
-  hipLaunchKernelGGL(k_scatter_rows<float2>, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, in,
-                     ldi, si, ridx, out, ldo, so, batch);
+  const FastDiv f = make_fastdiv(M);
+  hipLaunchKernelGGL(k_scatter_rows<float2>, move_grid((ll)M * N, batch), dim3(NT), 0, st, M, N, f.mul, f.shift,
+                     in, ldi, si, ridx, out, ldo, so, batch);
   return hipGetLastError();
 }
 
@@ -562,9 +623,11 @@ hipError_t zadd(hipStream_t st, const double2* x, const double2* y, double2* z, 
 hipError_t set2d(hipStream_t st, int M, int N, double2* out, ll ldo, ll so, double2 diag,
                  double2 off, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if ((ll)M * N > 0x7fffffffLL) return hipErrorInvalidValue;
   KernelTimer kt(st, K_MOVE, 0.0, 16.0 * (double)M * N * batch);
-  hipLaunchKernelGGL(k_set2d, dim3(blocks_for((ll)M * N * batch)), dim3(NT), 0, st, M, N, out, ldo,
-                     so, diag, off, batch);
+  const FastDiv f = make_fastdiv(M);
+  hipLaunchKernelGGL(k_set2d, move_grid((ll)M * N, batch), dim3(NT), 0, st, M, N, f.mul, f.shift, out, ldo, so,
+                     diag, off, batch);
   return hipGetLastError();
 }
 

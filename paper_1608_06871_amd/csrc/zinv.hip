@@ -1128,9 +1128,9 @@ hipError_t side_stream(hipStream_t st, hipStream_t* out) {
 // look-ahead's own w x n copies (the side stream still reads those).
 int lookahead_width(const Inv& v) {
   if (!v.nopiv) return BMAX;
-  if (v.IBw && (size_t)WPW * v.n <= t_elems(v.n)) return wide_width(v.n);  // wide panels: one block inverse each
+  if (v.IBw && (size_t)WPW * v.n <= (size_t)v.sT) return wide_width(v.n);  // wide panels: one block inverse each
   for (int w = 4 * BMAX; w > BMAX; w -= BMAX)
-    if ((size_t)w * v.n + t_elems_block(w) <= t_elems(v.n)) return w;
+    if ((size_t)w * v.n + t_elems_block(w) <= (size_t)v.sT) return w;
   return BMAX;
 }
 
@@ -1269,9 +1269,16 @@ bool use_rbt(int n, int batch) {
   return n >= RBT_MIN_N;
 }
 
-size_t std_workspace(int n, int batch, bool wide) {
+// Pivot-row copies per matrix: the recursive blocking's largest w x nd
+// block, and for the butterfly path at least the look-ahead's WPW x n.
+size_t t_elems_for(int n, bool rbt) {
+  const size_t t = t_elems(n), la = (size_t)WPW * n;
+  return rbt && la > t ? la : t;
+}
+
+size_t std_workspace(int n, int batch, bool wide, bool rbt = false) {
   size_t bytes = align256((size_t)batch * n * sizeof(int) * 2);   // sig + pos
-  bytes += align256((size_t)batch * t_elems(n) * sizeof(double2));  // pivot rows T
+  bytes += align256((size_t)batch * t_elems_for(n, rbt) * sizeof(double2));  // pivot rows T
   if (wide) {
     bytes += align256((size_t)batch * BMAX * BMAX * sizeof(double2));  // IB
     bytes += 2 * align256(cand_ints(n, batch) * sizeof(int));          // candidates
@@ -1317,7 +1324,7 @@ size_t zinv_perm_workspace(int n, int batch) { return std_workspace(n, batch, n 
 
 size_t zinv_workspace(int n, int batch) {
   const bool rbt = use_rbt(n, batch);
-  size_t bytes = std_workspace(n, batch, n > NS_MAX_N || rbt);
+  size_t bytes = std_workspace(n, batch, n > NS_MAX_N || rbt, rbt);
   if (rbt) {
     bytes += align256((size_t)batch * n * n * sizeof(double2));            // transformed matrix
     bytes += 3 * align256((size_t)batch * n * NPROBE * sizeof(double2));   // probes X0, Y, X1
@@ -1349,8 +1356,8 @@ hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int ba
   v.pos = v.sig + (size_t)batch * n;
   p += align256((size_t)batch * n * sizeof(int) * 2);
   v.T = (double2*)p;
-  v.sT = (ll)t_elems(n);
-  p += align256((size_t)batch * t_elems(n) * sizeof(double2));
+  v.sT = (ll)t_elems_for(n, nopiv && wide_ws);
+  p += align256((size_t)batch * v.sT * sizeof(double2));
   if (n > NS_MAX_N || nopiv) {
     v.IB = (double2*)p;
     p += align256((size_t)batch * BMAX * BMAX * sizeof(double2));
@@ -1364,10 +1371,10 @@ hipError_t zinv_core(hipStream_t st, int n, double2* work, ll lda, ll sA, int ba
   }
   HPS_HIP_TRY(hipGetLastError());
   // (the look-ahead's pivot-row copies, b x n, fit the T buffer above the
-  // register-panel limit, and below it for the pivot-free wide panels once
-  // WPW x n <= t_elems(n), i.e. from order 320: the order-448
-  // merge matrices take 7 wide panels instead of 14 recursive 32-column ones)
-  const bool la_fits = n > NS_MAX_N || (nopiv && wide_ws && (size_t)WPW * n <= t_elems(n));
+  // register-panel limit, and below it on the butterfly path, whose T holds
+  // WPW x n: the order-448 merge matrices take 7 wide panels instead of 14
+  // recursive 32-column ones)
+  const bool la_fits = n > NS_MAX_N || (nopiv && wide_ws);
   return la_fits && use_lookahead(n, batch) ? lookahead_inverse(v) : process_block(v, 0, n);
 }
 
@@ -1389,7 +1396,7 @@ hipError_t pivoted_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, 
 hipError_t rbt_inverse(hipStream_t st, int n, double2* work, ll lda, ll sA, double2* out, ll ldo, ll sO,
                        int batch, void* ws, int* info) {
   const int m = n / 4;
-  char* p = (char*)ws + std_workspace(n, batch, true);
+  char* p = (char*)ws + std_workspace(n, batch, true, true);
   double2* T = (double2*)p;
   const ll nn = (ll)n * n;
   p += align256((size_t)batch * nn * sizeof(double2));
