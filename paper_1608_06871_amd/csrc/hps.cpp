@@ -184,6 +184,10 @@ struct hps_ctx {
 
   hipEvent_t ev[16] = {};  // start/end pairs: factor, solve, far field, jvp, vjp, and the factor's
                            // leaf stage, merge tree and top system
+  // second stream of the leaf stage and its fork / join events (created on
+  // first use, default priority)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   double t_wave = 0.0;
   bool ev_used[8] = {};
 };
@@ -463,11 +467,25 @@ void set_wavenumber(hps_ctx* c, double k) {
 // All per-level counts below are for the whole batch: the P problems' trees
 // form a forest whose nodes are numbered problem-major, so at every level
 // node i has children 2 i and 2 i + 1 one level down, exactly as in one tree.
+// The leaf stage runs in two parts on two streams, so that one part's panel
+// eliminations (vector ALU, latency-bound) overlap the other's products
+// (matrix cores).  Returns the first leaf of the second part (0: one part):
+// half the problems, or half the leaves of a single problem; small stages
+// stay on one stream.
+int leaf_split(int nl, int lpp, int P) {
+  if (nl < 512) return 0;
+  return P >= 2 ? (P / 2) * lpp : nl / 2;
+}
+
+size_t align_ws(size_t x) { return (x + 255) & ~(size_t)255; }
+
 void plan_factor_buffers(hps_ctx* c) {
   const Geometry& g = c->g;
   const size_t P = c->P;
   const size_t nl = (size_t)g.nleaf * P, ne = g.ne, mi = g.mi, nb = c->nb;
   size_t zws = zinv_workspace((int)mi, (int)nl);
+  const int h = leaf_split((int)nl, g.nleaf, (int)P);
+  if (h > 0) zws = std::max(zws, align_ws(zinv_workspace((int)mi, h)) + zinv_workspace((int)mi, (int)nl - h));
   size_t rmax = nl * ne * ne, blk = 0, w = 0, q = 0, v = 0;
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
@@ -632,19 +650,44 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   const ll smm = (ll)mi * mi;
   CK(leaf_assemble(st, S0, nn, q, k2v, mi, mi, c->sA.z(), nl, lpp));
   double2* Si = c->sInv.z();
-  CK(zinv(st, mi, c->sA.z(), mi, smm, Si, mi, smm, nl, c->sZws.p, c->sInfo.i()));
-  // Y = -S^-1 P1
-  CK(zgemm_div(st, OP_N, OP_N, mi, ne, mi, MONE, Si, mi, smm, 1, P1, mi, nn, lpp, ZERO, c->dY.z(), mi,
-               (ll)mi * ne, nl));
-  // R = R0 + V Y
   double2* Rc = c->sR0.z();
-  CK(gather_perm(st, ne, ne, R0, ne, nn, lpp, nullptr, 0, ne, nullptr, 0, ne, Rc, ne, (ll)ne * ne, nl));
-  CK(zgemm_div(st, OP_N, OP_N, ne, ne, mi, ONE, V, ne, nn, lpp, c->dY.z(), mi, (ll)mi * ne, 1, ONE, Rc, ne,
-               (ll)ne * ne, nl));
-  // H = V S^-1
-  if (c->o.keep_derivs)
-    CK(zgemm_div(st, OP_N, OP_N, ne, mi, mi, ONE, V, ne, nn, lpp, Si, mi, smm, 1, ZERO, c->dH.z(), ne,
-                 (ll)ne * mi, nl));
+  // leaves [z0, z1) on stream s with inverse workspace ws; the per-problem
+  // operands are those of problem z0 / lpp, indexed by leaf / lpp when the
+  // part starts a problem, else shared by the whole part (one problem)
+  auto leaf_part = [&](hipStream_t s, int z0, int z1, void* ws) {
+    const int b = z1 - z0;
+    const ll pz = (ll)(z0 / lpp) * nn;
+    const int dv = (z0 % lpp == 0) ? lpp : b;
+    double2* Sz = Si + (ll)z0 * smm;
+    double2* Yz = c->dY.z() + (ll)z0 * mi * ne;
+    double2* Rz = Rc + (ll)z0 * ne * ne;
+    CK(zinv(s, mi, c->sA.z() + (ll)z0 * smm, mi, smm, Sz, mi, smm, b, ws, c->sInfo.i() + z0));
+    // Y = -S^-1 P1
+    CK(zgemm_div(s, OP_N, OP_N, mi, ne, mi, MONE, Sz, mi, smm, 1, P1 + pz, mi, nn, dv, ZERO, Yz, mi, (ll)mi * ne,
+                 b));
+    // R = R0 + V Y
+    CK(gather_perm(s, ne, ne, R0 + pz, ne, nn, dv, nullptr, 0, ne, nullptr, 0, ne, Rz, ne, (ll)ne * ne, b));
+    CK(zgemm_div(s, OP_N, OP_N, ne, ne, mi, ONE, V + pz, ne, nn, dv, Yz, mi, (ll)mi * ne, 1, ONE, Rz, ne,
+                 (ll)ne * ne, b));
+    // H = V S^-1
+    if (c->o.keep_derivs)
+      CK(zgemm_div(s, OP_N, OP_N, ne, mi, mi, ONE, V + pz, ne, nn, dv, Sz, mi, smm, 1, ZERO,
+                   c->dH.z() + (ll)z0 * ne * mi, ne, (ll)ne * mi, b));
+  };
+  const int h = leaf_split(nl, lpp, P);
+  if (h > 0) {
+    if (!c->side) CK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    if (!c->fork) CK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    if (!c->join) CK(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+    CK(hipEventRecord(c->fork, st));
+    CK(hipStreamWaitEvent(c->side, c->fork, 0));
+    leaf_part(st, 0, h, c->sZws.p);
+    leaf_part(c->side, h, nl, (char*)c->sZws.p + align_ws(zinv_workspace(mi, h)));
+    CK(hipEventRecord(c->join, c->side));
+    CK(hipStreamWaitEvent(st, c->join, 0));
+  } else {
+    leaf_part(st, 0, nl, c->sZws.p);
+  }
   if (c->mixed) CK(hipMemcpyAsync(c->dRleaf.p, Rc, zb((size_t)nl * ne * ne), hipMemcpyDeviceToDevice, st));
   mark(c, 5, 1);
 
@@ -1516,6 +1559,12 @@ void hps_destroy(hps_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->st);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  if (c->join) (void)hipEventDestroy(c->join);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
