@@ -155,6 +155,10 @@ struct hps_ctx {
   DBuf dRrootH, dZinvH;
   std::vector<DBuf> dD, dU;
   DBuf sA, sInv, sZws, sR0, sR1, sBlk, sW, sWinv, sQ, sVin, sV, sTmp, sInfo, sRbt;
+  // second set of the merge scratch that a level's operator products for the
+  // sweeps (V, U) read on the second stream while the next level runs (odd
+  // levels; allocated when those products are formed)
+  DBuf sBlk2, sWinv2, sVin2, sTmp2;
   // per merge level, the block moves that depend only on the children's maps
   // (one launch per level; built and uploaded once per factorisation)
   std::vector<MoveDesc> hMoves;
@@ -188,6 +192,7 @@ struct hps_ctx {
   // first use, default priority)
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t lev_ready = nullptr, lev_done[2] = {};  // merge levels: main -> second stream, and back
   double t_wave = 0.0;
   bool ev_used[8] = {};
 };
@@ -504,6 +509,13 @@ void plan_factor_buffers(hps_ctx* c) {
   c->sR0.ensure(zb(rmax));
   c->sR1.ensure(zb(rmax));
   c->sBlk.ensure(zb(blk));
+  const bool derivs = c->o.keep_derivs || c->mixed;
+  if (derivs) {
+    c->sBlk2.ensure(zb(blk));
+    c->sWinv2.ensure(zb(w));
+    c->sVin2.ensure(zb(v));
+    c->sTmp2.ensure(zb(v));
+  }
   c->sW.ensure(zb(w));
   c->sWinv.ensure(zb(w));
   c->sQ.ensure(zb(q));
@@ -551,6 +563,26 @@ void plan_factor_buffers(hps_ctx* c) {
 // zero blocks, and V's and Tm's fixed parts), as one list per level, uploaded
 // to the device.  The moves of a level write disjoint elements; they run at
 // the start of the level, before the products that read or complete them.
+// Scratch set of merge level l: with sweep operators, odd levels take the
+// second set, so that a level's V and U products (second stream) read their
+// blocks while the next level fills the other set.
+struct MergeScratch {
+  double2 *blk, *winv, *vin, *tmp;
+};
+MergeScratch merge_scratch(hps_ctx* c, int l) {
+  if ((c->o.keep_derivs || c->mixed) && (l & 1))
+    return MergeScratch{c->sBlk2.z(), c->sWinv2.z(), c->sVin2.z(), c->sTmp2.z()};
+  return MergeScratch{c->sBlk.z(), c->sWinv.z(), c->sVin.z(), c->sTmp.z()};
+}
+
+// The context's second stream and its events (default priority; created on
+// first use).
+void ensure_side(hps_ctx* c) {
+  if (!c->side) CK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&c->fork, &c->join, &c->lev_ready, &c->lev_done[0], &c->lev_done[1]})
+    if (!*e) CK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+}
+
 void build_merge_moves(hps_ctx* c) {
   const Geometry& g = c->g;
   const int P = c->P;
@@ -573,7 +605,8 @@ void build_merge_moves(hps_ctx* c) {
     const double2* Rb = Rc + (ll)nc * nc;
     double2* Rn = (Rc == c->sR0.z()) ? c->sR1.z() : c->sR0.z();
     const ll ms = (ll)m * s, ss = (ll)s * s, sp = (ll)np * np, sd = 4 * ms, sq = 2 * ms, sv = 2 * ss;
-    double2* A13 = c->sBlk.z();
+    const MergeScratch scr = merge_scratch(c, l);
+    double2* A13 = scr.blk;
     double2* A31 = A13 + (ll)cnt * ms;
     double2* A33 = A31 + (ll)cnt * ms;
     double2* B23 = A33 + (ll)cnt * ss;
@@ -600,9 +633,9 @@ void build_merge_moves(hps_ctx* c) {
     fill(m, m, Rn + (ll)m * np, np, sp, zero, zero);
     fill(m, m, Rn + m, np, sp, zero, zero);
     if (derivs) {
-      gather(s, s, Rb, i3b, i3b, c->sVin.z(), s, sv, 1.0);                     // V_in = [B33, -I]
-      fill(s, s, c->sVin.z() + ss, s, sv, mone, zero);
-      fill(s, 2 * s, c->sTmp.z(), s, sv, one, zero);                           // Tm = [I, 0] (+ A33 V)
+      gather(s, s, Rb, i3b, i3b, scr.vin, s, sv, 1.0);                         // V_in = [B33, -I]
+      fill(s, s, scr.vin + ss, s, sv, mone, zero);
+      fill(s, 2 * s, scr.tmp, s, sv, one, zero);                               // Tm = [I, 0] (+ A33 V)
     }
     Rc = Rn;
   }
@@ -635,6 +668,11 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   // info[0 .. ninfo): zero pivots per matrix; info[ninfo]: non-finite flags
   // (1: the contrast, 2: the top inverse)
   int* nonfinite = c->sInfo.i() + ninfo;
+  // work left on the second stream by an interrupted pass ends before this one
+  if (c->side) {
+    CK(hipEventRecord(c->join, c->side));
+    CK(hipStreamWaitEvent(st, c->join, 0));
+  }
   CK(hipMemsetAsync(c->sInfo.p, 0, sizeof(int) * (ninfo + 1), st));
   CK(hipMemsetAsync(c->sRbt.p, 0, 16, st));
   CK(flag_nonfinite(st, q, (ll)P * g.nleaf * mi, 1, nonfinite));
@@ -676,9 +714,7 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   };
   const int h = leaf_split(nl, lpp, P);
   if (h > 0) {
-    if (!c->side) CK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    if (!c->fork) CK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
-    if (!c->join) CK(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+    ensure_side(c);
     CK(hipEventRecord(c->fork, st));
     CK(hipStreamWaitEvent(c->side, c->fork, 0));
     leaf_part(st, 0, h, c->sZws.p);
@@ -694,11 +730,14 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   // merge tree
   mark(c, 6, 0);
   profile_set_phase(PH_MERGE);
+  const bool derivs = c->o.keep_derivs || c->mixed;
+  if (derivs && g.nlev > 0) ensure_side(c);
   build_merge_moves(c);
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
     const int cnt = L.count * P, m = L.m, s = L.s, np = L.np;
-    double2* A13 = c->sBlk.z();
+    const MergeScratch scr = merge_scratch(c, l);
+    double2* A13 = scr.blk;
     double2* A31 = A13 + (ll)cnt * m * s;
     double2* A33 = A31 + (ll)cnt * s * m;
     double2* B23 = A33 + (ll)cnt * s * s;
@@ -707,6 +746,9 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
     // the child blocks, the identity of W, the -B32 and -A31 parts of Q and D,
     // the parent map's diagonal blocks and zero blocks (and V's and Tm's fixed
     // parts): one launch of independent moves
+    // this level's scratch set was last read by level l - 2's products on
+    // the second stream
+    if (derivs && l >= 3) CK(hipStreamWaitEvent(st, c->lev_done[l & 1], 0));
     {
       const int o0 = c->moveOff[l], o1 = c->moveOff[l + 1];
       ll mx = 0;
@@ -716,7 +758,7 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
     }
     // W = I - B33 A33, inverted
     double2* W = c->sW.z();
-    double2* Wi = c->sWinv.z();
+    double2* Wi = scr.winv;
     CK(zgemm(st, OP_N, OP_N, s, s, s, MONE, B33, s, ss, A33, s, ss, ONE, W, s, ss, cnt));
     CK(zinv(st, s, W, s, ss, Wi, s, ss, cnt, c->sZws.p, c->sInfo.i()));
     // Q = [B33 A31, -B32]
@@ -735,27 +777,33 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
     CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, A13, m, ms, D, 2 * s, sd, ONE, Rn, np, sp, cnt));
     CK(zgemm(st, OP_N, OP_N, m, 2 * m, s, ONE, B23, m, ms, D + s, 2 * s, sd, ONE, Rn + m, np, sp,
              cnt));
-    if (c->o.keep_derivs || c->mixed) {
-      double2* Vin = c->sVin.z();
+    // the sweeps' operators V and U (and the complex64 copies) need nothing
+    // of the next level: they run on the second stream meanwhile
+    if (derivs) {
+      CK(hipEventRecord(c->lev_ready, st));
+      CK(hipStreamWaitEvent(c->side, c->lev_ready, 0));
+      hipStream_t xs = c->side;
+      double2* Vin = scr.vin;
       double2* V = c->sV.z();
-      double2* Tm = c->sTmp.z();
+      double2* Tm = scr.tmp;
       const ll sv = 2 * ss;
-      CK(zgemm(st, OP_N, OP_N, s, 2 * s, s, ONE, Wi, s, ss, Vin, s, sv, ZERO, V, s, sv, cnt));
+      CK(zgemm(xs, OP_N, OP_N, s, 2 * s, s, ONE, Wi, s, ss, Vin, s, sv, ZERO, V, s, sv, cnt));
       double2* U = c->dU[l].z();
-      CK(zgemm(st, OP_N, OP_N, m, 2 * s, s, ONE, A13, m, ms, V, s, sv, ZERO, U, 2 * m, sd, cnt));
-      CK(zgemm(st, OP_N, OP_N, s, 2 * s, s, ONE, A33, s, ss, V, s, sv, ONE, Tm, s, sv, cnt));
-      CK(zgemm(st, OP_N, OP_N, m, 2 * s, s, MONE, B23, m, ms, Tm, s, sv, ZERO, U + m, 2 * m, sd,
+      CK(zgemm(xs, OP_N, OP_N, m, 2 * s, s, ONE, A13, m, ms, V, s, sv, ZERO, U, 2 * m, sd, cnt));
+      CK(zgemm(xs, OP_N, OP_N, s, 2 * s, s, ONE, A33, s, ss, V, s, sv, ONE, Tm, s, sv, cnt));
+      CK(zgemm(xs, OP_N, OP_N, m, 2 * s, s, MONE, B23, m, ms, Tm, s, sv, ZERO, U + m, 2 * m, sd,
                cnt));
       if (c->mixed) {
         // E = [V; -Tm]: shared-edge sources h3 to f3 (the down-sweep's h term)
         double2* E = c->sE.z();
         const ll se = 4 * ss;
-        CK(gather2d(st, s, 2 * s, V, s, sv, nullptr, nullptr, E, 2 * s, se, 1.0, cnt));
-        CK(gather2d(st, s, 2 * s, Tm, s, sv, nullptr, nullptr, E + s, 2 * s, se, -1.0, cnt));
-        CK(to_f32(st, E, (ll)cnt * se, (float2*)c->dE32[l].p));
-        CK(to_f32(st, D, (ll)cnt * sd, (float2*)c->dD32[l].p));
-        CK(to_f32(st, U, (ll)cnt * sd, (float2*)c->dU32[l].p));
+        CK(gather2d(xs, s, 2 * s, V, s, sv, nullptr, nullptr, E, 2 * s, se, 1.0, cnt));
+        CK(gather2d(xs, s, 2 * s, Tm, s, sv, nullptr, nullptr, E + s, 2 * s, se, -1.0, cnt));
+        CK(to_f32(xs, E, (ll)cnt * se, (float2*)c->dE32[l].p));
+        CK(to_f32(xs, D, (ll)cnt * sd, (float2*)c->dD32[l].p));
+        CK(to_f32(xs, U, (ll)cnt * sd, (float2*)c->dU32[l].p));
       }
+      CK(hipEventRecord(c->lev_done[l & 1], xs));
     }
     Rc = Rn;
   }
@@ -774,6 +822,8 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
     CK(conj_transpose(st, nb, c->dZinv.z(), nb, sbb, c->dZinvH.z(), nb, sbb, P));
   }
   CK(flag_nonfinite(st, (const double*)c->dZinv.p, 2 * (ll)P * sbb, 2, nonfinite));
+  // the last merge levels' sweep operators (second stream) overlap the top
+  if (derivs && g.nlev > 0) CK(hipStreamWaitEvent(st, c->lev_done[g.nlev & 1], 0));
   mark(c, 7, 1);
   mark(c, 0, 1);
   profile_set_phase(PH_OTHER);
@@ -1437,6 +1487,7 @@ int64_t device_bytes(const hps_ctx* c) {
   const DBuf* bufs[] = {&c->dLeaf, &c->dBop, &c->dC1, &c->dbnode, &c->dPk, &c->dY, &c->dH,
                         &c->dRroot, &c->dZinv, &c->dRrootH, &c->dZinvH, &c->sA, &c->sInv, &c->sZws, &c->sR0, &c->sR1,
                         &c->sBlk, &c->sW, &c->sWinv, &c->sQ, &c->sVin, &c->sV, &c->sTmp, &c->sInfo,
+                        &c->sBlk2, &c->sWinv2, &c->sVin2, &c->sTmp2,
                         &c->d_dirs, &c->dG, &c->dRhs, &c->dF0, &c->dF1, &c->dF3, &c->du0, &c->dST,
                         &c->dg, &c->dPhi, &c->sB, &c->sST2, &c->dSx, &c->dSy,
                         &c->dNodeGrid, &c->sS1, &c->sS2, &c->sS3, &c->sGn, &c->sGnZ};
@@ -1565,6 +1616,9 @@ void hps_destroy(hps_ctx* c) {
   }
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->join) (void)hipEventDestroy(c->join);
+  if (c->lev_ready) (void)hipEventDestroy(c->lev_ready);
+  for (auto& e : c->lev_done)
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
