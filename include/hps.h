@@ -119,13 +119,18 @@ typedef struct hps_opts {
                             redoes its sweep in complex128 (exact FP64 result, refine_fallback = 1
                             in hps_stats) instead of returning HPS_ENOCONV */
   int exterior;          /* hps_exterior */
+  int streams;           /* streams of hps_factor: 2 (default) runs half the leaf stage, and each
+                            merge level's operators for the sweeps (V, U) while the next level
+                            proceeds, on a second stream the context owns (forked from and joined
+                            to `stream` with events inside the call); 1 keeps all work on `stream`
+                            (for callers that already run several contexts concurrently) */
 } hps_opts;
 
 typedef struct hps_ctx hps_ctx;
 
 /* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
  * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1,
- * max_refine = 8, fallback_fp64 = 1, refine_tol = 1e-10, HPS_EXT_GREEN (the far-field error follows the interface
+ * max_refine = 8, fallback_fp64 = 1, refine_tol = 1e-10, HPS_EXT_GREEN, streams = 2 (the far-field error follows the interface
  * residual closely, so 1e-10 leaves two orders of margin under a 1e-8 far-field
  * target; one correction reaches it at k = 80). */
 void hps_default_opts(hps_opts* o);

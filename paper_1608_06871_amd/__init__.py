@@ -33,7 +33,8 @@ class Opts(ctypes.Structure):
                 ("eta_scale", ctypes.c_double), ("keep_derivs", ctypes.c_int),
                 ("precision", ctypes.c_int), ("host_threads", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("nprob", ctypes.c_int), ("max_refine", ctypes.c_int),
-                ("refine_tol", ctypes.c_double), ("fallback_fp64", ctypes.c_int), ("exterior", ctypes.c_int)]
+                ("refine_tol", ctypes.c_double), ("fallback_fp64", ctypes.c_int), ("exterior", ctypes.c_int),
+                ("streams", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -132,11 +133,13 @@ class Solver:
     """One HPS context: geometry fixed at construction; factor/solve/... as in
     the C ABI (include/hps.h).  With nprob > 1 the context holds a batch of
     independent problems on the same grid: per-problem arrays get a leading
-    problem axis (q [nprob, npde], far field [nprob, ndir, ntheta], ...)."""
+    problem axis (q [nprob, npde], far field [nprob, ndir, ntheta], ...).
+    streams: 2 lets hps_factor overlap work on a second stream of the
+    context, 1 keeps everything on `stream` (hps_opts.streams)."""
 
     def __init__(self, nleaf=4, p=16, box=(-1.0, 1.0, -1.0, 1.0), eta_scale=1.0,
                  keep_derivs=True, host_threads=0, stream=None, nprob=1, precision="fp64",
-                 max_refine=None, refine_tol=None, fallback_fp64=None, exterior="green"):
+                 max_refine=None, refine_tol=None, fallback_fp64=None, exterior="green", streams=2):
         torch = _torch()
         L = lib()
         o = Opts()
@@ -160,6 +163,7 @@ class Solver:
             raise ValueError(f"exterior must be one of {sorted(EXTERIORS)}")
         o.exterior = EXTERIORS[exterior]
         self.exterior = exterior
+        o.streams = int(streams)
         self.precision = precision
         self.max_refine, self.refine_tol = o.max_refine, o.refine_tol
         if stream is None:

@@ -489,7 +489,7 @@ void plan_factor_buffers(hps_ctx* c) {
   const size_t P = c->P;
   const size_t nl = (size_t)g.nleaf * P, ne = g.ne, mi = g.mi, nb = c->nb;
   size_t zws = zinv_workspace((int)mi, (int)nl);
-  const int h = leaf_split((int)nl, g.nleaf, (int)P);
+  const int h = c->o.streams > 1 ? leaf_split((int)nl, g.nleaf, (int)P) : 0;
   if (h > 0) zws = std::max(zws, align_ws(zinv_workspace((int)mi, h)) + zinv_workspace((int)mi, (int)nl - h));
   size_t rmax = nl * ne * ne, blk = 0, w = 0, q = 0, v = 0;
   for (int l = 1; l <= g.nlev; ++l) {
@@ -509,8 +509,7 @@ void plan_factor_buffers(hps_ctx* c) {
   c->sR0.ensure(zb(rmax));
   c->sR1.ensure(zb(rmax));
   c->sBlk.ensure(zb(blk));
-  const bool derivs = c->o.keep_derivs || c->mixed;
-  if (derivs) {
+  if ((c->o.keep_derivs || c->mixed) && c->o.streams > 1) {
     c->sBlk2.ensure(zb(blk));
     c->sWinv2.ensure(zb(w));
     c->sVin2.ensure(zb(v));
@@ -570,7 +569,7 @@ struct MergeScratch {
   double2 *blk, *winv, *vin, *tmp;
 };
 MergeScratch merge_scratch(hps_ctx* c, int l) {
-  if ((c->o.keep_derivs || c->mixed) && (l & 1))
+  if ((c->o.keep_derivs || c->mixed) && c->o.streams > 1 && (l & 1))
     return MergeScratch{c->sBlk2.z(), c->sWinv2.z(), c->sVin2.z(), c->sTmp2.z()};
   return MergeScratch{c->sBlk.z(), c->sWinv.z(), c->sVin.z(), c->sTmp.z()};
 }
@@ -712,7 +711,7 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
       CK(zgemm_div(s, OP_N, OP_N, ne, mi, mi, ONE, V + pz, ne, nn, dv, Sz, mi, smm, 1, ZERO,
                    c->dH.z() + (ll)z0 * ne * mi, ne, (ll)ne * mi, b));
   };
-  const int h = leaf_split(nl, lpp, P);
+  const int h = c->o.streams > 1 ? leaf_split(nl, lpp, P) : 0;
   if (h > 0) {
     ensure_side(c);
     CK(hipEventRecord(c->fork, st));
@@ -731,7 +730,8 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   mark(c, 6, 0);
   profile_set_phase(PH_MERGE);
   const bool derivs = c->o.keep_derivs || c->mixed;
-  if (derivs && g.nlev > 0) ensure_side(c);
+  const bool overlap = derivs && c->o.streams > 1;  // V, U products on the second stream
+  if (overlap && g.nlev > 0) ensure_side(c);
   build_merge_moves(c);
   for (int l = 1; l <= g.nlev; ++l) {
     const LevelPattern& L = g.lev[l];
@@ -748,7 +748,7 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
     // parts): one launch of independent moves
     // this level's scratch set was last read by level l - 2's products on
     // the second stream
-    if (derivs && l >= 3) CK(hipStreamWaitEvent(st, c->lev_done[l & 1], 0));
+    if (overlap && l >= 3) CK(hipStreamWaitEvent(st, c->lev_done[l & 1], 0));
     {
       const int o0 = c->moveOff[l], o1 = c->moveOff[l + 1];
       ll mx = 0;
@@ -780,9 +780,12 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
     // the sweeps' operators V and U (and the complex64 copies) need nothing
     // of the next level: they run on the second stream meanwhile
     if (derivs) {
-      CK(hipEventRecord(c->lev_ready, st));
-      CK(hipStreamWaitEvent(c->side, c->lev_ready, 0));
-      hipStream_t xs = c->side;
+      hipStream_t xs = st;
+      if (overlap) {
+        CK(hipEventRecord(c->lev_ready, st));
+        CK(hipStreamWaitEvent(c->side, c->lev_ready, 0));
+        xs = c->side;
+      }
       double2* Vin = scr.vin;
       double2* V = c->sV.z();
       double2* Tm = scr.tmp;
@@ -803,7 +806,7 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
         CK(to_f32(xs, D, (ll)cnt * sd, (float2*)c->dD32[l].p));
         CK(to_f32(xs, U, (ll)cnt * sd, (float2*)c->dU32[l].p));
       }
-      CK(hipEventRecord(c->lev_done[l & 1], xs));
+      if (overlap) CK(hipEventRecord(c->lev_done[l & 1], xs));
     }
     Rc = Rn;
   }
@@ -823,7 +826,7 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
   }
   CK(flag_nonfinite(st, (const double*)c->dZinv.p, 2 * (ll)P * sbb, 2, nonfinite));
   // the last merge levels' sweep operators (second stream) overlap the top
-  if (derivs && g.nlev > 0) CK(hipStreamWaitEvent(st, c->lev_done[g.nlev & 1], 0));
+  if (overlap && g.nlev > 0) CK(hipStreamWaitEvent(st, c->lev_done[g.nlev & 1], 0));
   mark(c, 7, 1);
   mark(c, 0, 1);
   profile_set_phase(PH_OTHER);
@@ -1526,6 +1529,7 @@ void hps_default_opts(hps_opts* o) {
   o->refine_tol = 1e-10;
   o->fallback_fp64 = 1;
   o->exterior = HPS_EXT_GREEN;
+  o->streams = 2;
 }
 
 hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
@@ -1538,6 +1542,7 @@ hps_status hps_create(const hps_opts* opts, hps_ctx** out) {
   if (o.p < 4 || o.p > 20) return HPS_EINVAL;
   if (o.precision != HPS_FP64 && o.precision != HPS_MIXED) return HPS_EINVAL;
   if (o.exterior != HPS_EXT_GREEN && o.exterior != HPS_EXT_BURTON_MILLER) return HPS_EINVAL;
+  if (o.streams != 1 && o.streams != 2) return HPS_EINVAL;
   if (o.nprob < 1 || o.nprob > 4096) return HPS_EINVAL;
   if (o.precision == HPS_MIXED && (o.max_refine < 0 || o.max_refine > 100 || !(o.refine_tol > 0.0)))
     return HPS_EINVAL;

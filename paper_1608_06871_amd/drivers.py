@@ -282,10 +282,13 @@ class BatchForward:
     (padded columns are computed and dropped).  Groups run concurrently, each
     on its own stream and host thread (the library releases the interpreter
     lock during its calls), so the launches of small groups overlap the work
-    of large ones.  Contexts and streams are kept between calls."""
+    of large ones.  Contexts and streams are kept between calls.  streams:
+    the contexts' own stream count (hps_opts.streams); by default 1 when the
+    groups run concurrently (they already overlap), else 2."""
 
-    def __init__(self, p=16, keep_derivs=False, m_split=64, concurrent=True, precision="fp64"):
+    def __init__(self, p=16, keep_derivs=False, m_split=64, concurrent=True, precision="fp64", streams=None):
         self.p = p
+        self.streams = streams if streams is not None else (1 if concurrent else 2)
         self.keep_derivs = keep_derivs
         self.precision = precision
         self.m_split = m_split  # problems with more directions than this batch separately
@@ -298,7 +301,7 @@ class BatchForward:
         if key not in self._ctx:
             stream = torch.cuda.Stream() if self.concurrent else None
             self._ctx[key] = Solver(nleaf=L, p=self.p, nprob=nprob, keep_derivs=self.keep_derivs, stream=stream,
-                                    precision=self.precision)
+                                    precision=self.precision, streams=self.streams)
         return self._ctx[key]
 
     def groups(self, problems):

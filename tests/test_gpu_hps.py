@@ -256,3 +256,33 @@ def test_deferred_butterfly_check_redoes_factorisation_pivoted():
         hps.zinv_pivoting(-1, 1e-10)
     ok = run()
     assert _rel(ok[0].numpy(), ref[0].numpy()) <= 1e-9
+
+
+@pytest.mark.parametrize("case", ["L32", "mixed_L32", "batch_L16"])
+def test_second_stream_gives_identical_results(case):
+    """hps_opts.streams = 2 (half the leaf stage and the merge levels' V, U
+    products on the context's second stream) runs the same kernels on the
+    same operands as streams = 1: far field, total field, jvp and vjp agree
+    bit for bit (32 x 32 leaves: the leaf stage splits within the problem;
+    a 2-problem batch on 16 x 16 leaves: at the problem boundary)."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    L = 16 if case == "batch_L16" else 32
+    nprob = 2 if case == "batch_L16" else 1
+    prec = "mixed" if case.startswith("mixed") else "fp64"
+    k, M, P = 40.0, 8, 16
+    print(f"streams 1 vs 2: {case}", flush=True)
+    out = {}
+    for ns in (1, 2):
+        s = hps.Solver(nleaf=L, p=16, nprob=nprob, precision=prec, streams=ns)
+        xy = s.node_coords()
+        qs = [synth.parity_inputs(xy, M, P, seed=11 + b) for b in range(nprob)]
+        q = torch.from_numpy(np.stack([x["q"] for x in qs]) if nprob > 1 else qs[0]["q"]).cuda()
+        r = torch.from_numpy(np.stack([x["r"] for x in qs]) if nprob > 1 else qs[0]["r"]).cuda()
+        dq = torch.from_numpy(np.stack([x["dq"] for x in qs]) if nprob > 1 else qs[0]["dq"]).cuda()
+        s.factor(q, [k + 3.0 * b for b in range(nprob)] if nprob > 1 else k)
+        s.solve(synth.equispaced_angles(M))
+        ff = s.far_field(synth.equispaced_angles(P), 2.0).cpu()
+        out[ns] = (ff, s.total_field().cpu(), s.jvp(dq).cpu(), s.vjp(r).cpu())
+    for a, b in zip(out[1], out[2]):
+        assert torch.equal(a, b)

@@ -53,7 +53,10 @@ def test_default_opts_and_invalid_create_on_cpu():
     assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
     bad.x1, bad.exterior = 1.0, 2  # no such exterior relation
     assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
-    assert o.exterior == 0
+    for n in (0, 3):  # one or two streams only
+        bad.exterior, bad.streams = 0, n
+        assert L.hps_create(ctypes.byref(bad), ctypes.byref(h)) == hps.HPS_EINVAL
+    assert o.exterior == 0 and o.streams == 2
 
 
 def test_status_codes_match_the_header():
