@@ -651,6 +651,25 @@ def main():
                         "launches": kd["launches"], "avg_launch_ms": per_launch_ms,
                         "bytes_per_launch": kd["bytes"] / kd["launches"]}
         log("kernel classes: " + ", ".join(f"{n} {v['total_ms']:.1f} ms/{v['launches']}" for n, v in kernels.items()))
+        # the same step with the factorisation on one stream: the dominant
+        # class's launches then never share the chip with the other stream's
+        # (one untimed step first: the full leaf batch is a new GEMM shape)
+        s.set_streams(1)
+        step()
+        torch.cuda.synchronize()
+        hps.profile_start()
+        t1 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t1
+        k1 = hps.profile_stop()[dom]
+        s.set_streams(2)
+        a1 = (k1["flops"] if roofline["bound"] == "mfma" else k1["bytes"]) / (k1["total_ms"] * 1e-3)
+        a1 = a1 / 1e12 if roofline["bound"] == "mfma" else a1 / 1e9
+        roofline["one_stream"] = {"achieved": a1, "frac": a1 / roofline["peak"], "launches": k1["launches"],
+                                  "avg_launch_ms": k1["total_ms"] / k1["launches"],
+                                  "profiled_step_ms": t1 * 1e3}
+        log(f"one-stream step: {t1 * 1e3:.1f} ms, {dom} {a1:.1f} {roofline['unit']}")
         med_now = {ph: float(np.median(v)) for ph, v in phases.items()}
         stage = phase_report(kernels, {f"t_{ph}_ms": v for ph, v in med_now.items()}, L, M)
         log("stages: " + ", ".join(f"{ph} {v['wall_ms']:.1f} ms {v['tflops']:.1f} TF" for ph, v in stage.items()))

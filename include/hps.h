@@ -171,6 +171,11 @@ hps_status hps_set_wavenumber(hps_ctx* ctx, double k);
  * (problems whose wavenumber is unchanged keep their operators). */
 hps_status hps_set_wavenumbers(hps_ctx* ctx, const double* k_host);
 
+/* Sets hps_opts.streams (1 or 2, else HPS_EINVAL) for the next hps_factor
+ * calls of this context: a scheduling choice only, the results are the same
+ * bit for bit. */
+hps_status hps_set_streams(hps_ctx* ctx, int streams);
+
 /* Factorises the discrete interior + exterior problem for the real contrast
  * q_nodes (device, npde doubles, PDE-node order) at wavenumber k > 0: leaf
  * impedance maps, the merge tree, and the inverse of the top (boundary)

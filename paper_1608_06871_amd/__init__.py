@@ -64,6 +64,7 @@ SIGNATURES = [
     ("hps_node_coords", _I, [_P, _P]),
     ("hps_set_wavenumber", _I, [_P, _D]),
     ("hps_set_wavenumbers", _I, [_P, _P]),
+    ("hps_set_streams", _I, [_P, _I]),
     ("hps_factor", _I, [_P, _P, _D]),
     ("hps_factor_batch", _I, [_P, _P, _P]),
     ("hps_solve", _I, [_P, _I, _P]),
@@ -207,6 +208,10 @@ class Solver:
         """k: one wavenumber for every problem, or one per problem."""
         kv = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.float64), (self.nprob,)))
         self._check(lib().hps_set_wavenumbers(self._h, kv.ctypes.data_as(ctypes.c_void_p)), "set_wavenumber")
+
+    def set_streams(self, streams):
+        """hps_set_streams: 1 or 2 streams for the next factorisations."""
+        self._check(lib().hps_set_streams(self._h, int(streams)), "set_streams")
 
     def factor(self, q, k):
         """q: [npde] (or [nprob, npde]) float64 GPU tensor; k: scalar or one per problem."""

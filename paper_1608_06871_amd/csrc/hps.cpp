@@ -1646,6 +1646,12 @@ hps_status hps_set_wavenumber(hps_ctx* c, double k) {
   return guard(c, [&] { set_wavenumber(c, k); });
 }
 
+hps_status hps_set_streams(hps_ctx* c, int streams) {
+  if (!c || (streams != 1 && streams != 2)) return HPS_EINVAL;
+  c->o.streams = streams;
+  return HPS_OK;
+}
+
 hps_status hps_set_wavenumbers(hps_ctx* c, const double* k) {
   if (!c || !k) return HPS_EINVAL;
   return guard(c, [&] { set_wavenumbers(c, k); });

@@ -286,3 +286,8 @@ def test_second_stream_gives_identical_results(case):
         out[ns] = (ff, s.total_field().cpu(), s.jvp(dq).cpu(), s.vjp(r).cpu())
     for a, b in zip(out[1], out[2]):
         assert torch.equal(a, b)
+    # the count can be changed between factorisations; others are refused
+    s.set_streams(1)
+    with pytest.raises(hps.HpsError) as e:
+        s.set_streams(3)
+    assert e.value.code == hps.HPS_EINVAL
