@@ -72,16 +72,18 @@ hps_status hps_zinv(void* stream, int n, int batch, double* A, double* inv);
 hps_status hps_zinv_noalloc(void* stream, int n, int batch, double* A, double* inv, int* status_dev);
 
 /* Column blocking of the inverses of order above 512, and of the
- * butterfly-transformed ones (pivot-free panels) from order 320 (hps_zinv and
- * the factorisation's W and Z inverses), process-wide; a performance choice, both
- * give the inverse to rounding (the merges and the top of the Section 2
- * direct solver only use the products with W^{-1} and Z^{-1}):
+ * butterfly-transformed ones (pivot-free panels, order >= 224) below it
+ * (hps_zinv and the factorisation's W and Z inverses), process-wide; a
+ * performance choice, both give the inverse to rounding (the merges and the
+ * top of the Section 2 direct solver only use the products with W^{-1} and
+ * Z^{-1}):
  *   mode 1: right-looking with one panel of look-ahead (the next panel's
  *           pivot search overlaps the update of the other columns on a
  *           second stream);
  *   mode 0: recursive column blocking (fewer, larger GEMM updates);
  *   mode -1 (default): mode 1 while the batch of matrices fits the 256 MB
- *           last-level cache (batch * n * n * 16 bytes), else mode 0.
+ *           last-level cache (batch * n * n * 16 bytes) and, below order
+ *           512, holds at most 32 matrices; else mode 0.
  * HPS_ZINV_LOOKAHEAD = 0 / 1 in the environment sets the initial mode.
  * HPS_EINVAL for other modes. */
 hps_status hps_zinv_blocking(int mode);

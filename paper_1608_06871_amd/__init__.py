@@ -431,9 +431,9 @@ def gemm_tuning(mode=1, force=-1):
 
 def zinv_blocking(mode=-1):
     """Column blocking of the inverses of order above 512 and of the
-    butterfly-transformed ones from order 320 (process-wide):
-    1 right-looking with look-ahead, 0 recursive, -1 by size (look-ahead while
-    the batch fits the last-level cache)."""
+    butterfly-transformed ones below it (process-wide): 1 right-looking with
+    look-ahead, 0 recursive, -1 by size (look-ahead while the batch fits the
+    last-level cache, and below order 512 for at most 32 matrices)."""
     rc = lib().hps_zinv_blocking(int(mode))
     if rc != HPS_OK:
         raise HpsError(rc, "hps_zinv_blocking")

@@ -52,8 +52,9 @@ void gemm_tuning_info(int* shapes, double* seconds);
 int gemm_variant_count();
 
 // Blocking of zinv for orders above 512 and butterfly-transformed orders
-// from 320 (process-wide): -1 by size (look-ahead while the batch fits the
-// last-level cache), 0 recursive, 1 look-ahead.
+// below (process-wide): -1 by size (look-ahead while the batch fits the
+// last-level cache, and below order 512 for at most 32 matrices), 0
+// recursive, 1 look-ahead.
 void zinv_set_blocking(int mode);
 
 // Pivoting of zinv (process-wide): -1 butterfly transform + pivot-free

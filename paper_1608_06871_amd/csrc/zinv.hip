@@ -1210,11 +1210,13 @@ hipError_t process_block(const Inv& v, int c0, int c1) {
   return block_update(v, m, c1, c0, m);
 }
 
-// Orders above the register-panel limit, and pivot-free (butterfly) ones from
-// order 320: right-looking with look-ahead, or the recursive column blocking.  The right-looking scheme reads and writes
-// every matrix of the batch once per 32-column panel, which pays while the
-// batch stays resident in the 256 MB last-level cache; larger batches take
-// the recursive blocking, whose fewer, larger products need less traffic.
+// Orders above the register-panel limit, and butterfly-transformed
+// (pivot-free) ones below it: right-looking with look-ahead, or the recursive
+// column blocking.  The right-looking scheme reads and writes every matrix of
+// the batch once per panel, which pays while the batch stays resident in the
+// 256 MB last-level cache (and, below the register-panel limit, for batches
+// of at most 32 matrices); larger batches take the recursive blocking, whose
+// fewer, larger products need less traffic.
 // g_blocking: -2 not read yet, -1 that rule, 0 / 1 recursive / look-ahead
 // (zinv_set_blocking, or HPS_ZINV_LOOKAHEAD = 0 / 1 in the environment).
 std::atomic<int> g_blocking{-2};
@@ -1228,6 +1230,11 @@ bool use_lookahead(int n, int batch) {
     m = g_blocking.load();
   }
   if (m >= 0) return m == 1;
+  // butterfly orders up to the register-panel limit: the look-ahead's one
+  // workgroup per matrix and panel pays for a few matrices only (order 224:
+  // 0.43 / 0.50 ms against 0.53 / 0.61 recursive for 8 / 32 matrices, 0.89
+  // against 0.72 for 64; order 448: 0.74 against 0.99 for 4, even at 64)
+  if (n <= NS_MAX_N && batch > 32) return false;
   return (double)batch * n * n * sizeof(double2) <= 256.0 * 1024 * 1024;
 }
 

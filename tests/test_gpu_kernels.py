@@ -156,10 +156,10 @@ def test_zinv_blockings_agree(n, batch, mode):
         assert err < 1e-11, (b, err)
 
 
-@pytest.mark.parametrize("n", [320, 448, 452])
+@pytest.mark.parametrize("n", [224, 320, 448, 452])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_zinv_butterfly_blockings_agree(n, mode):
-    """Butterfly-transformed orders from 320 up to the register-panel limit
+    """Butterfly-transformed orders from 224 up to the register-panel limit
     take the look-ahead with wide pivot-free panels under blocking 1 (and the
     default rule) and the recursive 32-column panels under 0: both give
     inv A = I to rounding with no fallback to the pivoted path; 452 ends with
