@@ -541,6 +541,8 @@ def main():
     ap.add_argument("--no-small-m", action="store_true", help="skip the 16-direction sweep timing")
     ap.add_argument("--no-rl", action="store_true", help="skip the recursive-linearization timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-problem batch")
+    ap.add_argument("--streams", type=int, choices=[1, 2], default=2,
+                    help="streams of the benchmark context (hps_opts.streams)")
     ap.add_argument("--batch-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--tune", choices=["auto", "on", "off"], default="auto",
                     help="GEMM tile autotuning (every distinct GEMM shape times its candidate tile shapes on its "
@@ -581,7 +583,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     log(f"config {args.config}: L={L} k={k} M={M} P={P}")
-    s = hps.Solver(nleaf=L, p=16, keep_derivs=True)
+    s = hps.Solver(nleaf=L, p=16, keep_derivs=True, streams=args.streams)
     xy = s.node_coords()
     q_np, dq_np, r_np = inputs(xy, cfg)
     q = torch.from_numpy(q_np).cuda()
@@ -663,7 +665,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter() - t1
         k1 = hps.profile_stop()[dom]
-        s.set_streams(2)
+        s.set_streams(args.streams)
         a1 = (k1["flops"] if roofline["bound"] == "mfma" else k1["bytes"]) / (k1["total_ms"] * 1e-3)
         a1 = a1 / 1e12 if roofline["bound"] == "mfma" else a1 / 1e9
         roofline["one_stream"] = {"achieved": a1, "frac": a1 / roofline["peak"], "launches": k1["launches"],
@@ -789,7 +791,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"HPS forward+jvp+vjp, k={k:g}, {L}x{L} leaves of 16x16, "
                                f"{M} directions, {P} angles, R={R:g}, FP64",
-                   "k": k, "nleaf": L, "p": 16, "ndir": M, "ntheta": P, "precision": "fp64"},
+                   "k": k, "nleaf": L, "p": 16, "ndir": M, "ntheta": P, "precision": "fp64",
+                   "streams": args.streams},
         "factor_ms": med["factor"],
         "solve_ms": med["solve"],
         "far_field_ms": med["far_field"],
