@@ -272,6 +272,9 @@ typedef struct hps_stats {
   int refine_iters;       /* HPS_MIXED: corrections made by the last solve */
   double refine_residual; /* HPS_MIXED: its final relative interface residual */
   int refine_fallback;    /* HPS_MIXED: 1 if the last solve redid its sweep in complex128 */
+  int cg_graph_iters;     /* last hps_gn_step: CG iterations replayed from a captured graph (the
+                             first runs directly; 0 when capture was not possible, e.g. with the
+                             launch profiler recording) */
 } hps_stats;
 
 /* Timings of the last calls (synchronises the stream) and memory use. */

@@ -44,7 +44,7 @@ class Stats(ctypes.Structure):
                 ("t_leaf_ms", ctypes.c_double), ("t_merge_ms", ctypes.c_double), ("t_top_ms", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("ndir", ctypes.c_int), ("singular", ctypes.c_int),
                 ("nonfinite", ctypes.c_int), ("refine_iters", ctypes.c_int), ("refine_residual", ctypes.c_double),
-                ("refine_fallback", ctypes.c_int)]
+                ("refine_fallback", ctypes.c_int), ("cg_graph_iters", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):

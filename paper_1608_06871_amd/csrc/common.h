@@ -163,6 +163,8 @@ enum KernelKind {
 // call that is issuing kernels).
 enum Phase { PH_OTHER = 0, PH_LEAF, PH_MERGE, PH_TOP, PH_SOLVE, PH_FAR, PH_JVP, PH_VJP, PHASE_COUNT };
 void profile_set_phase(int phase);
+// True while the launch profiler records (its events must not be captured).
+bool profile_active();
 
 // RAII: when profiling is on, records HIP events around the kernel launched
 // inside its scope, with that launch's algorithmic flops and bytes.

@@ -137,6 +137,7 @@ struct hps_ctx {
   int refine_iters = 0;
   double refine_res = 0.0;
   int refine_fallback = 0;  // last solve fell back to the complex128 sweep
+  int cg_graph_iters = 0;   // last GN step: CG iterations replayed from a graph
   DBuf dRleaf;                              // leaf ItI maps (complex128)
   std::vector<DBuf> dD32, dU32, dE32;       // complex64 sweep operators per level
   DBuf sE;                                  // h-to-f3 maps before conversion
@@ -193,6 +194,7 @@ struct hps_ctx {
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   hipEvent_t lev_ready = nullptr, lev_done[2] = {};  // merge levels: main -> second stream, and back
+  bool capturing = false;  // the stream is being captured into a graph: no stage timers
   double t_wave = 0.0;
   bool ev_used[8] = {};
 };
@@ -207,6 +209,7 @@ double elapsed_ms(hps_ctx* c, int a) {
 }
 
 void mark(hps_ctx* c, int a, int end) {
+  if (c->capturing) return;
   CK(hipEventRecord(c->ev[2 * a + end], c->st));
   if (end) c->ev_used[a] = true;
 }
@@ -1417,8 +1420,9 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
           "bad Gauss-Newton arguments");
   const ll npde = (ll)c->g.nleaf * c->g.mi, ns = (ll)S * S, nd = (ll)M * nt;
   hipStream_t st = c->st;
-  // work vectors: q | g | x r p Ap | partial(256) | scalars(4)
-  c->sGn.ensure(sizeof(double) * (2 * npde + 4 * ns + 256 + 4));
+  c->cg_graph_iters = 0;
+  // work vectors: q | g | x r p Ap | partial(256) | scalars(4) | CG scalars | CG flags
+  c->sGn.ensure(sizeof(double) * (2 * npde + 4 * ns + 256 + 4 + CG_NS) + sizeof(int) * CG_NF);
   c->sGnZ.ensure(zb(2 * nd));
   double* q = c->sGn.d();
   double* gv = q + npde;
@@ -1428,6 +1432,8 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
   double* Ap = pv + ns;
   double* partial = Ap + ns;
   double* sc = partial + 256;
+  double* cs = sc + 4;
+  int* cf = (int*)(cs + CG_NS);
   double2* res = c->sGnZ.z();
   double2* jv = res + nd;
   auto dotv = [&](const double* a, const double* b) {
@@ -1456,28 +1462,110 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
   CK(band_mask(st, r, S, band));  // unknowns: the modes in the band only
   CK(hipMemsetAsync(x, 0, sizeof(double) * ns, st));
   CK(hipMemcpyAsync(pv, r, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
-  double rr = dotv(r, r);
-  const double bnorm = std::sqrt(rr);
+  const double bnorm = std::sqrt(dotv(r, r));
   int it = 0;
   double rel = bnorm > 0.0 ? 1.0 : 0.0;
-  while (it < max_iter && rel > tol) {
-    // Ap = E^T Re(J^H J E p)
-    sine_eval(c, S, pv, q);
-    jvp(c, q, (double*)jv);
-    vjp(c, (const double*)jv, gv);
-    sine_adjoint(c, S, gv, Ap);
-    CK(band_mask(st, Ap, S, band));
-    const double pAp = dotv(pv, Ap);
-    if (!(pAp > 0.0)) break;
-    const double alpha = rr / pAp;
-    CK(axpby(st, alpha, pv, 1.0, x, ns));
-    CK(axpby(st, -alpha, Ap, 1.0, r, ns));
-    const double rr_new = dotv(r, r);
-    ++it;
-    rel = std::sqrt(rr_new) / bnorm;
-    if (rel <= tol) break;
-    CK(axpby(st, 1.0, r, rr_new / rr, pv, ns));
-    rr = rr_new;
+  if (it < max_iter && rel > tol) {
+    // CG with its scalars on the device: rr, then per iteration
+    // Ap = E^T Re(J^H J E p), alpha, x += alpha p, r -= alpha Ap, rr_new,
+    // beta, p = r + beta p (cg_alpha / cg_beta stop the updates once done).
+    // The iterations after the first replay one captured iteration.  The
+    // legacy default stream cannot be captured: the loop then runs on the
+    // context's second stream (forked here, joined when the block ends), with
+    // the library's calls issued on it meanwhile, from the first iteration on
+    // (which also sets up that stream's GEMM workspaces and tile choices).
+    struct StreamSwap {
+      hps_ctx* c;
+      hipStream_t saved;
+      ~StreamSwap() {
+        if (c->st != saved) {
+          (void)hipEventRecord(c->join, c->st);
+          c->st = saved;
+          (void)hipStreamWaitEvent(saved, c->join, 0);
+        }
+      }
+    } swap{c, st};
+    const bool try_graph = !profile_active();
+    if (try_graph && st == nullptr) {
+      ensure_side(c);
+      CK(hipEventRecord(c->fork, st));
+      CK(hipStreamWaitEvent(c->side, c->fork, 0));
+      c->st = c->side;
+    }
+    CK(dot(c->st, r, r, ns, partial, cs + CG_RR));
+    CK(cg_init(c->st, cs, cf));
+    auto iteration = [&]() {
+      sine_eval(c, S, pv, q);
+      jvp(c, q, (double*)jv);
+      vjp(c, (const double*)jv, gv);
+      sine_adjoint(c, S, gv, Ap);
+      hipStream_t s = c->st;  // the context's stream, or the second stream for replays
+      CK(band_mask(s, Ap, S, band));
+      CK(dot(s, pv, Ap, ns, partial, cs + CG_PAP));
+      CK(cg_alpha(s, cs, cf));
+      CK(axpby_dev(s, cs + CG_ALPHA, 1.0, pv, nullptr, x, ns));
+      CK(axpby_dev(s, cs + CG_ALPHA, -1.0, Ap, nullptr, r, ns));
+      CK(dot(s, r, r, ns, partial, cs + CG_RRNEW));
+      CK(cg_beta(s, cs, cf, bnorm, tol));
+      CK(axpby_dev(s, nullptr, 1.0, r, cs + CG_BETA, pv, ns));
+    };
+    int fl[CG_NF] = {0, 0, 0};
+    auto read_state = [&]() {
+      CK(hipMemcpyAsync(fl, cf, sizeof(fl), hipMemcpyDeviceToHost, c->st));
+      CK(hipMemcpyAsync(&rel, cs + CG_REL, sizeof(double), hipMemcpyDeviceToHost, c->st));
+      CK(hipStreamSynchronize(c->st));
+      it = fl[CG_ITERS];
+    };
+    // the first iteration runs directly; the state is read back every few
+    // replays (an iteration after the stop changes nothing)
+    iteration();
+    read_state();
+    hipGraphExec_t exec = nullptr;
+    const int it_direct = it;
+    if (!fl[CG_DONE] && it < max_iter && try_graph) {
+      hipGraph_t graph = nullptr;
+      c->capturing = true;
+      hipError_t e = hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          iteration();
+        } catch (...) {
+          e = hipErrorUnknown;
+        }
+        const hipError_t e2 = hipStreamEndCapture(c->st, &graph);
+        if (e == hipSuccess) e = e2;
+      }
+      c->capturing = false;
+      if (e == hipSuccess && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        // capture not possible: the remaining iterations run directly (the
+        // captured launches never executed); leave the stream out of capture
+        // mode and clear the error the attempt left behind
+        exec = nullptr;
+        hipStreamCaptureStatus cs_status = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(c->st, &cs_status) == hipSuccess && cs_status != hipStreamCaptureStatusNone) {
+          hipGraph_t g2 = nullptr;
+          (void)hipStreamEndCapture(c->st, &g2);
+          if (g2) (void)hipGraphDestroy(g2);
+        }
+        (void)hipGetLastError();
+      }
+    }
+    while (!fl[CG_DONE] && it < max_iter) {
+      const int chunk = std::min(4, max_iter - it);
+      for (int j = 0; j < chunk; ++j) {
+        if (exec)
+          CK(hipGraphLaunch(exec, c->st));
+        else
+          iteration();
+      }
+      read_state();
+    }
+    if (exec) {
+      (void)hipGraphExecDestroy(exec);
+      c->cg_graph_iters = it - it_direct;
+    }
   }
   CK(hipMemcpyAsync(coef_out, coef, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
   CK(axpby(st, 1.0, x, 1.0, coef_out, ns));
@@ -1756,6 +1844,7 @@ hps_status hps_get_stats(hps_ctx* c, hps_stats* out) {
     out->refine_iters = c->refine_iters;
     out->refine_residual = c->refine_res;
     out->refine_fallback = c->refine_fallback;
+    out->cg_graph_iters = c->cg_graph_iters;
   });
 }
 

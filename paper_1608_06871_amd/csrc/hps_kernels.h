@@ -118,6 +118,24 @@ hipError_t flag_nonfinite(hipStream_t st, const double* x, ll n, int bit, int* f
 hipError_t band_mask(hipStream_t st, double* x, int S, int band);
 // y = a x + b y
 hipError_t axpby(hipStream_t st, double a, const double* x, double b, double* y, ll n);
+
+// Conjugate-gradient scalars kept on the device (so that an iteration can be
+// captured in a graph and replayed without reading them back).  s holds
+// doubles [CG_RR, CG_PAP, CG_ALPHA, CG_RRNEW, CG_BETA, CG_REL], f the ints
+// [CG_DONE, CG_ACTIVE, CG_ITERS].
+enum { CG_RR = 0, CG_PAP, CG_ALPHA, CG_RRNEW, CG_BETA, CG_REL, CG_NS };
+enum { CG_DONE = 0, CG_ACTIVE, CG_ITERS, CG_NF };
+// rel = 1 and the flags cleared (rr is written by dot).
+hipError_t cg_init(hipStream_t st, double* s, int* f);
+// alpha = rr / pAp, or 0 with the iteration inactive once done or when
+// pAp <= 0 (which also sets done).
+hipError_t cg_alpha(hipStream_t st, double* s, int* f);
+// For an active iteration: iterations + 1, rel = sqrt(rr_new) / bnorm; done
+// when rel <= tol (beta 0), else beta = rr_new / rr and rr = rr_new.
+hipError_t cg_beta(hipStream_t st, double* s, int* f, double bnorm, double tol);
+// y = (sa * *a) x + (b ? *b : 1) y (a null: 1), the same arithmetic as axpby.
+hipError_t axpby_dev(hipStream_t st, const double* a, double sa, const double* x, const double* b, double* y,
+                     ll n);
 // z = x - y (complex)
 hipError_t zsub(hipStream_t st, const double2* x, const double2* y, double2* z, ll n);
 

@@ -397,6 +397,51 @@ __global__ void k_axpby(double a, const double* x, double b, double* y, ll n) {
   for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT) y[i] = a * x[i] + b * y[i];
 }
 
+__global__ void k_axpby_dev(const double* ap, double sa, const double* x, const double* bp, double* y, ll n) {
+  const double a = ap ? sa * *ap : sa, b = bp ? *bp : 1.0;
+  for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_cg_init(double* s, int* f) {
+  if (threadIdx.x != 0) return;
+  s[CG_REL] = 1.0;
+  f[CG_DONE] = 0;
+  f[CG_ACTIVE] = 0;
+  f[CG_ITERS] = 0;
+}
+
+__global__ void k_cg_alpha(double* s, int* f) {
+  if (threadIdx.x != 0) return;
+  const double pAp = s[CG_PAP];
+  if (f[CG_DONE] || !(pAp > 0.0)) {
+    f[CG_DONE] = 1;
+    f[CG_ACTIVE] = 0;
+    s[CG_ALPHA] = 0.0;
+    return;
+  }
+  f[CG_ACTIVE] = 1;
+  s[CG_ALPHA] = s[CG_RR] / pAp;
+}
+
+__global__ void k_cg_beta(double* s, int* f, double bnorm, double tol) {
+  if (threadIdx.x != 0) return;
+  if (!f[CG_ACTIVE]) {
+    s[CG_BETA] = 0.0;
+    return;
+  }
+  f[CG_ITERS] += 1;
+  const double rr_new = s[CG_RRNEW];
+  const double rel = sqrt(rr_new) / bnorm;
+  s[CG_REL] = rel;
+  if (rel <= tol) {
+    f[CG_DONE] = 1;
+    s[CG_BETA] = 0.0;
+    return;
+  }
+  s[CG_BETA] = rr_new / s[CG_RR];
+  s[CG_RR] = rr_new;
+}
+
 // z = x - y (complex)
 __global__ void k_zsub(const double2* x, const double2* y, double2* z, ll n) {
   for (ll i = blockIdx.x * (ll)NT + threadIdx.x; i < n; i += (ll)gridDim.x * NT)
@@ -453,6 +498,28 @@ hipError_t band_mask(hipStream_t st, double* x, int S, int band) {
 hipError_t axpby(hipStream_t st, double a, const double* x, double b, double* y, ll n) {
   KernelTimer kt(st, K_POINT, 3.0 * n, 24.0 * n);
   hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(NT), 0, st, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t axpby_dev(hipStream_t st, const double* a, double sa, const double* x, const double* b, double* y,
+                     ll n) {
+  KernelTimer kt(st, K_POINT, 3.0 * n, 24.0 * n);
+  hipLaunchKernelGGL(k_axpby_dev, dim3(blocks_for(n)), dim3(NT), 0, st, a, sa, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t cg_init(hipStream_t st, double* s, int* f) {
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64), 0, st, s, f);
+  return hipGetLastError();
+}
+
+hipError_t cg_alpha(hipStream_t st, double* s, int* f) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, st, s, f);
+  return hipGetLastError();
+}
+
+hipError_t cg_beta(hipStream_t st, double* s, int* f, double bnorm, double tol) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, st, s, f, bnorm, tol);
   return hipGetLastError();
 }
 

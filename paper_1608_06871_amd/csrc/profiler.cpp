@@ -62,6 +62,8 @@ KernelTimer::~KernelTimer() {
 
 void profile_set_phase(int phase) { g_phase.store(phase, std::memory_order_relaxed); }
 
+bool profile_active() { return g_on.load(); }
+
 }  // namespace hps
 
 extern "C" {

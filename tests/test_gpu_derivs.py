@@ -129,6 +129,41 @@ def test_gn_step_matches_oracle():
     assert abs(info["misfit"] - np.linalg.norm(r0)) < 1e-9 * np.linalg.norm(r0)
     got = out.cpu().numpy().reshape(S, S)
     assert np.max(np.abs(got - C1)) < 1e-9 * np.max(np.abs(C1 - C0))
+    # after the first, the CG iterations replay one captured graph
+    assert info["cg_iters"] > 1 and s.stats()["cg_graph_iters"] == info["cg_iters"] - 1
+
+
+def test_gn_step_graph_replay_equals_direct_launches():
+    """The captured CG iteration runs the same kernels on the same operands as
+    direct launches (forced by the launch profiler, which disables capture):
+    the coefficients, iteration count and residual agree bit for bit, also
+    when the step stops at max_iter."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    L, k, M, P, S = 4, 6.0, 8, 16, 5
+    s = hps.Solver(nleaf=L, p=16)
+    xy = s.node_coords()
+    q = torch.from_numpy(synth.gaussian_bumps(xy, 5, 3)).cuda()
+    th = synth.equispaced_angles(P)
+    s.factor(q, k)
+    s.solve(directions(M))
+    data = s.far_field(th, 2.0).clone()
+    C0 = torch.zeros(S * S, dtype=torch.float64, device="cuda")
+    for max_iter, tol in ((7, 1e-13), (60, 1e-10)):
+        a, ia = s.gn_step(k, directions(M), th, 2.0, C0, data, max_iter=max_iter, tol=tol)
+        a = a.clone()
+        ga = s.stats()["cg_graph_iters"]
+        hps.profile_start()
+        try:
+            b, ib = s.gn_step(k, directions(M), th, 2.0, C0, data, max_iter=max_iter, tol=tol)
+        finally:
+            hps.profile_stop()
+        print(f"max_iter {max_iter}: {ia['cg_iters']} iterations ({ga} replayed), rel {ia['cg_rel_res']:.2e}",
+              flush=True)
+        assert ga == ia["cg_iters"] - 1 and s.stats()["cg_graph_iters"] == 0
+        assert ia["cg_iters"] == ib["cg_iters"] and ia["cg_rel_res"] == ib["cg_rel_res"]
+        assert torch.equal(a, b)
+    assert ia["cg_iters"] < 60 and ia["cg_rel_res"] <= 1e-10  # the second call converged before max_iter
 
 
 def test_recursive_linearization_small_matches_oracle():
