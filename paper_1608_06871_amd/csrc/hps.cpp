@@ -559,12 +559,6 @@ void plan_factor_buffers(hps_ctx* c) {
   }
 }
 
-// The block moves of every merge level that depend only on the children's
-// maps (gathers of the child blocks, the identity of W, the -B32 part of Q,
-// the -A31 and zero parts of D's lower half, the parent map's diagonal and
-// zero blocks, and V's and Tm's fixed parts), as one list per level, uploaded
-// to the device.  The moves of a level write disjoint elements; they run at
-// the start of the level, before the products that read or complete them.
 // Scratch set of merge level l: with sweep operators, odd levels take the
 // second set, so that a level's V and U products (second stream) read their
 // blocks while the next level fills the other set.
@@ -585,6 +579,12 @@ void ensure_side(hps_ctx* c) {
     if (!*e) CK(hipEventCreateWithFlags(e, hipEventDisableTiming));
 }
 
+// The block moves of every merge level that depend only on the children's
+// maps (gathers of the child blocks, the identity of W, the -B32 part of Q,
+// the -A31 and zero parts of D's lower half, the parent map's diagonal and
+// zero blocks, and V's and Tm's fixed parts), as one list per level, uploaded
+// to the device.  The moves of a level write disjoint elements; they run at
+// the start of the level, before the products that read or complete them.
 void build_merge_moves(hps_ctx* c) {
   const Geometry& g = c->g;
   const int P = c->P;
@@ -746,12 +746,12 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
     double2* B23 = A33 + (ll)cnt * s * s;
     double2* B33 = B23 + (ll)cnt * m * s;
     const ll ms = (ll)m * s, ss = (ll)s * s;
-    // the child blocks, the identity of W, the -B32 and -A31 parts of Q and D,
-    // the parent map's diagonal blocks and zero blocks (and V's and Tm's fixed
-    // parts): one launch of independent moves
     // this level's scratch set was last read by level l - 2's products on
     // the second stream
     if (overlap && l >= 3) CK(hipStreamWaitEvent(st, c->lev_done[l & 1], 0));
+    // the child blocks, the identity of W, the -B32 and -A31 parts of Q and D,
+    // the parent map's diagonal blocks and zero blocks (and V's and Tm's fixed
+    // parts): one launch of independent moves
     {
       const int o0 = c->moveOff[l], o1 = c->moveOff[l + 1];
       ll mx = 0;
@@ -1520,7 +1520,12 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
     // replays (an iteration after the stop changes nothing)
     iteration();
     read_state();
-    hipGraphExec_t exec = nullptr;
+    struct Exec {
+      hipGraphExec_t e = nullptr;
+      ~Exec() {
+        if (e) (void)hipGraphExecDestroy(e);
+      }
+    } exec;
     const int it_direct = it;
     if (!fl[CG_DONE] && it < max_iter && try_graph) {
       hipGraph_t graph = nullptr;
@@ -1536,13 +1541,14 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
         if (e == hipSuccess) e = e2;
       }
       c->capturing = false;
-      if (e == hipSuccess && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e == hipSuccess && graph) e = hipGraphInstantiate(&exec.e, graph, nullptr, nullptr, 0);
       if (graph) (void)hipGraphDestroy(graph);
       if (e != hipSuccess) {
         // capture not possible: the remaining iterations run directly (the
         // captured launches never executed); leave the stream out of capture
         // mode and clear the error the attempt left behind
-        exec = nullptr;
+        if (exec.e) (void)hipGraphExecDestroy(exec.e);
+        exec.e = nullptr;
         hipStreamCaptureStatus cs_status = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(c->st, &cs_status) == hipSuccess && cs_status != hipStreamCaptureStatusNone) {
           hipGraph_t g2 = nullptr;
@@ -1555,17 +1561,14 @@ GnResult gn_step(hps_ctx* c, double k, int M, const double* ang, int nt, const d
     while (!fl[CG_DONE] && it < max_iter) {
       const int chunk = std::min(4, max_iter - it);
       for (int j = 0; j < chunk; ++j) {
-        if (exec)
-          CK(hipGraphLaunch(exec, c->st));
+        if (exec.e)
+          CK(hipGraphLaunch(exec.e, c->st));
         else
           iteration();
       }
       read_state();
     }
-    if (exec) {
-      (void)hipGraphExecDestroy(exec);
-      c->cg_graph_iters = it - it_direct;
-    }
+    if (exec.e) c->cg_graph_iters = it - it_direct;
   }
   CK(hipMemcpyAsync(coef_out, coef, sizeof(double) * ns, hipMemcpyDeviceToDevice, st));
   CK(axpby(st, 1.0, x, 1.0, coef_out, ns));
