@@ -904,8 +904,9 @@ void down_level(hps_ctx* c, int l, int op, const double2* Op, const double2* Fp,
   else
     CK(zgemm_rowmap(st, OP_C, OP_N, 2 * s, M, np, ONE, Op, np, 4LL * m * s, Fp, np, sp, ZERO, Fch, nc, sc,
                     c->dMap3[l].i(), s, (ll)nc * M, cnt));
-  CK(scatter_rows(st, m, M, Fp, np, sp, c->didx[4 * l].i(), Fch, nc, sc, cnt));
-  CK(scatter_rows(st, m, M, Fp + m, np, sp, c->didx[4 * l + 2].i(), Fch + (ll)nc * M, nc, sc, cnt));
+  const RowMove mv[2] = {{Fp, np, sp, c->didx[4 * l].i(), Fch, nc, sc, m, 1},
+                         {Fp + m, np, sp, c->didx[4 * l + 2].i(), Fch + (ll)nc * M, nc, sc, m, 1}};
+  CK(row_moves(st, mv, 2, M, cnt));
 }
 
 // ---- mixed precision: complex64 sweeps refined on the skeleton system ----
@@ -1263,10 +1264,13 @@ void jvp(hps_ctx* c, const double* dq, double* out) {
     const double2* Ha = Hc;
     const double2* Hb = Hc + (ll)nc * M;
     double2* H3 = c->dF3.z();
-    CK(gather2d(st, m, M, Ha, nc, sc, c->didx[4 * l].i(), nullptr, Ho, np, sp, 1.0, cnt));
-    CK(gather2d(st, m, M, Hb, nc, sc, c->didx[4 * l + 2].i(), nullptr, Ho + m, np, sp, 1.0, cnt));
-    CK(gather2d(st, s, M, Ha, nc, sc, c->didx[4 * l + 1].i(), nullptr, H3, 2 * s, s3, 1.0, cnt));
-    CK(gather2d(st, s, M, Hb, nc, sc, c->didx[4 * l + 3].i(), nullptr, H3 + s, 2 * s, s3, 1.0, cnt));
+    // the children's exterior data to the parent ordering, their shared-edge
+    // data to H3: one launch
+    const RowMove mv[4] = {{Ha, nc, sc, c->didx[4 * l].i(), Ho, np, sp, m, 0},
+                           {Hb, nc, sc, c->didx[4 * l + 2].i(), Ho + m, np, sp, m, 0},
+                           {Ha, nc, sc, c->didx[4 * l + 1].i(), H3, 2 * s, s3, s, 0},
+                           {Hb, nc, sc, c->didx[4 * l + 3].i(), H3 + s, 2 * s, s3, s, 0}};
+    CK(row_moves(st, mv, 4, M, cnt));
     CK(zgemm(st, OP_N, OP_N, np, M, 2 * s, ONE, c->dU[l].z(), np, 4LL * m * s, H3, 2 * s, s3, ONE,
              Ho, np, sp, cnt));
     std::swap(Hc, Ho);

@@ -77,6 +77,22 @@ struct MoveDesc {
 // Fills the division parameters of host-side descriptors before their copy
 // to the device.
 void multi_move_prepare(MoveDesc* desc, int ndesc);
+
+// A row move of M rows by N columns over a batch: gather (out row i = in row
+// ridx[i]) or scatter (out row ridx[i] = in row i).
+struct RowMove {
+  const double2* in;
+  ll ldi, si;
+  const int* ridx;
+  double2* out;
+  ll ldo, so;
+  int M;
+  int scatter;
+};
+// Up to four independent row moves with the same N and batch in one launch
+// (passed by value: no device copy of the list, so the launch can be
+// captured); the moves must write disjoint elements.
+hipError_t row_moves(hipStream_t st, const RowMove* moves, int nmoves, int N, int batch);
 // Applies ndesc independent moves (device array `desc`, over `batch` matrices
 // each) in one launch; the moves must write disjoint elements.  max_elems:
 // the largest M * N * batch among them.

@@ -118,6 +118,36 @@ __global__ void k_set2d(int M, int N, unsigned fdm, int fds, double2* out, ll ld
   }
 }
 
+struct RowMoves4 {
+  RowMove m[4];
+  unsigned fdm[4];
+  int fds[4];
+};
+
+// Move blockIdx.y of the list (selected by uniform branches, so the list stays
+// in the kernel arguments): z (stride gridDim.z) runs over the batch, x over
+// the elements of one matrix.
+__global__ void k_row_moves(RowMoves4 d, int N, int batch) {
+  const int y = blockIdx.y;
+  const RowMove mv = y == 0 ? d.m[0] : y == 1 ? d.m[1] : y == 2 ? d.m[2] : d.m[3];
+  const unsigned fdm = y == 0 ? d.fdm[0] : y == 1 ? d.fdm[1] : y == 2 ? d.fdm[2] : d.fdm[3];
+  const int fds = y == 0 ? d.fds[0] : y == 1 ? d.fds[1] : y == 2 ? d.fds[2] : d.fds[3];
+  const unsigned per = (unsigned)mv.M * (unsigned)N;
+  if (blockIdx.x * NT >= per) return;
+  for (int b = blockIdx.z; b < batch; b += gridDim.z) {
+    const double2* ib = mv.in + (ll)b * mv.si;
+    double2* ob = mv.out + (ll)b * mv.so;
+    for (unsigned e = blockIdx.x * NT + threadIdx.x; e < per; e += gridDim.x * NT) {
+      const unsigned j = fdiv(e, fdm, fds), i = e - j * (unsigned)mv.M;
+      const int r = mv.ridx[i];
+      if (mv.scatter)
+        ob[(ll)r + (ll)j * mv.ldo] = ib[(ll)i + (ll)j * mv.ldi];
+      else
+        ob[(ll)i + (ll)j * mv.ldo] = ib[(ll)r + (ll)j * mv.ldi];
+    }
+  }
+}
+
 // Move desc[blockIdx.y]: z (stride gridDim.z) runs over the batch, x over the
 // elements of one matrix.
 __global__ void k_multi_move(const MoveDesc* desc, int batch) {
@@ -545,6 +575,29 @@ FastDiv make_fastdiv(int d) {
   const int l = 32 - __builtin_clz((unsigned)(d - 1));  // ceil(log2 d), d >= 2
   const unsigned long long p = 1ULL << (31 + l);
   return FastDiv{(unsigned)((p + (unsigned long long)d - 1) / (unsigned long long)d), l - 1};
+}
+
+hipError_t row_moves(hipStream_t st, const RowMove* moves, int nmoves, int N, int batch) {
+  if (nmoves < 1 || nmoves > 4 || N <= 0 || batch <= 0) return nmoves == 0 ? hipSuccess : hipErrorInvalidValue;
+  RowMoves4 d{};
+  ll maxper = 0;
+  double bytes = 0.0;
+  for (int i = 0; i < nmoves; ++i) {
+    const ll per = (ll)moves[i].M * N;
+    if (moves[i].M <= 0 || per > 0x7fffffffLL) return hipErrorInvalidValue;
+    d.m[i] = moves[i];
+    const FastDiv f = make_fastdiv(moves[i].M);
+    d.fdm[i] = f.mul;
+    d.fds[i] = f.shift;
+    maxper = per > maxper ? per : maxper;
+    bytes += 32.0 * (double)per * batch;
+  }
+  KernelTimer kt(st, K_MOVE, 0.0, bytes);
+  ll gx = (maxper + NT - 1) / NT, gz = batch;
+  while (gx * nmoves * gz > 1048576 && gz > 1) gz = (gz + 1) / 2;
+  if (gz > 65535) gz = 65535;
+  hipLaunchKernelGGL(k_row_moves, dim3((unsigned)gx, nmoves, (unsigned)gz), dim3(NT), 0, st, d, N, batch);
+  return hipGetLastError();
 }
 
 void multi_move_prepare(MoveDesc* desc, int ndesc) {
