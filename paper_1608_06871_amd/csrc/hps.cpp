@@ -194,6 +194,7 @@ struct hps_ctx {
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   hipEvent_t lev_ready = nullptr, lev_done[2] = {};  // merge levels: main -> second stream, and back
+  hipEvent_t q_ready = nullptr, q_done = nullptr;     // a level's Q product on the second stream
   bool capturing = false;  // the stream is being captured into a graph: no stage timers
   double t_wave = 0.0;
   bool ev_used[8] = {};
@@ -575,7 +576,8 @@ MergeScratch merge_scratch(hps_ctx* c, int l) {
 // first use).
 void ensure_side(hps_ctx* c) {
   if (!c->side) CK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&c->fork, &c->join, &c->lev_ready, &c->lev_done[0], &c->lev_done[1]})
+  for (hipEvent_t* e : {&c->fork, &c->join, &c->lev_ready, &c->lev_done[0], &c->lev_done[1], &c->q_ready,
+                        &c->q_done})
     if (!*e) CK(hipEventCreateWithFlags(e, hipEventDisableTiming));
 }
 
@@ -759,15 +761,27 @@ bool factor_pass(hps_ctx* c, const double* q, bool defer) {
         mx = std::max(mx, (ll)c->hMoves[t].M * c->hMoves[t].N * cnt);
       CK(multi_move(st, (const MoveDesc*)c->dMoves.p + o0, o1 - o0, mx, cnt));
     }
+    // Q = [B33 A31, -B32] needs no W: where W's inverse is a latency-bound
+    // look-ahead chain (butterfly orders), Q runs beside it on the second
+    // stream
+    double2* Q = c->sQ.z();
+    const ll sq = 2 * ms;
+    const bool q_side = overlap && s >= 224;
+    if (q_side) {
+      CK(hipEventRecord(c->q_ready, st));
+      CK(hipStreamWaitEvent(c->side, c->q_ready, 0));
+      CK(zgemm(c->side, OP_N, OP_N, s, m, s, ONE, B33, s, ss, A31, s, ms, ZERO, Q, s, sq, cnt));
+      CK(hipEventRecord(c->q_done, c->side));
+    }
     // W = I - B33 A33, inverted
     double2* W = c->sW.z();
     double2* Wi = scr.winv;
     CK(zgemm(st, OP_N, OP_N, s, s, s, MONE, B33, s, ss, A33, s, ss, ONE, W, s, ss, cnt));
     CK(zinv(st, s, W, s, ss, Wi, s, ss, cnt, c->sZws.p, c->sInfo.i()));
-    // Q = [B33 A31, -B32]
-    double2* Q = c->sQ.z();
-    const ll sq = 2 * ms;
-    CK(zgemm(st, OP_N, OP_N, s, m, s, ONE, B33, s, ss, A31, s, ms, ZERO, Q, s, sq, cnt));
+    if (q_side)
+      CK(hipStreamWaitEvent(st, c->q_done, 0));
+    else
+      CK(zgemm(st, OP_N, OP_N, s, m, s, ONE, B33, s, ss, A31, s, ms, ZERO, Q, s, sq, cnt));
     // D = [X; Yb]
     double2* D = c->dD[l].z();
     const ll sd = 4 * ms;
@@ -1717,6 +1731,8 @@ void hps_destroy(hps_ctx* c) {
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->join) (void)hipEventDestroy(c->join);
   if (c->lev_ready) (void)hipEventDestroy(c->lev_ready);
+  if (c->q_ready) (void)hipEventDestroy(c->q_ready);
+  if (c->q_done) (void)hipEventDestroy(c->q_done);
   for (auto& e : c->lev_done)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->ev)
