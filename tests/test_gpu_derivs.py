@@ -196,3 +196,27 @@ def test_recursive_linearization_small_matches_oracle():
     got = coef.cpu().numpy().reshape(bands[-1], bands[-1])
     print("misfits per k:", [f"{e['misfit']:.3e}" for e in log], flush=True)
     assert np.max(np.abs(got - ref[-1])) < 1e-8 * np.max(np.abs(ref[-1]))
+
+
+def test_gn_step_graph_on_a_caller_stream():
+    """On a caller's (non-default) stream the CG iterations are captured on
+    that stream itself: same step, bit for bit, as on the default stream."""
+    torch = _torch()
+    import paper_1608_06871_amd as hps
+    L, k, M, P, S = 4, 5.0, 8, 16, 4
+    th = synth.equispaced_angles(P)
+    out = []
+    for stream in (None, torch.cuda.Stream()):
+        s = hps.Solver(nleaf=L, p=16, stream=stream)
+        q = torch.from_numpy(synth.gaussian_bumps(s.node_coords(), 4, 8)).cuda()
+        torch.cuda.synchronize()
+        s.factor(q, k)
+        s.solve(directions(M))
+        data = s.far_field(th, 2.0).clone()
+        C0 = torch.zeros(S * S, dtype=torch.float64, device="cuda")
+        c, info = s.gn_step(k, directions(M), th, 2.0, C0, data, max_iter=30, tol=1e-12)
+        torch.cuda.synchronize()
+        out.append((c.clone(), info, s.stats()["cg_graph_iters"]))
+    (a, ia, ga), (b, ib, gb) = out
+    assert ga == ia["cg_iters"] - 1 and gb == ib["cg_iters"] - 1 and gb > 0
+    assert ia["cg_iters"] == ib["cg_iters"] and torch.equal(a, b)
