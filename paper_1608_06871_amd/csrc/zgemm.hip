@@ -258,6 +258,7 @@ __global__ __launch_bounds__(NT, WAVES) void gemm_kernel(ArgsT<T> a) {
 // tiles of one small matrix, or neighbouring tiles of a large one, then share
 // their operand panels in one L2 instead of fetching them on several XCDs.
 constexpr unsigned NXCD = 8;
+constexpr int GROUP_M = 8;  // row tiles per group in the single-matrix tile order
 __device__ inline unsigned xcd_order(unsigned i, unsigned n) {
   const unsigned x = i % NXCD, k = i / NXCD, q = n / NXCD, r = n % NXCD;
   return x * q + (x < r ? x : r) + k;
@@ -321,8 +322,21 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   const int tilesM = (a.M + TM - 1) / TM;
   const unsigned wg = xcd_order(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
   const unsigned tile = wg % gridDim.x;
-  const int m0 = (tile % tilesM) * TM;
-  const int n0 = (tile / tilesM) * TN;
+  int m0, n0;
+  const int tilesN = (int)gridDim.x / tilesM;
+  if (gridDim.y == 1 && tilesM > GROUP_M && tilesN >= 2 * GROUP_M) {
+    // one large matrix with many column tiles (the rank-W updates of the
+    // large inverses): groups of GROUP_M row tiles, columns within a group,
+    // so that an XCD's contiguous range of tiles is a band of rows (its A
+    // rows read once) and the tiles running together share A and B panels
+    const int per_group = GROUP_M * tilesN, g = (int)tile / per_group;
+    const int first = g * GROUP_M, gsize = min(tilesM - first, GROUP_M), r = (int)tile % per_group;
+    m0 = (first + r % gsize) * TM;
+    n0 = (r / gsize) * TN;
+  } else {
+    m0 = (tile % tilesM) * TM;
+    n0 = (tile / tilesM) * TN;
+  }
   const ll b = wg / gridDim.x;
   const double2* A = a.A + b * a.sA;
   const double2* B = a.B + b * a.sB;
