@@ -324,11 +324,12 @@ __global__ __launch_bounds__(NT, WAVES) void zgemm_kernel(Args a) {
   const unsigned tile = wg % gridDim.x;
   int m0, n0;
   const int tilesN = (int)gridDim.x / tilesM;
-  if (gridDim.y == 1 && tilesM > GROUP_M && tilesN >= 2 * GROUP_M) {
-    // one large matrix with many column tiles (the rank-W updates of the
-    // large inverses): groups of GROUP_M row tiles, columns within a group,
-    // so that an XCD's contiguous range of tiles is a band of rows (its A
-    // rows read once) and the tiles running together share A and B panels
+  if (tilesM > GROUP_M && tilesN >= 2 * GROUP_M) {
+    // large matrices with many column tiles (the rank-W updates of the
+    // large inverses, the coarse merge levels): groups of GROUP_M row tiles,
+    // columns within a group, so that an XCD's contiguous range of tiles is a
+    // band of rows (its A rows read once) and the tiles running together
+    // share A and B panels
     const int per_group = GROUP_M * tilesN, g = (int)tile / per_group;
     const int first = g * GROUP_M, gsize = min(tilesM - first, GROUP_M), r = (int)tile % per_group;
     m0 = (first + r % gsize) * TM;
