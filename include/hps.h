@@ -119,20 +119,25 @@ typedef struct hps_opts {
                             redoes its sweep in complex128 (exact FP64 result, refine_fallback = 1
                             in hps_stats) instead of returning HPS_ENOCONV */
   int exterior;          /* hps_exterior */
-  int streams;           /* streams of hps_factor: 2 (default) runs half the leaf stage, and each
-                            merge level's operators for the sweeps (V, U) while the next level
-                            proceeds, on a second stream the context owns (forked from and joined
+  int streams;           /* streams of hps_factor: 2 (default) runs half the leaf stage, each merge
+                            level's operators for the sweeps (V, U) while the next level proceeds,
+                            and on the levels whose W inverse has order >= 224 the level's Q
+                            product, on a second stream the context owns (forked from and joined
                             to `stream` with events inside the call); 1 keeps all work on `stream`
-                            (for callers that already run several contexts concurrently) */
+                            (for callers that already run several contexts concurrently).  The
+                            results are the same bit for bit.  (hps_gn_step captures its CG
+                            iterations in a graph on `stream`, or on the second stream when
+                            `stream` is the legacy default stream, which cannot be captured.) */
 } hps_opts;
 
 typedef struct hps_ctx hps_ctx;
 
 /* Fills *o with the defaults: Omega = [-1, 1]^2, nleaf = 4, p = 16,
  * eta_scale = 1, keep_derivs = 1, HPS_FP64, default stream, nprob = 1,
- * max_refine = 8, fallback_fp64 = 1, refine_tol = 1e-10, HPS_EXT_GREEN, streams = 2 (the far-field error follows the interface
- * residual closely, so 1e-10 leaves two orders of margin under a 1e-8 far-field
- * target; one correction reaches it at k = 80). */
+ * max_refine = 8, fallback_fp64 = 1, refine_tol = 1e-10, HPS_EXT_GREEN,
+ * streams = 2 (the far-field error follows the interface residual closely, so
+ * 1e-10 leaves two orders of margin under a 1e-8 far-field target; one
+ * correction reaches it at k = 80). */
 void hps_default_opts(hps_opts* o);
 
 /* Creates a context for the geometry in *opts (host-side set-up only; device
@@ -249,7 +254,9 @@ hps_status hps_sine_adjoint(hps_ctx* ctx, int S, const double* g, double* coef);
  * coef, coef_out: device, S*S doubles (layout of hps_sine_eval).  Host
  * outputs (may be NULL): CG iterations, final relative CG residual, and the
  * data misfit ||r|| before the step.  Leaves the context factored and solved
- * at q = E coef.  Synchronous.  Requires keep_derivs. */
+ * at q = E coef.  Synchronous.  Requires keep_derivs.  The CG scalars stay on
+ * the device; after the first iteration the others replay one captured graph
+ * (bit-identical to direct launches; hps_stats.cg_graph_iters). */
 hps_status hps_gn_step(hps_ctx* ctx, double k, int ndir, const double* dir_angle_host, int ntheta,
                        const double* theta_host, double R, int S, int band, const double* coef,
                        const double* data, int max_iter, double tol, double* coef_out,
